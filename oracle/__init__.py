@@ -1,0 +1,42 @@
+"""CPU oracle for the reduced scattering system (RED / ORI).
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously correct
+reference written from the paper (Ramm & Tran, "A Fast Algorithm for Solving
+Scalar Wave Scattering Problem by Billions of Particles", arXiv:1602.04691).
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import it.  The GPU library never imports, links or calls
+anything here, and nothing here imports the GPU library: the two share no code.
+
+Everything is complex128 / float64 NumPy, with LAPACK (``numpy.linalg.solve``)
+as the only library primitive beyond ``numpy.fft`` in the Section 3 route.
+
+Parity pins: every function is pinned by a CPU test in
+``tests/test_oracle_pins.py`` (no function is "parity unpinned").
+"""
+
+from .ori_oracle import (  # noqa: F401
+    C_S,
+    cell_points,
+    cell_volume,
+    green,
+    coupling,
+    symmetric_scale,
+    green_matrix,
+    system_matrix,
+    symmetric_system_matrix,
+    solve_direct,
+    scatter_dense,
+    sample_scatter_rows,
+    sample_residual_rows,
+    brute_force_system,
+    gauss_solve,
+    cocg,
+    solve_symmetrized_cocg,
+)
+from .section3 import (  # noqa: F401
+    mirror_pad_axis,
+    zero_pad_axis,
+    green_table,
+    convolve_section3,
+    scatter_section3,
+)

@@ -1,0 +1,284 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test is chosen so that a plausible mistake in the oracle (a dropped
+factor, a wrong sign, the diagonal factor on the wrong side, a transposed
+axis, a wrong padding) fails at least one of them.  CPU only.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+def _varied_case(n, k, seed, side=1.0, origin=(0.0, 0.0, 0.0), offset=0.5):
+    rng = np.random.default_rng(seed)
+    P = n ** 3
+    h = (-1.0 + 0.5j) * (1.0 + 0.3 * rng.uniform(-1, 1, P)) + 0.2j * rng.uniform(-1, 1, P)
+    N = 0.5 + rng.uniform(0, 1, P)
+    u0 = rng.standard_normal(P) + 1j * rng.standard_normal(P)
+    pts = O.cell_points(n, side, origin, offset)
+    return pts, h, N, u0
+
+
+# --- exact special cases -----------------------------------------------------
+def test_single_cube_is_incident_field():
+    # n = 1: P = 1, the sum of eq. 2.19 is empty, so u = u0 exactly.
+    pts = O.cell_points(1)
+    D = O.coupling(np.array([-1 + 0.5j]), None, 1)
+    A = O.system_matrix(pts, 3.0, D)
+    u = O.solve_direct(A, np.array([0.3 - 0.7j]))
+    assert u[0] == 0.3 - 0.7j
+
+
+@pytest.mark.parametrize("side,k,h,N", [(1.0, 1.0, -1 + 0.5j, 1.0),
+                                        (1.3, 4.0, 0.7 - 2.0j, 2.5),
+                                        (0.2, 11.0, -30 + 1j, 0.25)])
+def test_two_per_side_closed_form(side, k, h, N):
+    # n = 2, constant h, N and u0 = 1: by the cube's symmetry all 8 unknowns are
+    # equal, each cube sees 3 neighbours at distance a = side/2, 3 at a*sqrt(2)
+    # and 1 at a*sqrt(3):  u (1 + c_S h N (side/2)^3 * sum G) = 1.
+    a = side / 2.0
+
+    def G(r):
+        return complex(math.cos(k * r), math.sin(k * r)) / (4 * math.pi * r)
+
+    Dc = 4 * math.pi * h * N * a ** 3
+    u_exact = 1.0 / (1.0 + Dc * (3 * G(a) + 3 * G(a * math.sqrt(2)) + G(a * math.sqrt(3))))
+    pts = O.cell_points(2, side=side, origin=(0.4, -1.0, 2.0))
+    D = O.coupling(np.full(8, h), np.full(8, N), 2, side)
+    u = O.solve_direct(O.system_matrix(pts, k, D), np.ones(8, complex))
+    assert np.max(np.abs(u - u_exact)) <= 1e-15 * 4
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_brute_force_matches_vectorised_lapack(n):
+    # Pure-Python assembly (term by term from eq. 2.19) + own Gaussian
+    # elimination against the NumPy assembly + LAPACK zgesv.
+    k = 2.7
+    pts, h, N, u0 = _varied_case(n, k, seed=10 + n, side=1.7, origin=(0.1, 0.2, -0.3))
+    A_bf = O.brute_force_system(n, k, h, N, side=1.7, origin=(0.1, 0.2, -0.3))
+    u_bf = np.array(O.gauss_solve(A_bf, u0))
+    D = O.coupling(h, N, n, 1.7)
+    A = O.system_matrix(pts, k, D)
+    assert np.max(np.abs(A - np.array(A_bf))) <= 1e-15
+    assert _rel(O.solve_direct(A, u0), u_bf) <= 1e-13
+
+
+def test_green_matrix_symmetric_and_zero_diagonal():
+    pts = O.cell_points(4, side=1.1, origin=(0.3, 0.0, 0.0))
+    G0 = O.green_matrix(pts, 5.0)
+    assert np.all(np.diag(G0) == 0)
+    assert np.max(np.abs(G0 - G0.T)) == 0.0
+
+
+def test_born_limit_sign_and_scale():
+    # h = eps*h1: u = u0 - G0 D u0 + O(eps^2).  The first-order field is written
+    # out here as the explicit sum of eq. 2.19 over p != q (Python loops).
+    n, k = 3, 4.0
+    pts, h1, N, u0 = _varied_case(n, k, seed=3)
+    P = n ** 3
+    vol = 1.0 / P
+    born1 = np.zeros(P, complex)
+    for q in range(P):
+        s = 0j
+        for p in range(P):
+            if p != q:
+                r = math.dist(pts[q], pts[p])
+                s += (complex(math.cos(k * r), math.sin(k * r)) / (4 * math.pi * r)) * h1[p] * N[p] * u0[p] * vol
+        born1[q] = -4 * math.pi * s
+    errs = []
+    for eps in (1e-2, 5e-3, 2.5e-3):
+        D = O.coupling(eps * h1, N, n)
+        u = O.solve_direct(O.system_matrix(pts, k, D), u0)
+        errs.append(np.linalg.norm(u - (u0 + eps * born1)))
+    assert abs(errs[0] / errs[1] - 4.0) < 0.05 and abs(errs[1] / errs[2] - 4.0) < 0.03
+
+
+def test_reciprocity_fixes_diagonal_side():
+    # D (I + G0 D)^{-1} = (D^{-1} + G0)^{-1} is symmetric, so
+    # F_ij = u0_j^T D u_i is symmetric in (i, j) for varying h and N.
+    n, k = 3, 3.0
+    pts, h, N, _ = _varied_case(n, k, seed=5)
+    D = O.coupling(h, N, n)
+    A = O.system_matrix(pts, k, D)
+    rng = np.random.default_rng(0)
+    U0 = rng.standard_normal((O.cell_points(n).shape[0], 4)) + 1j * rng.standard_normal((n ** 3, 4))
+    U = O.solve_direct(A, U0)
+    F = U0.T @ (D[:, None] * U)
+    assert np.max(np.abs(F - F.T)) <= 1e-13 * np.max(np.abs(F))
+    # the wrong placement (I + D G0) breaks it
+    Aw = O.green_matrix(pts, k) * D[:, None]
+    Aw[np.diag_indices_from(Aw)] += 1
+    Uw = O.solve_direct(Aw, U0)
+    Fw = U0.T @ (D[:, None] * Uw)
+    assert np.max(np.abs(Fw - Fw.T)) > 1e-6 * np.max(np.abs(Fw))
+
+
+def test_mirror_symmetry_per_axis():
+    # Data symmetric under i_a -> n-1-i_a gives a symmetric solution; checked
+    # for each axis separately (an axis mix-up breaks one of them).
+    n, k = 4, 6.0
+    rng = np.random.default_rng(7)
+    for axis in range(3):
+        base_h = (-1 + 0.5j) * (1 + 0.2 * rng.uniform(-1, 1, (n, n, n)))
+        base_u = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+        h = base_h + np.flip(base_h, axis)
+        u0 = base_u + np.flip(base_u, axis)
+        pts = O.cell_points(n)
+        D = O.coupling(h.reshape(-1), None, n)
+        u = O.solve_direct(O.system_matrix(pts, k, D), u0.reshape(-1)).reshape(n, n, n)
+        assert np.max(np.abs(u - np.flip(u, axis))) <= 1e-13
+        # a field symmetric on another axis only does not give this symmetry
+        u_other = O.solve_direct(O.system_matrix(pts, k, D), base_u.reshape(-1)).reshape(n, n, n)
+        assert np.max(np.abs(u_other - np.flip(u_other, axis))) > 1e-3
+
+
+def test_origin_shift_is_a_phase():
+    # G depends on x_q - x_p only: moving the cube by t multiplies the
+    # plane-wave solution by exp(i k alpha . t).
+    n, k = 3, 2.0
+    alpha = np.array([0.6, 0.0, 0.8])
+    h = np.full(n ** 3, -1 + 0.5j) * (1 + 0.1 * np.linspace(-1, 1, n ** 3))
+    t = np.array([0.3, -1.1, 0.7])
+    sol = []
+    for org in ((0.0, 0.0, 0.0), tuple(t)):
+        pts = O.cell_points(n, origin=org)
+        u0 = workloads.plane_wave(n, k, alpha, origin=org)
+        D = O.coupling(h, None, n)
+        sol.append(O.solve_direct(O.system_matrix(pts, k, D), u0))
+    assert _rel(sol[1], np.exp(1j * k * alpha @ t) * sol[0]) <= 1e-13
+
+
+# --- symmetrisation, COCG ------------------------------------------------------
+def test_symmetrised_system_gives_the_same_solution():
+    n, k = 4, 5.0
+    pts, h, N, u0 = _varied_case(n, k, seed=8)
+    D = O.coupling(h, N, n)
+    u_ref = O.solve_direct(O.system_matrix(pts, k, D), u0)
+    S = O.symmetric_scale(D)
+    As = O.symmetric_system_matrix(pts, k, S)
+    assert np.max(np.abs(As - As.T)) <= 1e-15 * np.max(np.abs(As))
+    w = O.solve_direct(As, S * u0)
+    assert _rel(w / S, u_ref) <= 1e-13
+    u_rec = u0 - O.green_matrix(pts, k) @ (S * w)
+    assert _rel(u_rec, u_ref) <= 1e-13
+    # the other branch of the square root gives the same u
+    w2 = O.solve_direct(O.symmetric_system_matrix(pts, k, -S), -S * u0)
+    assert _rel(u0 - O.green_matrix(pts, k) @ (-S * w2), u_ref) <= 1e-13
+
+
+def test_cocg_real_spd_is_cg_and_terminates():
+    # On a real SPD matrix the bilinear form is the Euclidean one, so COCG is
+    # textbook CG: exact in at most P steps (here P = 12, well conditioned).
+    rng = np.random.default_rng(1)
+    M = rng.standard_normal((12, 12))
+    A = M @ M.T + 12 * np.eye(12)
+    b = rng.standard_normal(12)
+    x, hist = O.cocg(lambda v: A @ v, b, tol=1e-14, maxiter=12)
+    assert _rel(x, np.linalg.solve(A, b)) <= 1e-12
+    # the first step is the steepest-descent step x1 = (b^T b / b^T A b) b
+    x1, _ = O.cocg(lambda v: A @ v, b, tol=0, maxiter=1)
+    alpha = (b @ b) / (b @ A @ b)
+    assert _rel(x1, alpha * b) <= 1e-15
+
+
+def test_cocg_complex_symmetric_matches_lu():
+    n, k = 4, 5.0
+    pts, h, N, u0 = _varied_case(n, k, seed=9)
+    D = O.coupling(h, N, n)
+    u_ref = O.solve_direct(O.system_matrix(pts, k, D), u0)
+    u, hist = O.solve_symmetrized_cocg(pts, k, D, u0, tol=1e-13)
+    assert hist[-1] < 1e-13
+    assert _rel(u, u_ref) <= 1e-11
+
+
+# --- the Section 3 route, the padding example and Table 6 ------------------------
+def _read_blocks(path):
+    blocks, cur = {}, None
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("["):
+            cur = line.strip("[]")
+            blocks[cur] = []
+        else:
+            blocks[cur].append([float(v) for v in line.split()])
+    return {k: np.array(v) for k, v in blocks.items()}
+
+
+def test_section3_padding_example():
+    g = _read_blocks(os.path.join(GOLDEN, "section3_padding_example.txt"))
+    assert np.array_equal(O.mirror_pad_axis(g["G"], 1), g["G_padded"])
+    assert np.array_equal(O.zero_pad_axis(g["G"], 1, 6), g["u_padded"])
+
+
+@pytest.mark.parametrize("n,k,side", [(1, 1.0, 1.0), (2, 3.0, 1.0), (3, 5.0, 0.7), (5, 2.0, 1.0), (8, 9.0, 2.0)])
+def test_section3_route_equals_dense_sum(n, k, side):
+    pts, h, N, v = _varied_case(n, k, seed=n, side=side)
+    D = O.coupling(h, N, n, side)
+    y_dense = O.scatter_dense(pts, k, D, v)
+    y_fft = O.scatter_section3(n, k, D, v, side=side)
+    if n == 1:
+        assert np.all(y_dense == 0) and np.all(y_fft == 0)
+    else:
+        assert _rel(y_fft, y_dense) <= 1e-13
+
+
+def test_row_sampler_equals_dense_rows():
+    n, k = 6, 4.0
+    pts, h, N, v = _varied_case(n, k, seed=2)
+    D = O.coupling(h, N, n)
+    rows = np.array([0, 7, 100, 215])
+    y = O.sample_scatter_rows(pts, k, D, v, rows, chunk=50)
+    y_dense = O.scatter_dense(pts, k, D, v)[rows]
+    assert np.max(np.abs(y - y_dense)) <= 1e-14 * np.max(np.abs(y_dense))
+
+
+def test_paper_table6_first_iterate():
+    # Weak pin at the paper's own scale (b = 20, P = 8000, Section 4 values):
+    # the printed digits are those of the first COCG iterate of the
+    # sign-flipped system on the corner lattice (see the fixture header).
+    rows = np.loadtxt(os.path.join(GOLDEN, "table6_red_b20.txt"))
+    b, k = 20, 0.182651
+    h = np.full(b ** 3, 2.65481e-09 + 5.30961e-06j)
+    D = -O.coupling(h, None, b)                       # h -> -h
+    u0 = workloads.plane_wave(b, k, (1.0, 0.0, 0.0), offset=0.0)
+
+    def apply(v):
+        return v + O.scatter_section3(b, k, D, v)
+
+    x1, _ = O.cocg(apply, u0, tol=0.0, maxiter=1)
+    got = x1.reshape(b, b, b)
+    for i1, re, im in rows:
+        plane = got[int(i1)]
+        # all entries of the printed 5x5 block are equal; check the lattice
+        # points i2, i3 in {0, 4, 8, 12, 16}
+        sub = plane[::4, ::4]
+        assert np.all(np.abs(sub.real - re) <= 0.5e-6 + 1e-12)
+        assert np.all(np.abs(sub.imag - im) <= 0.5e-6 + 1e-12)
+    # and the printed sign of eq. 2.19 does not reproduce the first block
+    x1p, _ = O.cocg(lambda v: v + O.scatter_section3(b, k, -D, v), u0, tol=0.0, maxiter=1)
+    assert abs(x1p[0].imag - rows[0, 2]) > 1e-5
+
+
+def test_workload_generator_is_seeded():
+    a = workloads.make_case(4, 5.0, 3)
+    b = workloads.make_case(4, 5.0, 3)
+    assert np.array_equal(a["h"], b["h"]) and np.array_equal(a["u0"], b["u0"])
+    assert abs(np.linalg.norm(a["alpha"]) - 1) < 1e-15
+    pts = O.cell_points(4)
+    assert _rel(a["u0"], np.exp(1j * 5.0 * pts @ a["alpha"])) <= 1e-14
+    d = workloads.fibonacci_directions(32)
+    assert np.allclose(np.linalg.norm(d, axis=1), 1.0)
