@@ -1,0 +1,174 @@
+/*
+ * ori.h -- C ABI of the MI355X (gfx950) solver for the reduced linear system
+ * of Ramm & Tran, "A Fast Algorithm for Solving Scalar Wave Scattering
+ * Problem by Billions of Particles" (arXiv:1602.04691).
+ *
+ * The system (Section 2, eq. 2.19, with c_S = 4 pi for spheres):
+ *
+ *     u_q + sum_{p != q} G(x_q, x_p) D_p u_p = u0_q,     q = 0 .. P-1,
+ *     G(x, y) = exp(i k |x - y|) / (4 pi |x - y|)           (eq. 2.6a)
+ *     D_p     = 4 pi h_p N_p |Delta_p|,  |Delta_p| = (side/n)^3,
+ *
+ * on the n^3 cubes Delta_p of the cube [origin, origin + side]^3, with the
+ * point x_p = origin + side * (i + cell_offset) / n of each cube
+ * (cell_offset = 0.5: centres, eqs. 2.18-2.19; 0: the lattice of eq. 3.3.5).
+ * It is solved by COCG (van der Vorst & Melissen; cited in Sections 1 and 3)
+ * whose products with the Green's matrix are 3-D convolutions evaluated with
+ * FFTs after zero padding (Section 3, eqs. 3.3.4-3.3.8): here on a (2n)^3
+ * grid with a precomputed kernel spectrum.
+ *
+ * Conventions (all entry points):
+ *  - Flat index p = (i1 * n + i2) * n + i3, i3 fastest.  P = n^3.
+ *  - Complex arrays are interleaved {re, im} doubles (C99 double complex,
+ *    torch.complex128), 16-byte aligned.
+ *  - Every array argument is DEVICE memory of the current HIP device
+ *    (hipMalloc / torch CUDA tensors).  Host pointers are rejected with
+ *    ORI_ERR_INVALID_ARG before any kernel runs.  Structs (ori_grid,
+ *    ori_solve_opts, ori_solve_info) are host memory.
+ *  - Caller buffers are never retained: ori_load copies what it needs.
+ *  - All device work is ordered on the stream given to ori_create /
+ *    ori_setup (NULL: the null stream); every call returns after that work
+ *    has completed.
+ *  - Errors are status codes; nothing aborts or throws across the ABI.
+ *    ori_last_error(ctx) gives a text.  After ORI_ERR_DEVICE the context is
+ *    poisoned: only ori_destroy is valid.
+ *  - A context is not thread safe; distinct contexts are independent.
+ *  - Supported n: 2n must factor as 2^a 3^b 5^c with 2n in
+ *    {2,4,6,8,10,12,16,20,24,32,40,48,64,80,96,128,192,256,384,512,1024};
+ *    any other n gives ORI_ERR_UNSUPPORTED.
+ */
+#ifndef ORI_H
+#define ORI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ori_ctx_s* ori_ctx; /* opaque; owns every device workspace */
+
+typedef enum {
+  ORI_OK = 0,
+  ORI_ERR_INVALID_ARG = 1,   /* bad size, pointer, value (NaN/Inf, N < 0, ...) */
+  ORI_ERR_OUT_OF_MEMORY = 2, /* workspace above the given limit, or hipMalloc failed */
+  ORI_ERR_DEVICE = 3,        /* a HIP call failed; the context is poisoned */
+  ORI_ERR_BREAKDOWN = 4,     /* COCG breakdown: r^T r = 0 or p^T A p = 0 with r, p != 0 */
+  ORI_ERR_NOT_CONVERGED = 5, /* iteration limit reached; u holds the last iterate */
+  ORI_ERR_UNSUPPORTED = 6    /* n with no FFT plan */
+} ori_status;
+
+typedef enum {
+  ORI_FP64 = 0, /* complex128 everywhere */
+  ORI_MIXED = 1 /* complex64 FFT matvec, FP64 reductions and FP64 true-residual refinement */
+} ori_precision;
+
+typedef enum {
+  ORI_OP_SYSTEM = 0,    /* y = x + G0 (D x)            the matrix of eq. 2.19      */
+  ORI_OP_SYMMETRIC = 1, /* y = x + S G0 (S x), S^2 = D  its complex-symmetric form */
+  ORI_OP_GREEN = 2      /* y = G0 x                     the sum of eq. 3.3.4 alone */
+} ori_operator;
+
+/* Bit mask for ori_create: which precisions get workspaces. */
+#define ORI_PROVISION_FP64 1
+#define ORI_PROVISION_MIXED 2
+
+typedef struct {
+  int64_t n;          /* cubes per side (P = n^3 unknowns), n >= 1          */
+  double side;        /* edge of the cube domain (> 0); the paper uses 1     */
+  double origin[3];   /* corner of the cube domain                           */
+  double cell_offset; /* point of each cube: origin + side*(i + offset)/n    */
+} ori_grid;
+
+typedef struct {
+  double tol;            /* stop when ||r|| / ||b|| < tol (recursive residual of the
+                            symmetric system; Section 4's residual-based error)       */
+  int32_t max_iter;      /* COCG iteration cap (FP64); total inner iterations (mixed)  */
+  int32_t precision;     /* ori_precision                                           */
+  int32_t check_every;   /* read the residual norm on the host every this many
+                            iterations (>= 1; 0 means 1)                             */
+  int32_t use_x0;        /* 1: u holds an initial guess of u on entry                */
+  double inner_tol;      /* mixed: relative tolerance of each inner solve (0: 1e-5)  */
+  int32_t max_outer;     /* mixed: refinement cycles (0: 10)                         */
+  int32_t true_residual; /* 1: also compute ||u0 - A u|| / ||u0|| (one extra matvec) */
+} ori_solve_opts;
+
+typedef struct {
+  int32_t iterations;       /* COCG iterations (FP64 + inner complex64)            */
+  int32_t refinements;      /* mixed: FP64 refinement cycles performed             */
+  int64_t matvecs;          /* FFT operator applications, all precisions           */
+  int64_t matvecs_c64;      /* ... of which in complex64                           */
+  double rel_res_recursive; /* final ||r|| / ||b|| of the symmetric system         */
+  double rel_res_true;      /* ||u0 - A u|| / ||u0|| of eq. 2.19, or -1 if not asked */
+  double seconds;           /* wall time of the call                               */
+} ori_solve_info;
+
+/* Fill opts with the defaults: tol 1e-10, max_iter 1000, FP64, check_every 1,
+ * no x0, inner_tol 1e-5, max_outer 10, true_residual 1. */
+void ori_default_opts(ori_solve_opts* opts);
+
+/* Device bytes that ori_create would allocate for this grid and provision
+ * mask (host-only arithmetic; no device call).  Returns ORI_ERR_INVALID_ARG /
+ * ORI_ERR_UNSUPPORTED for a bad grid. */
+ori_status ori_workspace_bytes(const ori_grid* g, int32_t provision, int64_t* bytes);
+
+/* Allocate a context and its workspaces for grid g (a1-a2 buffers, the FFT
+ * arena, the COCG vectors).  provision: ORI_PROVISION_* mask (FP64 is always
+ * provisioned).  mem_limit_bytes > 0 caps the workspace: above it the call
+ * returns ORI_ERR_OUT_OF_MEMORY without touching the device.  stream: a
+ * hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL. */
+ori_status ori_create(const ori_grid* g, int32_t provision, int64_t mem_limit_bytes,
+                      void* stream, ori_ctx* out);
+
+/* Compute the coefficients and the kernel spectrum for wave number k > 0
+ * (Sections 2-3): D = 4 pi h N |Delta|, S = sqrt(D), b = S u0, and the FFT
+ * of the zero-excluded Green's table G(|m| side/n) on the (2n)^3 grid.
+ *   h  : device complex128[P], boundary impedance function h(x_p) (eq. 2.19)
+ *   N  : device float64[P], distribution density N(x_p) >= 0 (eq. 2.17);
+ *        NULL means N = 1
+ *   u0 : device complex128[P], incident field u0(x_p) (eq. 2.4 or any field)
+ * NaN/Inf anywhere or N < 0 gives ORI_ERR_INVALID_ARG.  May be called again
+ * on the same context with new data (no reallocation). */
+ori_status ori_load(ori_ctx ctx, double k, const void* h, const double* N, const void* u0);
+
+/* ori_create(g, FP64|MIXED, 0, stream, out) followed by ori_load. */
+ori_status ori_setup(const ori_grid* g, double k, const void* h, const double* N,
+                     const void* u0, void* stream, ori_ctx* out);
+
+/* Solve eq. 2.19 for u (device complex128[P]).  COCG runs on the complex
+ * symmetric form (I + S G0 S) w = S u0 and returns u = u0 - G0 S w.
+ * opts NULL: defaults.  info (host, may be NULL) is filled on every return
+ * that reached the device.  On ORI_ERR_NOT_CONVERGED / ORI_ERR_BREAKDOWN u
+ * holds the solution recovered from the last iterate. */
+ori_status ori_solve(ori_ctx ctx, const ori_solve_opts* opts, void* u, ori_solve_info* info);
+
+/* y = op(x) with the FFT operator (device complex128[P] each; x != y).
+ * precision ORI_MIXED runs the FFT stages in complex64 (inputs and outputs
+ * stay complex128).  Used by tests and the benchmark. */
+ori_status ori_matvec(ori_ctx ctx, int32_t op, int32_t precision, const void* x, void* y);
+
+/* Per-kernel timing with HIP events on the context stream.  enable = 1
+ * clears the counters and starts recording every launch; 0 stops. */
+ori_status ori_profile_enable(ori_ctx ctx, int32_t enable);
+
+/* Average device duration (ms) and launch count of each kernel kind since
+ * ori_profile_enable(ctx, 1).  names[i] (static strings) identify the kinds;
+ * up to max entries are written; *count receives the number of kinds. */
+ori_status ori_profile_read(ori_ctx ctx, int32_t max, const char** names, double* avg_ms,
+                            int64_t* launches, int32_t* count);
+
+/* Release every device allocation of ctx (NULL is ignored). */
+void ori_destroy(ori_ctx ctx);
+
+/* Text of the last error on ctx, or of the last failed ori_create/ori_setup
+ * in this thread when ctx is NULL.  Never NULL. */
+const char* ori_last_error(ori_ctx ctx);
+
+/* Library version string. */
+const char* ori_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORI_H */

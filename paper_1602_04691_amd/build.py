@@ -1,0 +1,96 @@
+"""Build libori.so for gfx950 with hipcc (in-tree, no JIT cache).
+
+    python -m paper_1602_04691_amd.build [--jobs N] [--incremental]
+
+Compiles the FFT pass kernels once per supported padded length L
+(``csrc/passes.hip`` with ``-DORI_L=<L>``), the auxiliary kernels and the
+host runtime, and links ``paper_1602_04691_amd/libori.so``.
+"""
+
+import argparse
+import os
+import re
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libori.so")
+ARCH = "gfx950"
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # no packed FP32 instructions anywhere in this library
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", INCLUDE, "-I", CSRC,
+]
+
+
+def supported_lengths():
+    text = open(os.path.join(CSRC, "plan.h")).read()
+    m = re.search(r"#define ORI_FOR_EACH_L\(X\)(.*?)\n\n", text, re.S)
+    return [int(v) for v in re.findall(r"X\((\d+)\)", m.group(1))]
+
+
+def _sources():
+    units = [(os.path.join(CSRC, "passes.hip"), f"passes_L{L}.o", [f"-DORI_L={L}"])
+             for L in supported_lengths()]
+    units.append((os.path.join(CSRC, "aux.hip"), "aux.o", []))
+    units.append((os.path.join(CSRC, "ori_api.cpp"), "ori_api.o", ["-x", "hip"]))
+    return units
+
+
+def _deps_mtime():
+    return max(os.path.getmtime(os.path.join(d, f))
+               for d in (CSRC, INCLUDE) for f in os.listdir(d)
+               if f.endswith((".h", ".hip", ".cpp")))
+
+
+def _compile(unit, incremental):
+    src, obj, extra = unit
+    out = os.path.join(BUILD, obj)
+    if incremental and os.path.exists(out) and os.path.getmtime(out) >= _deps_mtime():
+        return out, ""
+    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", out]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    log = "\n".join(l for l in (p.stdout + p.stderr).splitlines() if "packed-fp32-ops" not in l)
+    if p.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{log}")
+    return out, log
+
+
+def build(jobs=None, incremental=False, verbose=False):
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or int(os.environ.get("MAX_JOBS", "0") or 0) or min(16, os.cpu_count() or 4)
+    units = _sources()
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda u: _compile(u, incremental), units))
+    objs = [o for o, _ in results]
+    for _, log in results:
+        if verbose and log.strip():
+            print(log)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{p.stdout}{p.stderr}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true")
+    ap.add_argument("-v", "--verbose", action="store_true")
+    a = ap.parse_args(argv)
+    print(build(a.jobs, a.incremental, a.verbose))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,356 @@
+// Register/LDS Stockham FFT engine for one workgroup of pencils (gfx950).
+//
+// The product with the Green's matrix is a 3-D convolution (Section 3,
+// eqs. 3.3.4-3.3.7), evaluated with the convolution theorem (eq. 3.3.8) on
+// a grid padded to L = 2n per axis.  Each pass of that evaluation is a batch
+// of length-L DFTs along one axis ("pencils").  A workgroup owns NP pencils
+// and TPP threads per pencil; each thread holds whole radix-R butterflies in
+// registers.  Stage s reads its inputs at  b + r * (L / R)  and writes its
+// outputs at  (b - k) R + k + j Ns  (k = b mod Ns, Ns = product of earlier
+// radices): the self-sorting Stockham order, so the last stage writes the
+// natural order and no bit reversal pass is needed.  The first stage reads
+// and the last stage writes global memory directly (the pattern
+// b + r * (L/R) is coalesced both along a contiguous pencil and across
+// adjacent strided pencils); the stages in between exchange through LDS.
+#pragma once
+
+#include "cx.h"
+#include "plan.h"
+
+namespace ori {
+
+// ---------------------------------------------------------------------------
+// DFT butterflies, natural order in and out.  Forward uses exp(-2 pi i/R).
+// ---------------------------------------------------------------------------
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> mul_w4(cx<T> a) {  // * exp(-+ i pi/2)
+  return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+// multiply by exp(-+ 2 pi i m / 16) for m = 0..7 (compile-time m)
+template <bool INV, int M, typename T>
+__device__ __forceinline__ cx<T> mul_w16(cx<T> a) {
+  constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+  constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+  constexpr double H = 0.70710678118654752440;   // cos(pi/4)
+  constexpr double cs[8] = {1.0, C1, H, S1, 0.0, -S1, -H, -C1};
+  constexpr double sn[8] = {0.0, S1, H, C1, 1.0, C1, H, S1};
+  if constexpr (M == 0) return a;
+  if constexpr (M == 4) return mul_w4<INV>(a);
+  const T c = static_cast<T>(cs[M]);
+  const T s = INV ? static_cast<T>(sn[M]) : static_cast<T>(-sn[M]);
+  return {a.re * c - a.im * s, a.re * s + a.im * c};
+}
+
+template <bool INV, int R, typename T>
+struct Dft;
+
+template <bool INV, typename T>
+struct Dft<INV, 2, T> {
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    cx<T> a = v[0];
+    v[0] = a + v[1];
+    v[1] = a - v[1];
+  }
+  __device__ __forceinline__ static void run_half(cx<T>* v) { v[1] = v[0]; }
+};
+
+template <bool INV, typename T>
+struct Dft<INV, 4, T> {
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+    cx<T> t2 = v[1] + v[3], t3 = mul_w4<INV>(v[1] - v[3]);
+    v[0] = t0 + t2;
+    v[2] = t0 - t2;
+    v[1] = t1 + t3;
+    v[3] = t1 - t3;
+  }
+  // inputs 2, 3 are zero
+  __device__ __forceinline__ static void run_half(cx<T>* v) {
+    cx<T> a = v[0], b = v[1], bw = mul_w4<INV>(v[1]);
+    v[0] = a + b;
+    v[2] = a - b;
+    v[1] = a + bw;
+    v[3] = a - bw;
+  }
+};
+
+template <bool INV, typename T>
+struct Dft<INV, 8, T> {
+  __device__ __forceinline__ static void combine(cx<T>* v, cx<T>* e, cx<T>* o) {
+    o[1] = mul_w16<INV, 2>(o[1]);
+    o[2] = mul_w16<INV, 4>(o[2]);
+    o[3] = mul_w16<INV, 6>(o[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = e[k] + o[k];
+      v[k + 4] = e[k] - o[k];
+    }
+  }
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<INV, 4, T>::run(e);
+    Dft<INV, 4, T>::run(o);
+    combine(v, e, o);
+  }
+  __device__ __forceinline__ static void run_half(cx<T>* v) {
+    cx<T> e[4] = {v[0], v[2], {}, {}};
+    cx<T> o[4] = {v[1], v[3], {}, {}};
+    Dft<INV, 4, T>::run_half(e);
+    Dft<INV, 4, T>::run_half(o);
+    combine(v, e, o);
+  }
+};
+
+template <bool INV, typename T>
+struct Dft<INV, 16, T> {
+  __device__ __forceinline__ static void combine(cx<T>* v, cx<T>* e, cx<T>* o) {
+    o[1] = mul_w16<INV, 1>(o[1]);
+    o[2] = mul_w16<INV, 2>(o[2]);
+    o[3] = mul_w16<INV, 3>(o[3]);
+    o[4] = mul_w16<INV, 4>(o[4]);
+    o[5] = mul_w16<INV, 5>(o[5]);
+    o[6] = mul_w16<INV, 6>(o[6]);
+    o[7] = mul_w16<INV, 7>(o[7]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      v[k] = e[k] + o[k];
+      v[k + 8] = e[k] - o[k];
+    }
+  }
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    cx<T> e[8], o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      e[k] = v[2 * k];
+      o[k] = v[2 * k + 1];
+    }
+    Dft<INV, 8, T>::run(e);
+    Dft<INV, 8, T>::run(o);
+    combine(v, e, o);
+  }
+  __device__ __forceinline__ static void run_half(cx<T>* v) {
+    cx<T> e[8] = {v[0], v[2], v[4], v[6], {}, {}, {}, {}};
+    cx<T> o[8] = {v[1], v[3], v[5], v[7], {}, {}, {}, {}};
+    Dft<INV, 8, T>::run_half(e);
+    Dft<INV, 8, T>::run_half(o);
+    combine(v, e, o);
+  }
+};
+
+template <bool INV, typename T>
+struct Dft<INV, 3, T> {
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    constexpr double C = -0.5;
+    constexpr double S = 0.86602540378443864676;  // sin(2 pi / 3)
+    const T sg = INV ? static_cast<T>(S) : static_cast<T>(-S);
+    cx<T> s = v[1] + v[2], d = v[1] - v[2];
+    cx<T> m = {v[0].re + static_cast<T>(C) * s.re, v[0].im + static_cast<T>(C) * s.im};
+    cx<T> id = {-sg * d.im, sg * d.re};  // i * sg * d
+    v[0] = v[0] + s;
+    v[1] = m + id;
+    v[2] = m - id;
+  }
+};
+
+template <bool INV, typename T>
+struct Dft<INV, 5, T> {
+  __device__ __forceinline__ static void run(cx<T>* v) {
+    constexpr double C1 = 0.30901699437494742410;   // cos(2 pi/5)
+    constexpr double C2 = -0.80901699437494742410;  // cos(4 pi/5)
+    constexpr double S1 = 0.95105651629515357212;   // sin(2 pi/5)
+    constexpr double S2 = 0.58778525229247312917;   // sin(4 pi/5)
+    const T s1 = INV ? static_cast<T>(S1) : static_cast<T>(-S1);
+    const T s2 = INV ? static_cast<T>(S2) : static_cast<T>(-S2);
+    const T c1 = static_cast<T>(C1), c2 = static_cast<T>(C2);
+    cx<T> b1 = v[1] + v[4], b2 = v[2] + v[3];
+    cx<T> d1 = v[1] - v[4], d2 = v[2] - v[3];
+    cx<T> m1 = {v[0].re + c1 * b1.re + c2 * b2.re, v[0].im + c1 * b1.im + c2 * b2.im};
+    cx<T> m2 = {v[0].re + c2 * b1.re + c1 * b2.re, v[0].im + c2 * b1.im + c1 * b2.im};
+    // i * (s1 d1 + s2 d2) and i * (s2 d1 - s1 d2)
+    cx<T> n1 = {-(s1 * d1.im + s2 * d2.im), s1 * d1.re + s2 * d2.re};
+    cx<T> n2 = {-(s2 * d1.im - s1 * d2.im), s2 * d1.re - s1 * d2.re};
+    v[0] = v[0] + b1 + b2;
+    v[1] = m1 + n1;
+    v[4] = m1 - n1;
+    v[2] = m2 + n2;
+    v[3] = m2 - n2;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Stage bookkeeping
+// ---------------------------------------------------------------------------
+template <int L, bool INV>
+struct Stages {
+  static constexpr RadixPlan plan = radix_plan(L);
+  static constexpr int NS = plan.n;
+  static constexpr int TPP = threads_per_pencil(L);
+  static constexpr int radix(int s) { return INV ? plan.r[NS - 1 - s] : plan.r[s]; }
+  static constexpr int ns(int s) {  // product of the radices before stage s
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= radix(i);
+    return p;
+  }
+  static constexpr int nbf(int s) { return L / radix(s); }            // butterflies per pencil
+  static constexpr int cnt(int s) { return (nbf(s) + TPP - 1) / TPP; }  // per thread
+};
+
+// One thread's view of its pencil in LDS: element e lives at base[e * ES].
+template <typename T>
+struct LdsPencil {
+  cx<T>* base;
+  int es;
+  __device__ __forceinline__ cx<T>& at(int e) const { return base[e * es]; }
+};
+
+// Stage data: cnt(s) butterflies of radix(s) complex values.
+template <typename T, int C, int R>
+struct Regs {
+  cx<T> v[C][R];
+};
+
+template <typename T, int L, bool INV>
+struct Engine {
+  using St = Stages<L, INV>;
+  static constexpr int NS = St::NS;
+  static constexpr int TPP = St::TPP;
+
+  template <int s>
+  using RegsOf = Regs<T, St::cnt(s), St::radix(s)>;
+
+  // twiddle + butterfly of stage s, in registers
+  template <int s, bool HALF_IN>
+  __device__ __forceinline__ static void compute(RegsOf<s>& g, int bt, const cx<T>* __restrict__ tw) {
+    constexpr int R = St::radix(s);
+    constexpr int NSs = St::ns(s);
+    constexpr int TS = L / (NSs * R);
+#pragma unroll
+    for (int i = 0; i < St::cnt(s); ++i) {
+      const int b = bt + i * TPP;
+      if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
+      if constexpr (NSs > 1) {
+        const int k = b % NSs;
+#pragma unroll
+        for (int r = 1; r < R; ++r) g.v[i][r] = twiddle<INV>(g.v[i][r], tw[r * k * TS]);
+      }
+      if constexpr (HALF_IN && s == 0 && (R % 2 == 0)) {
+        Dft<INV, R, T>::run_half(g.v[i]);
+      } else {
+        Dft<INV, R, T>::run(g.v[i]);
+      }
+    }
+  }
+
+  // outputs of stage s -> LDS (Stockham positions)
+  template <int s>
+  __device__ __forceinline__ static void write_lds(const RegsOf<s>& g, int bt, LdsPencil<T> p) {
+    constexpr int R = St::radix(s);
+    constexpr int NSs = St::ns(s);
+#pragma unroll
+    for (int i = 0; i < St::cnt(s); ++i) {
+      const int b = bt + i * TPP;
+      if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
+      const int k = b % NSs;
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int j = 0; j < R; ++j) p.at(base + j * NSs) = g.v[i][j];
+    }
+  }
+
+  // inputs of stage s <- LDS
+  template <int s>
+  __device__ __forceinline__ static void read_lds(RegsOf<s>& g, int bt, LdsPencil<T> p) {
+    constexpr int R = St::radix(s);
+    constexpr int STRIDE = L / R;
+#pragma unroll
+    for (int i = 0; i < St::cnt(s); ++i) {
+      const int b = bt + i * TPP;
+      if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
+#pragma unroll
+      for (int r = 0; r < R; ++r) g.v[i][r] = p.at(b + r * STRIDE);
+    }
+  }
+
+  // Stage 0 inputs from a functor: load(e) for e = b + r L/R0.  With HALF_IN
+  // the upper half (e >= L/2) is zero and never loaded.
+  template <bool HALF_IN, class Load>
+  __device__ __forceinline__ static void load_first(RegsOf<0>& g, int bt, Load&& load) {
+    constexpr int R = St::radix(0);
+    constexpr int STRIDE = L / R;
+    constexpr bool SKIP = HALF_IN && (R % 2 == 0);
+#pragma unroll
+    for (int i = 0; i < St::cnt(0); ++i) {
+      const int b = bt + i * TPP;
+      if (St::nbf(0) % TPP != 0 && b >= St::nbf(0)) continue;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (SKIP && r >= R / 2) {
+          g.v[i][r] = cx<T>{};
+        } else if (HALF_IN && !SKIP) {
+          const int e = b + r * STRIDE;
+          g.v[i][r] = e < L / 2 ? load(e) : cx<T>{};
+        } else {
+          g.v[i][r] = load(b + r * STRIDE);
+        }
+      }
+    }
+  }
+
+  // Last-stage outputs to a functor: store(e, value) for e = b + j L/R_last.
+  // With HALF_OUT only e < L/2 is stored.
+  template <bool HALF_OUT, class Store>
+  __device__ __forceinline__ static void store_last(const RegsOf<NS - 1>& g, int bt, Store&& store) {
+    constexpr int s = NS - 1;
+    constexpr int R = St::radix(s);
+    constexpr int STRIDE = L / R;
+#pragma unroll
+    for (int i = 0; i < St::cnt(s); ++i) {
+      const int b = bt + i * TPP;
+      if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int e = b + j * STRIDE;
+        if (HALF_OUT && (R % 2 == 0) && j >= R / 2) continue;
+        if (HALF_OUT && (R % 2 != 0) && e >= L / 2) continue;
+        store(e, g.v[i][j]);
+      }
+    }
+  }
+
+  // Run stages s..NS-1 starting from inputs already in LDS; hand the last
+  // stage's outputs (natural order, element b + j L/R) to fin(regs).
+  template <int s, class Fin>
+  __device__ __forceinline__ static void run_from_lds(int bt, LdsPencil<T> p, const cx<T>* __restrict__ tw,
+                                                      Fin&& fin) {
+    RegsOf<s> g;
+    read_lds<s>(g, bt, p);
+    __syncthreads();
+    compute<s, false>(g, bt, tw);
+    if constexpr (s + 1 < NS) {
+      write_lds<s>(g, bt, p);
+      __syncthreads();
+      run_from_lds<s + 1>(bt, p, tw, fin);
+    } else {
+      fin(g);
+    }
+  }
+
+  // Whole transform: stage 0 from registers g0 (already loaded), the rest
+  // through LDS; fin(regs of the last stage).
+  template <bool HALF_IN, class Fin>
+  __device__ __forceinline__ static void run(RegsOf<0>& g0, int bt, LdsPencil<T> p,
+                                             const cx<T>* __restrict__ tw, Fin&& fin) {
+    compute<0, HALF_IN>(g0, bt, tw);
+    if constexpr (NS > 1) {
+      write_lds<0>(g0, bt, p);
+      __syncthreads();
+      run_from_lds<1>(bt, p, tw, fin);
+    } else {
+      fin(g0);
+    }
+  }
+};
+
+}  // namespace ori

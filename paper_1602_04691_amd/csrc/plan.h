@@ -1,0 +1,97 @@
+// FFT plans for the padded length L = 2n of each axis (Section 3 pads every
+// axis before the convolution theorem, eq. 3.3.8).  Shared by host and device
+// code: everything here is constexpr.
+#pragma once
+
+#include <cstdint>
+
+namespace ori {
+
+// Every supported padded length, one translation unit of FFT kernels each.
+#define ORI_FOR_EACH_L(X) \
+  X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) \
+  X(128) X(192) X(256) X(384) X(512) X(1024)
+
+struct RadixPlan {
+  int n;     // number of Stockham stages
+  int r[4];  // forward radix order; the inverse runs them in reverse
+};
+
+// The first forward radix is even so that the zero upper half of a padded
+// input is skipped at compile time; few stages (radix 8 / 16) keep the LDS
+// exchanges between stages to a minimum.
+constexpr RadixPlan radix_plan(int L) {
+  switch (L) {
+    case 2: return {1, {2, 0, 0, 0}};
+    case 4: return {1, {4, 0, 0, 0}};
+    case 6: return {2, {2, 3, 0, 0}};
+    case 8: return {1, {8, 0, 0, 0}};
+    case 10: return {2, {2, 5, 0, 0}};
+    case 12: return {2, {4, 3, 0, 0}};
+    case 16: return {1, {16, 0, 0, 0}};
+    case 20: return {2, {4, 5, 0, 0}};
+    case 24: return {2, {8, 3, 0, 0}};
+    case 32: return {2, {8, 4, 0, 0}};
+    case 40: return {2, {8, 5, 0, 0}};
+    case 48: return {2, {16, 3, 0, 0}};
+    case 64: return {2, {8, 8, 0, 0}};
+    case 80: return {2, {16, 5, 0, 0}};
+    case 96: return {3, {8, 4, 3, 0}};
+    case 128: return {2, {16, 8, 0, 0}};
+    case 192: return {3, {8, 8, 3, 0}};
+    case 256: return {2, {16, 16, 0, 0}};
+    case 384: return {3, {16, 8, 3, 0}};
+    case 512: return {3, {8, 8, 8, 0}};
+    case 1024: return {3, {16, 8, 8, 0}};
+    default: return {0, {0, 0, 0, 0}};
+  }
+}
+
+constexpr bool supported_length(int L) { return radix_plan(L).n > 0; }
+
+// Threads per pencil: the smallest butterfly count over the stages, so that
+// no stage leaves threads idle in its widest configuration.
+constexpr int threads_per_pencil(int L) {
+  RadixPlan p = radix_plan(L);
+  int t = L;
+  for (int s = 0; s < p.n; ++s) {
+    int b = L / p.r[s];
+    if (b < t) t = b;
+  }
+  return t;
+}
+
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+
+// Pencils per workgroup.  Strided passes need several adjacent pencils per
+// row so that each row read/written is a contiguous run (8 x 16 B = 128 B for
+// complex128, 16 x 8 B for complex64); contiguous passes only need enough
+// threads to fill the workgroup.
+// Workgroups are whole wavefronts (64 lanes): the reductions use full-wave
+// shuffles.
+constexpr int whole_waves(int np, int tpp) {
+  while ((np * tpp) % 64 != 0) np *= 2;
+  return np;
+}
+
+constexpr int pencils_strided(int L, int elem_bytes) {
+  int tpp = threads_per_pencil(L);
+  int np = pow2_floor(256 / tpp);
+  int lo = elem_bytes == 16 ? 8 : 16;
+  if (np < lo) np = lo;
+  if (np > 64) np = 64;
+  return whole_waves(np, tpp);
+}
+
+constexpr int pencils_contig(int L) {
+  int tpp = threads_per_pencil(L);
+  int np = pow2_floor(256 / tpp);
+  if (np < 1) np = 1;
+  return whole_waves(np, tpp);
+}
+
+}  // namespace ori

@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/ori.h declares, and rejects bad arguments before
+touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1602_04691_amd as ori
+from paper_1602_04691_amd import build as ori_build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ori.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ori_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(ori.LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding wraps each one
+    for n in names:
+        assert hasattr(ori, n), n
+
+
+def test_supported_lengths_match_header():
+    text = open(HEADER).read()
+    m = re.search(r"2n in\s*\*\s*\{([0-9,\s*]+)\}", text)
+    listed = [int(v) for v in re.findall(r"\d+", m.group(1))]
+    assert listed == ori_build.supported_lengths()
+
+
+def test_version_and_defaults():
+    assert "gfx950" in ori.ori_version()
+    o = ori.ori_default_opts()
+    assert o.tol == 1e-10 and o.max_iter == 1000 and o.precision == ori.ORI_FP64
+    assert o.check_every == 1 and o.true_residual == 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 16, 64, 128, 256, 512])
+def test_workspace_bytes_supported(n):
+    b = ori.ori_workspace_bytes(n)
+    L = 2 * n
+    assert b >= (L ** 3) * 16 + 8 * n ** 3 * 16
+    # FP64-only provisioning is smaller
+    assert ori.ori_workspace_bytes(n, ori.ORI_PROVISION_FP64) < b
+
+
+def test_workspace_bytes_metric_size_fits_hbm():
+    # n = 256 (16.8 M unknowns): a few GB; n = 512 stays far below 288 GB
+    assert ori.ori_workspace_bytes(256) < 8e9
+    assert ori.ori_workspace_bytes(512) < 60e9
+
+
+@pytest.mark.parametrize("n,status", [(0, ori.ORI_ERR_INVALID_ARG), (-3, ori.ORI_ERR_INVALID_ARG),
+                                      (7, ori.ORI_ERR_UNSUPPORTED), (11, ori.ORI_ERR_UNSUPPORTED),
+                                      (1024, ori.ORI_ERR_UNSUPPORTED)])
+def test_bad_grid_rejected_on_host(n, status):
+    with pytest.raises(ori.OriError) as e:
+        ori.ori_workspace_bytes(n)
+    assert e.value.status == status
+    assert ori.ori_last_error() != "no error"
+
+
+def test_bad_side_and_null_grid():
+    lib = ori.lib()
+    g = ori._grid(8, side=float("nan"))
+    out = ctypes.c_int64()
+    assert lib.ori_workspace_bytes(ctypes.byref(g), 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_workspace_bytes(None, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    g = ori._grid(8, side=-1.0)
+    assert lib.ori_workspace_bytes(ctypes.byref(g), 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    g = ori._grid(8, origin=(0.0, float("inf"), 0.0))
+    assert lib.ori_workspace_bytes(ctypes.byref(g), 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+
+
+def test_memory_limit_rejected_before_any_device_call():
+    # n = 512 under a 1 GB cap: ORI_ERR_OUT_OF_MEMORY, decided on the host
+    lib = ori.lib()
+    h = ctypes.c_void_p()
+    g = ori._grid(512)
+    st = lib.ori_create(ctypes.byref(g), 3, 1 << 30, None, ctypes.byref(h))
+    assert st == ori.ORI_ERR_OUT_OF_MEMORY
+    assert h.value is None
+    assert "exceeds the limit" in ori.ori_last_error()
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = ori.lib()
+    assert lib.ori_load(None, 1.0, None, None, None) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_solve(None, None, None, None) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_matvec(None, 0, 0, None, None) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_profile_enable(None, 1) == ori.ORI_ERR_INVALID_ARG
+    lib.ori_destroy(None)
+    assert lib.ori_create(None, 3, 0, None, None) == ori.ORI_ERR_INVALID_ARG
+
+
+def test_no_oracle_in_product_path():
+    # the library and its binding never reach the CPU oracle
+    pkg = os.path.join(ROOT, "paper_1602_04691_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
