@@ -1,0 +1,319 @@
+"""Benchmark: COCG matvecs/s and achieved HBM GB/s at n = 256 (16.8 M unknowns).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu-baseline]
+
+One step is one pass of the whole solver path over one batch of synthetic
+input already resident in HBM: ori_load (coefficients D, S, b and the kernel
+spectrum on the padded (2n)^3 grid) followed by ori_solve in complex128 to a
+relative residual of 1e-8 (COCG, result recovery and the true residual of
+eq. 2.19).  ``value`` is the number of FFT operator applications per second
+over the timed steps.  The same steps are then timed with the mixed-precision
+solve, and a plain operator loop gives the per-matvec rate; the dominant
+kernel's duration is measured live with HIP events on the solver's stream.
+
+Prints ONE JSON line.  Only one GPU is used: --gpus above 1 exits with a
+message.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "COCG matvecs/sec and achieved HBM GB/s at n=256 (16.8M unknowns), fp64 vs mixed"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pass_bytes(n, elem):
+    """Algorithmic HBM bytes per launch of each pass in a COCG iteration.
+
+    Elements of the padded work arrays: A = n*n*L, B = n*L*L with L = 2n;
+    vectors are complex128 (16 B) in the FP64 solve, ``elem`` is the FFT
+    element size (16 B complex128, 8 B complex64).
+    """
+    n3 = n ** 3
+    kp3 = (n + 1) ** 3
+    vec = 16 if elem == 16 else 8  # inner mixed solve keeps vectors in complex64
+    return {
+        # read r, p, S; write p, A (2 n^3)
+        "f1": 4 * n3 * vec + 2 * n3 * elem,
+        # read A (2 n^3), write B (4 n^3)
+        "f2": 6 * n3 * elem,
+        # read B (4 n^3) and the spectrum octant, write B (4 n^3)
+        "zpass": 8 * n3 * elem + kp3 * elem,
+        # read B (4 n^3), write A (2 n^3)
+        "i2": 6 * n3 * elem,
+        # read A (2 n^3), p, S; write q
+        "i1": 2 * n3 * elem + 3 * n3 * vec,
+        # read x, p, r, q; write x, r
+        "update": 6 * n3 * vec,
+    }
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1602_04691_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, n):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_n{n}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != kernel_sources_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(case, budget_s, x):
+    """Time the CPU oracle's dense rows of the same operator (bounded sample)."""
+    import numpy as np
+    import oracle as O
+    n, k = case["n"], case["k"]
+    P = n ** 3
+    pts = O.cell_points(n)
+    D = O.coupling(case["h"], case["N"], n)
+    rng = np.random.default_rng(123)
+    rows, vals = [], []
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        q = int(rng.integers(0, P))
+        vals.append(O.sample_scatter_rows(pts, k, D, x, [q])[0])
+        rows.append(q)
+    dt = time.perf_counter() - t0
+    rate = len(rows) / dt / P  # full matvecs per second
+    return rows, np.array(vals), dt, rate
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--matvecs", type=int, default=50, help="plain operator applications timed")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle rows for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain 1-to-1 copy of this many MiB (counter calibration)")
+    a = ap.parse_args()
+
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
+              "slab/RHS sharding is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1602_04691_amd as ori
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    name = {256: "n256_k5", 128: "n128_k5", 512: "n512_k10", 16: "n16_k1"}.get(a.n)
+    case = workloads.named_case(name) if name else workloads.make_case(a.n, 5.0, seed=5)
+    n, k = case["n"], case["k"]
+    P = n ** 3
+    log(f"[bench] workload n={n} k={k} P={P} steps={a.steps} warmup={a.warmup}")
+    t_gen = time.perf_counter()
+    h = torch.from_numpy(case["h"]).to(dev)
+    N = torch.from_numpy(case["N"]).to(dev)
+    u0 = torch.from_numpy(case["u0"]).to(dev)
+    u = torch.empty(P, dtype=torch.complex128, device=dev)
+    log(f"[bench] inputs resident in HBM ({time.perf_counter() - t_gen:.1f}s)")
+
+    ctx = ori.ori_create(n)
+    stream = torch.cuda.current_stream()
+
+    def step(precision):
+        ori.ori_load(ctx, k, h, N, u0)
+        _, info = ori.ori_solve(ctx, u, tol=a.tol, precision=precision)
+        return info
+
+    def timed(precision, steps):
+        infos = []
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos.append(step(precision))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, ev0.elapsed_time(ev1) / 1e3, infos
+
+    # ---- FP64 steps (the headline value) -----------------------------------
+    for _ in range(a.warmup):
+        step(ori.ORI_FP64)
+    ori.ori_profile_enable(ctx, True)
+    wall, ev_s, infos = timed(ori.ORI_FP64, a.steps)
+    prof64 = ori.ori_profile_read(ctx)
+    ori.ori_profile_enable(ctx, False)
+    mv64 = sum(i["matvecs"] for i in infos)
+    value = mv64 / wall
+    i0 = infos[-1]
+    log(f"[bench] fp64: {wall / a.steps * 1e3:.2f} ms/step, {mv64 / a.steps:.1f} matvecs/step, "
+        f"iters={i0['iterations']} relres={i0['rel_res_recursive']:.2e} true={i0['rel_res_true']:.2e}")
+
+    # time of the solve alone (to 1e-8) without the load
+    ori.ori_load(ctx, k, h, N, u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, solve64 = ori.ori_solve(ctx, u, tol=a.tol, precision=ori.ORI_FP64)
+    t_solve64 = time.perf_counter() - t0
+    u64 = u.clone()
+
+    # ---- mixed-precision steps ---------------------------------------------
+    mixed = None
+    if not a.no_mixed:
+        for _ in range(a.warmup):
+            step(ori.ORI_MIXED)
+        ori.ori_profile_enable(ctx, True)
+        wall_m, _, infos_m = timed(ori.ORI_MIXED, a.steps)
+        profmx = ori.ori_profile_read(ctx)
+        ori.ori_profile_enable(ctx, False)
+        ori.ori_load(ctx, k, h, N, u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, solvemx = ori.ori_solve(ctx, u, tol=a.tol, precision=ori.ORI_MIXED)
+        t_solvemx = time.perf_counter() - t0
+        diff = float(torch.linalg.vector_norm(u - u64) / torch.linalg.vector_norm(u64))
+        mvm = sum(i["matvecs"] for i in infos_m)
+        mixed = {
+            "matvecs_per_s": mvm / wall_m,
+            "ms_per_step": wall_m / a.steps * 1e3,
+            "time_to_tol_s": t_solvemx,
+            "inner_iterations": solvemx["iterations"],
+            "refinements": solvemx["refinements"],
+            "matvecs_c64": solvemx["matvecs_c64"],
+            "matvecs": solvemx["matvecs"],
+            "rel_res_true": solvemx["rel_res_true"],
+            "rel_diff_vs_fp64_solution": diff,
+            "speedup_time_to_tol_vs_fp64": t_solve64 / t_solvemx,
+            "kernel_ms": {kk: round(v[0], 5) for kk, v in profmx.items()},
+        }
+        log(f"[bench] mixed: time-to-{a.tol:g} {t_solvemx * 1e3:.2f} ms vs fp64 {t_solve64 * 1e3:.2f} ms")
+
+    # ---- plain operator loop (per-matvec rate) ------------------------------
+    x = u0.clone()
+    y = torch.empty_like(x)
+    mv_rates = {}
+    mv_prof = {}
+    for prec, tag in ((ori.ORI_FP64, "c128"), (ori.ORI_MIXED, "c64")):
+        for _ in range(3):
+            ori.ori_matvec(ctx, x, y, ori.ORI_OP_SYMMETRIC, prec)
+        ori.ori_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.matvecs):
+            ori.ori_matvec(ctx, x, y, ori.ORI_OP_SYMMETRIC, prec)
+        torch.cuda.synchronize()
+        mv_rates[tag] = a.matvecs / (time.perf_counter() - t0)
+        mv_prof[tag] = ori.ori_profile_read(ctx)
+        ori.ori_profile_enable(ctx, False)
+    log(f"[bench] operator loop: {mv_rates}")
+
+    # ---- roofline of the dominant kernel of the FP64 step --------------------
+    passes = ["f1.c128", "f2.c128", "zpass.c128", "i2.c128", "i1.c128", "update.c128"]
+    tot = {kk: prof64[kk][0] * prof64[kk][1] for kk in passes if kk in prof64}
+    dom = max(tot, key=tot.get)
+    dom_kind = dom.split(".")[0]
+    bytes64 = pass_bytes(n, 16)
+    avg_ms = prof64[dom][0]
+    achieved = bytes64[dom_kind] / (avg_ms * 1e-3) / 1e9
+    traffic = read_traffic(dom_kind + "_c128", n)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": bytes64[dom_kind], "avg_launch_ms": round(avg_ms, 5),
+                "launches": prof64[dom][1]}
+    # whole COCG iteration: algorithmic bytes / measured time of its kernels
+    it_bytes = sum(bytes64[kk] for kk in ("f1", "f2", "zpass", "i2", "i1", "update"))
+    it_ms = sum(prof64[f"{kk}.c128"][0] for kk in ("f1", "f2", "zpass", "i2", "i1", "update"))
+    log(f"[bench] dominant {dom}: {avg_ms:.4f} ms, {achieved:.0f} GB/s; iteration kernels {it_ms:.3f} ms")
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same operator --
+    cpu = None
+    if not a.no_cpu_baseline:
+        xs = x.cpu().numpy()
+        ori.ori_matvec(ctx, x, y, ori.ORI_OP_SYSTEM, ori.ORI_FP64)
+        yg = (y - x).cpu().numpy()
+        rows, vals, dt, rate = cpu_baseline(case, a.cpu_budget, xs)
+        err = float(np.linalg.norm(yg[rows] - vals) / np.linalg.norm(vals))
+        cpu = {"value": rate, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(rows)} dense rows of G0 D x at n={n} (P={P}) in {dt:.1f}s, "
+                         f"scaled to full matvecs/s",
+               "gpu_vs_oracle_rel_err_on_sample": err}
+        log(f"[bench] cpu oracle: {len(rows)} rows in {dt:.1f}s -> {rate:.3e} matvecs/s; GPU err {err:.2e}")
+
+    if a.calib_copy_mib > 0:
+        src = torch.empty(a.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    ctx.close()
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"ori_red_n{n}_k{k:g}", "n": n, "unknowns": P, "padded_grid": 2 * n,
+                   "k": k, "h": "(-1+0.5i)(1+0.1 xi), xi~U[-1,1]", "N": 1, "u0": "plane wave, random alpha",
+                   "seed": {256: 5, 128: 1, 512: 4}.get(n, 5), "tol": a.tol,
+                   "step": "ori_load (coefficients + kernel spectrum) + ori_solve complex128 COCG"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64": {"time_to_tol_s": t_solve64, "iterations": solve64["iterations"], "matvecs": solve64["matvecs"],
+                 "rel_res_recursive": solve64["rel_res_recursive"], "rel_res_true": solve64["rel_res_true"],
+                 "event_s_per_step": ev_s / a.steps,
+                 "iteration_kernel_ms": round(it_ms, 4),
+                 "iteration_model_gbs": round(it_bytes / (it_ms * 1e-3) / 1e9, 1),
+                 "kernel_ms": {kk: round(v[0], 5) for kk, v in prof64.items()}},
+        "mixed": mixed,
+        "matvec_only": {"per_s": {kk: round(v, 2) for kk, v in mv_rates.items()},
+                        "kernel_ms": {t: {kk: round(v[0], 5) for kk, v in p.items()} for t, p in mv_prof.items()}},
+        "kernel_sources_sha": kernel_sources_sha(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

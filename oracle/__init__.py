@@ -32,6 +32,8 @@ from .ori_oracle import (  # noqa: F401
     gauss_solve,
     cocg,
     solve_symmetrized_cocg,
+    objective,
+    adjoint_gradient_dense,
 )
 from .section3 import (  # noqa: F401
     mirror_pad_axis,

@@ -271,3 +271,34 @@ def solve_symmetrized_cocg(points, k, D, u0, tol=1e-10, maxiter=1000):
     w, hist = cocg(apply, S * u0, tol=tol, maxiter=maxiter)
     u = u0 - G0 @ (S * w)
     return u, hist
+
+
+# ---------------------------------------------------------------------------
+# adjoint gradient of J = sum |u - t|^2 with respect to h (material design)
+# ---------------------------------------------------------------------------
+def objective(u, t):
+    """J = sum_j |u_j - t_j|^2."""
+    e = np.asarray(u) - np.asarray(t)
+    return float(np.sum(e.real ** 2 + e.imag ** 2))
+
+
+def adjoint_gradient_dense(points, k, h, N, u0, t, n, side=1.0):
+    """J and g with dJ = Re sum_p g_p dh_p, by the adjoint of eq. 2.19.
+
+    A u = u0, A = I + G0 diag(c h), c_p = 4 pi N_p |Delta_p|.  Differentiating,
+    A du = -G0 diag(c dh) u, so with A^T lam = conj(u - t) (A^T = I + D G0):
+        dJ = 2 Re conj(u - t)^T du = Re sum_p g_p dh_p,
+        g_p = -2 c_p u_p (G0 lam)_p.
+    Hence dJ/dRe h_p = Re g_p and dJ/dIm h_p = -Im g_p.  Dense LU for both solves.
+    """
+    h = np.asarray(h, dtype=np.complex128)
+    c = coupling(np.ones_like(h), N, n, side).real     # 4 pi N |Delta|
+    D = c * h
+    G0 = green_matrix(points, k)
+    A = G0 * D[None, :]
+    A[np.diag_indices_from(A)] += 1.0
+    u = solve_direct(A, u0)
+    e = u - np.asarray(t)
+    lam = solve_direct(A.T, np.conj(e))
+    g = -2.0 * c * u * (G0 @ lam)
+    return objective(u, t), g, u

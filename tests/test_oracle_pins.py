@@ -282,3 +282,36 @@ def test_workload_generator_is_seeded():
     assert _rel(a["u0"], np.exp(1j * 5.0 * pts @ a["alpha"])) <= 1e-14
     d = workloads.fibonacci_directions(32)
     assert np.allclose(np.linalg.norm(d, axis=1), 1.0)
+
+
+# --- adjoint gradient ------------------------------------------------------------
+def test_adjoint_gradient_matches_central_differences():
+    # the definition of the derivative: central differences of J computed by
+    # dense LU, for the real and the imaginary part of h_p
+    n, k = 3, 4.0
+    pts, h, N, u0 = _varied_case(n, k, seed=21)
+    rng = np.random.default_rng(3)
+    t = u0 * (1 + 0.2 * rng.standard_normal(n ** 3))
+    J, g, _ = O.adjoint_gradient_dense(pts, k, h, N, u0, t, n)
+
+    def Jof(hh):
+        D = O.coupling(hh, N, n)
+        return O.objective(O.solve_direct(O.system_matrix(pts, k, D), u0), t)
+
+    assert abs(Jof(h) - J) <= 1e-13 * J
+    eps = 1e-6
+    for p in (0, 5, 13, 26):
+        for direction, part in ((1.0, g[p].real), (1j, -g[p].imag)):
+            hp, hm = h.copy(), h.copy()
+            hp[p] += eps * direction
+            hm[p] -= eps * direction
+            fd = (Jof(hp) - Jof(hm)) / (2 * eps)
+            assert abs(fd - part) <= 1e-6 * (abs(part) + 1e-3 * np.max(np.abs(g)))
+    # a wrong adjoint (A instead of A^T) gives a different gradient
+    D = O.coupling(h, N, n)
+    A = O.system_matrix(pts, k, D)
+    u = O.solve_direct(A, u0)
+    lam_wrong = O.solve_direct(A, np.conj(u - t))
+    c = O.coupling(np.ones(n ** 3), N, n).real
+    g_wrong = -2 * c * u * (O.green_matrix(pts, k) @ lam_wrong)
+    assert np.linalg.norm(g_wrong - g) > 1e-3 * np.linalg.norm(g)
