@@ -107,17 +107,23 @@ typedef struct {
  * no x0, inner_tol 1e-5, max_outer 10, true_residual 1. */
 void ori_default_opts(ori_solve_opts* opts);
 
-/* Device bytes that ori_create would allocate for this grid and provision
- * mask (host-only arithmetic; no device call).  Returns ORI_ERR_INVALID_ARG /
- * ORI_ERR_UNSUPPORTED for a bad grid. */
-ori_status ori_workspace_bytes(const ori_grid* g, int32_t provision, int64_t* bytes);
+/* Device bytes that ori_create would allocate for this grid, batch size and
+ * provision mask (host-only arithmetic; no device call).  Returns
+ * ORI_ERR_INVALID_ARG / ORI_ERR_UNSUPPORTED for a bad grid or batch. */
+ori_status ori_workspace_bytes(const ori_grid* g, int32_t nrhs, int32_t provision, int64_t* bytes);
 
-/* Allocate a context and its workspaces for grid g (a1-a2 buffers, the FFT
- * arena, the COCG vectors).  provision: ORI_PROVISION_* mask (FP64 is always
+/* Allocate a context and its workspaces for grid g and a batch of nrhs
+ * right-hand sides (1 <= nrhs <= 1024) that share one operator (same k, h,
+ * N) and differ in the incident field: the coefficient and spectrum
+ * buffers, the FFT work arrays and the COCG vectors of every right-hand side.
+ * Every per-right-hand-side array of the other calls is then [nrhs][P]
+ * (right-hand side i at offset i*P); each product and COCG step runs all of
+ * them in the same launches, and the kernel spectrum is read once per pass
+ * for the whole batch.  provision: ORI_PROVISION_* mask (FP64 is always
  * provisioned).  mem_limit_bytes > 0 caps the workspace: above it the call
  * returns ORI_ERR_OUT_OF_MEMORY without touching the device.  stream: a
  * hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL. */
-ori_status ori_create(const ori_grid* g, int32_t provision, int64_t mem_limit_bytes,
+ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_t mem_limit_bytes,
                       void* stream, ori_ctx* out);
 
 /* Compute the coefficients and the kernel spectrum for wave number k > 0
@@ -126,23 +132,53 @@ ori_status ori_create(const ori_grid* g, int32_t provision, int64_t mem_limit_by
  *   h  : device complex128[P], boundary impedance function h(x_p) (eq. 2.19)
  *   N  : device float64[P], distribution density N(x_p) >= 0 (eq. 2.17);
  *        NULL means N = 1
- *   u0 : device complex128[P], incident field u0(x_p) (eq. 2.4 or any field)
+ *   u0 : device complex128[nrhs][P], incident fields u0(x_p) (eq. 2.4 or any
+ *        field), one per right-hand side
  * NaN/Inf anywhere or N < 0 gives ORI_ERR_INVALID_ARG.  May be called again
  * on the same context with new data (no reallocation). */
 ori_status ori_load(ori_ctx ctx, double k, const void* h, const double* N, const void* u0);
 
-/* ori_create(g, FP64|MIXED, 0, stream, out) followed by ori_load. */
+/* ori_create(g, 1, FP64|MIXED, 0, stream, out) followed by ori_load. */
 ori_status ori_setup(const ori_grid* g, double k, const void* h, const double* N,
                      const void* u0, void* stream, ori_ctx* out);
 
-/* Solve eq. 2.19 for u (device complex128[P]).  COCG runs on the complex
- * symmetric form (I + S G0 S) w = S u0 and returns u = u0 - G0 S w.
- * opts NULL: defaults.  info (host, may be NULL) is filled on every return
- * that reached the device.  On ORI_ERR_NOT_CONVERGED / ORI_ERR_BREAKDOWN u
- * holds the solution recovered from the last iterate. */
+/* Solve eq. 2.19 for u (device complex128[nrhs][P]).  COCG runs on the
+ * complex symmetric form (I + S G0 S) w = S u0 and returns u = u0 - G0 S w.
+ * A batch runs in lockstep; a right-hand side that has converged stays
+ * frozen while the others continue.  opts NULL: defaults.  info (host, may
+ * be NULL) receives the worst over the batch (max iterations, max
+ * residuals); ori_batch_info gives each right-hand side.  On
+ * ORI_ERR_NOT_CONVERGED / ORI_ERR_BREAKDOWN (any right-hand side) u holds the
+ * solutions recovered from the last iterates. */
 ori_status ori_solve(ori_ctx ctx, const ori_solve_opts* opts, void* u, ori_solve_info* info);
 
-/* y = op(x) with the FFT operator (device complex128[P] each; x != y).
+/* Statistics of right-hand side i of the last ori_solve on ctx. */
+ori_status ori_batch_info(ori_ctx ctx, int32_t i, ori_solve_info* info);
+
+/* Adjoint of eq. 2.19 for material design.  With u the solution (from
+ * ori_solve on this context) and f a device complex128[P] vector, solve
+ * A^T lam = f, A^T = I + D G0 (same complex-symmetric COCG, division free:
+ * lam = f - S z with (I + S G0 S) z = S G0 f), and return
+ *     g_p = -c_p u_p (G0 lam)_p,    c_p = 4 pi N_p |Delta_p|,
+ * so that a real functional L(u) with dL = Re sum_j f_j du_j changes by
+ * dL = Re sum_p g_p dh_p  (dL/dRe h_p = Re g_p, dL/dIm h_p = -Im g_p) and
+ * by dL = Re sum_j lam_j du0_j.  For PyTorch's complex gradient convention,
+ * pass f = conj(grad_u); then grad_h = conj(g) and grad_u0 = conj(lam).
+ * g, lam: device complex128[P] outputs, either may be NULL (not both).
+ * opts: tolerance / precision of the adjoint solve (use_x0 is ignored).
+ * Needs a context with nrhs = 1 (else ORI_ERR_UNSUPPORTED). */
+ori_status ori_adjoint(ori_ctx ctx, const ori_solve_opts* opts, const void* u, const void* f, void* g, void* lam,
+                       ori_solve_info* info);
+
+/* Objective J = sum_j |u_j - t_j|^2 (t = u_target, device complex128[P]):
+ * solves eq. 2.19 into u, writes J (host double) and dJdh (device
+ * complex128[P]) with dJ = Re sum_p dJdh_p dh_p, i.e. dJ/dRe h_p = Re dJdh_p
+ * and dJ/dIm h_p = -Im dJdh_p (the adjoint above with f = 2 conj(u - t)).
+ * info sums both solves. */
+ori_status ori_gradient(ori_ctx ctx, const ori_solve_opts* opts, const void* u_target, void* u, double* J,
+                        void* dJdh, ori_solve_info* info);
+
+/* y = op(x) with the FFT operator (device complex128[nrhs][P] each).
  * precision ORI_MIXED runs the FFT stages in complex64 (inputs and outputs
  * stay complex128).  Used by tests and the benchmark. */
 ori_status ori_matvec(ori_ctx ctx, int32_t op, int32_t precision, const void* x, void* y);

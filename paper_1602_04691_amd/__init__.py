@@ -15,12 +15,13 @@ import os
 __all__ = [
     "OriError", "lib", "Grid", "SolveOpts", "SolveInfo", "Context",
     "ori_setup", "ori_create", "ori_load", "ori_solve", "ori_matvec", "ori_destroy",
+    "ori_adjoint", "ori_gradient", "OriSolve", "ori_batch_info",
     "ori_workspace_bytes", "ori_default_opts", "ori_profile_enable", "ori_profile_read",
     "ori_last_error", "ori_version",
     "ORI_OK", "ORI_ERR_INVALID_ARG", "ORI_ERR_OUT_OF_MEMORY", "ORI_ERR_DEVICE",
     "ORI_ERR_BREAKDOWN", "ORI_ERR_NOT_CONVERGED", "ORI_ERR_UNSUPPORTED",
     "ORI_FP64", "ORI_MIXED", "ORI_OP_SYSTEM", "ORI_OP_SYMMETRIC", "ORI_OP_GREEN",
-    "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve",
+    "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve", "solve_many",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libori.so")
@@ -80,12 +81,16 @@ def lib():
         sig = {
             "ori_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
             "ori_version": (ctypes.c_char_p, []),
-            "ori_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Grid), I32, ctypes.POINTER(I64)]),
-            "ori_create": (ctypes.c_int, [ctypes.POINTER(Grid), I32, I64, P, ctypes.POINTER(P)]),
+            "ori_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Grid), I32, I32, ctypes.POINTER(I64)]),
+            "ori_create": (ctypes.c_int, [ctypes.POINTER(Grid), I32, I32, I64, P, ctypes.POINTER(P)]),
+            "ori_batch_info": (ctypes.c_int, [P, I32, ctypes.POINTER(SolveInfo)]),
             "ori_load": (ctypes.c_int, [P, D, P, P, P]),
             "ori_setup": (ctypes.c_int, [ctypes.POINTER(Grid), D, P, P, P, P, ctypes.POINTER(P)]),
             "ori_solve": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo)]),
             "ori_matvec": (ctypes.c_int, [P, I32, I32, P, P]),
+            "ori_adjoint": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), P, P, P, P, ctypes.POINTER(SolveInfo)]),
+            "ori_gradient": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), P, P, ctypes.POINTER(D), P,
+                                            ctypes.POINTER(SolveInfo)]),
             "ori_profile_enable": (ctypes.c_int, [P, I32]),
             "ori_profile_read": (ctypes.c_int, [P, I32, ctypes.POINTER(ctypes.c_char_p),
                                                 ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(I32)]),
@@ -150,12 +155,13 @@ def _stream(stream):
 
 
 class Context:
-    """An ori_ctx plus the grid it was made for."""
+    """An ori_ctx plus the grid and batch size it was made for."""
 
-    def __init__(self, handle, n, stream):
+    def __init__(self, handle, n, stream, nrhs=1):
         self.handle = handle
         self.n = n
         self.P = n ** 3
+        self.nrhs = nrhs
         self.stream = stream
 
     def close(self):
@@ -182,26 +188,28 @@ def ori_default_opts():
     return o
 
 
-def ori_workspace_bytes(n, provision=ORI_PROVISION_FP64 | ORI_PROVISION_MIXED, side=1.0):
+def ori_workspace_bytes(n, provision=ORI_PROVISION_FP64 | ORI_PROVISION_MIXED, side=1.0, nrhs=1):
     b = ctypes.c_int64()
-    _check(lib().ori_workspace_bytes(ctypes.byref(_grid(n, side)), provision, ctypes.byref(b)))
+    _check(lib().ori_workspace_bytes(ctypes.byref(_grid(n, side)), int(nrhs), provision, ctypes.byref(b)))
     return b.value
 
 
 def ori_create(n, side=1.0, origin=(0.0, 0.0, 0.0), cell_offset=0.5,
-               provision=ORI_PROVISION_FP64 | ORI_PROVISION_MIXED, mem_limit_bytes=0, stream=None):
+               provision=ORI_PROVISION_FP64 | ORI_PROVISION_MIXED, mem_limit_bytes=0, stream=None, nrhs=1):
     import torch
     h = ctypes.c_void_p()
     st = _stream(stream)
-    _check(lib().ori_create(ctypes.byref(_grid(n, side, origin, cell_offset)), provision,
+    _check(lib().ori_create(ctypes.byref(_grid(n, side, origin, cell_offset)), int(nrhs), provision,
                             int(mem_limit_bytes), st, ctypes.byref(h)))
-    return Context(h, int(n), stream if stream is not None else torch.cuda.current_stream())
+    return Context(h, int(n), stream if stream is not None else torch.cuda.current_stream(), int(nrhs))
 
 
 def ori_load(ctx, k, h, N, u0):
+    """u0: complex128 CUDA tensor of nrhs * n^3 entries (batch-major)."""
     import torch
     _check(lib().ori_load(ctx.handle, float(k), _dev(h, torch.complex128, ctx.P, "h"),
-                          _dev(N, torch.float64, ctx.P, "N"), _dev(u0, torch.complex128, ctx.P, "u0")), ctx)
+                          _dev(N, torch.float64, ctx.P, "N"),
+                          _dev(u0, torch.complex128, ctx.nrhs * ctx.P, "u0")), ctx)
 
 
 def ori_setup(n, k, h, N, u0, side=1.0, origin=(0.0, 0.0, 0.0), cell_offset=0.5, stream=None):
@@ -215,24 +223,65 @@ def ori_setup(n, k, h, N, u0, side=1.0, origin=(0.0, 0.0, 0.0), cell_offset=0.5,
     return Context(hdl, int(n), stream if stream is not None else torch.cuda.current_stream())
 
 
+def _opts(tol=1e-10, max_iter=1000, precision=ORI_FP64, check_every=1, use_x0=False, inner_tol=1e-5,
+          max_outer=10, true_residual=True):
+    return SolveOpts(float(tol), int(max_iter), int(precision), int(check_every), int(bool(use_x0)),
+                     float(inner_tol), int(max_outer), int(bool(true_residual)))
+
+
 def ori_solve(ctx, u, tol=1e-10, max_iter=1000, precision=ORI_FP64, check_every=1, use_x0=False,
               inner_tol=1e-5, max_outer=10, true_residual=True, raise_on_error=True):
     """Solve into u (complex128 CUDA tensor, n^3).  Returns (status, info dict)."""
     import torch
-    o = SolveOpts(float(tol), int(max_iter), int(precision), int(check_every), int(bool(use_x0)),
-                  float(inner_tol), int(max_outer), int(bool(true_residual)))
+    o = _opts(tol, max_iter, precision, check_every, use_x0, inner_tol, max_outer, true_residual)
     info = SolveInfo()
-    st = lib().ori_solve(ctx.handle, ctypes.byref(o), _dev(u, torch.complex128, ctx.P, "u"), ctypes.byref(info))
+    st = lib().ori_solve(ctx.handle, ctypes.byref(o), _dev(u, torch.complex128, ctx.nrhs * ctx.P, "u"),
+                         ctypes.byref(info))
     d = info.as_dict()
     if raise_on_error:
         _check(st, ctx, d)
     return st, d
 
 
+def ori_adjoint(ctx, u, f, g=None, lam=None, raise_on_error=True, **opts):
+    """A^T lam = f; g = -c u (G0 lam).  Fills g and/or lam (CUDA tensors).  Returns (status, info)."""
+    import torch
+    o = _opts(**opts)
+    info = SolveInfo()
+    st = lib().ori_adjoint(ctx.handle, ctypes.byref(o), _dev(u, torch.complex128, ctx.P, "u"),
+                           _dev(f, torch.complex128, ctx.P, "f"), _dev(g, torch.complex128, ctx.P, "g"),
+                           _dev(lam, torch.complex128, ctx.P, "lam"), ctypes.byref(info))
+    d = info.as_dict()
+    if raise_on_error:
+        _check(st, ctx, d)
+    return st, d
+
+
+def ori_gradient(ctx, u_target, u, dJdh, raise_on_error=True, **opts):
+    """J = sum |u - t|^2 and dJdh (dJ = Re sum dJdh dh).  Returns (status, J, info)."""
+    import torch
+    o = _opts(**opts)
+    info = SolveInfo()
+    J = ctypes.c_double(float("nan"))
+    st = lib().ori_gradient(ctx.handle, ctypes.byref(o), _dev(u_target, torch.complex128, ctx.P, "u_target"),
+                            _dev(u, torch.complex128, ctx.P, "u"), ctypes.byref(J),
+                            _dev(dJdh, torch.complex128, ctx.P, "dJdh"), ctypes.byref(info))
+    d = info.as_dict()
+    if raise_on_error:
+        _check(st, ctx, d)
+    return st, J.value, d
+
+
 def ori_matvec(ctx, x, y, op=ORI_OP_SYSTEM, precision=ORI_FP64):
     import torch
-    _check(lib().ori_matvec(ctx.handle, int(op), int(precision), _dev(x, torch.complex128, ctx.P, "x"),
-                            _dev(y, torch.complex128, ctx.P, "y")), ctx)
+    _check(lib().ori_matvec(ctx.handle, int(op), int(precision), _dev(x, torch.complex128, ctx.nrhs * ctx.P, "x"),
+                            _dev(y, torch.complex128, ctx.nrhs * ctx.P, "y")), ctx)
+
+
+def ori_batch_info(ctx, i):
+    info = SolveInfo()
+    _check(lib().ori_batch_info(ctx.handle, int(i), ctypes.byref(info)), ctx)
+    return info.as_dict()
 
 
 def ori_destroy(ctx):
@@ -259,3 +308,74 @@ def solve(n, k, h, N, u0, side=1.0, origin=(0.0, 0.0, 0.0), cell_offset=0.5, **o
         u = torch.empty(int(n) ** 3, dtype=torch.complex128, device=h.device)
         _, info = ori_solve(ctx, u, **opts)
     return u, info
+
+
+def _autograd_function():
+    import torch
+
+    class _OriSolve(torch.autograd.Function):
+        """u = solution of eq. 2.19 for impedance h (and incident field u0).
+
+        Forward and backward both run in libori.so: the backward is one
+        adjoint COCG solve with the same operator (ori_adjoint).
+        """
+
+        @staticmethod
+        def forward(fctx, h, u0, N, n, k, side, opts):
+            ctx = ori_setup(n, k, h.detach().contiguous(), None if N is None else N.detach().contiguous(),
+                            u0.detach().contiguous(), side=side)
+            u = torch.empty(int(n) ** 3, dtype=torch.complex128, device=h.device)
+            ori_solve(ctx, u, **opts)
+            fctx.ori = ctx
+            fctx.opts = opts
+            fctx.save_for_backward(u)
+            return u
+
+        @staticmethod
+        def backward(fctx, grad_u):
+            (u,) = fctx.saved_tensors
+            ctx = fctx.ori
+            f = torch.conj(grad_u).resolve_conj().contiguous()
+            g = torch.empty_like(u) if fctx.needs_input_grad[0] else None
+            lam = torch.empty_like(u) if fctx.needs_input_grad[1] else None
+            if g is not None or lam is not None:
+                o = {k: v for k, v in fctx.opts.items() if k != "use_x0"}
+                ori_adjoint(ctx, u, f, g=g, lam=lam, **o)
+            ctx.close()
+            return (None if g is None else torch.conj(g), None if lam is None else torch.conj(lam),
+                    None, None, None, None, None)
+
+    return _OriSolve
+
+
+_ORI_SOLVE_FN = None
+
+
+def OriSolve(h, u0, n, k, N=None, side=1.0, **opts):
+    """Differentiable solve: torch.autograd.Function applied to (h, u0)."""
+    global _ORI_SOLVE_FN
+    if _ORI_SOLVE_FN is None:
+        _ORI_SOLVE_FN = _autograd_function()
+    return _ORI_SOLVE_FN.apply(h, u0, N, int(n), float(k), float(side), dict(opts))
+
+
+def solve_many(problems, **opts):
+    """Independent problems of any sizes, each on its own context and stream,
+    solved concurrently from a thread pool (the library call releases the
+    GIL).  problems: dicts with n, k, h, N, u0 (CUDA tensors).  Returns a list
+    of (u, info) in order."""
+    import concurrent.futures
+    import torch
+
+    def one(p):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            with ori_setup(p["n"], p["k"], p["h"], p.get("N"), p["u0"], side=p.get("side", 1.0), stream=s) as ctx:
+                u = torch.empty(int(p["n"]) ** 3, dtype=torch.complex128, device=p["h"].device)
+                _, info = ori_solve(ctx, u, **opts)
+        s.synchronize()
+        return u, info
+
+    torch.cuda.synchronize()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, len(problems))) as ex:
+        return list(ex.map(one, problems))

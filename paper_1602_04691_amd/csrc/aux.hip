@@ -1,6 +1,8 @@
-// Elementwise and reduction kernels: coefficients (eq. 2.19), the Green's
-// table for the spectrum (eqs. 2.6a, 3.3.7 and the padding of Section 3), and
-// the COCG vector updates with their bilinear reductions.
+// Elementwise and reduction kernels: coefficients of eq. 2.19, the
+// right-hand sides, and the COCG vector updates with their bilinear
+// reductions.  Reductions are two-stage and deterministic: fixed-order
+// per-workgroup partials, then one workgroup per right-hand side
+// (k_finalize) in a fixed order.
 #include "cx.h"
 #include "kernels.h"
 
@@ -13,7 +15,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Deterministic workgroup sum of 4 values (kRedThreads threads).
+// Deterministic workgroup sum of 4 values (kRedThreads threads); thread 0
+// writes out[0..3].
 __device__ __forceinline__ void block_sum4(double (&v)[4], double* out) {
   __shared__ double sh[(kRedThreads / 64) * 4];
 #pragma unroll
@@ -48,76 +51,60 @@ __device__ __forceinline__ cxd csqrt(cxd z) {
 
 __device__ __forceinline__ bool finite_cx(cxd z) { return isfinite(z.re) && isfinite(z.im); }
 
-// a1: D = 4 pi h N vol, S = sqrt(D), b = S u0
+// grid-stride loop over [0, P) within the right-hand side blockIdx.y
+#define ORI_RHS_LOOP(i)                                                                                \
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P;                 \
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+
+// a1, operator part: D = 4 pi h N vol, S = sqrt(D), c = 4 pi N vol
 __global__ void __launch_bounds__(kRedThreads)
-    k_coefficients(const cxd* __restrict__ h, const double* __restrict__ N, const cxd* __restrict__ u0,
-                   double vol, int64_t P, cxd* __restrict__ D, cxd* __restrict__ S, cxf* __restrict__ Sf,
-                   cxd* __restrict__ b, cxd* __restrict__ u0c, double* __restrict__ partials) {
+    k_coefficients(const cxd* __restrict__ h, const double* __restrict__ N, double vol, int64_t P,
+                   cxd* __restrict__ D, cxd* __restrict__ S, cxf* __restrict__ Sf, double* __restrict__ cN,
+                   double* __restrict__ partials) {
   constexpr double FOUR_PI = 12.566370614359172954;  // c_S for spheres
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P; i += stride) {
+  ORI_RHS_LOOP(i) {
     const cxd hv = h[i];
     const double nv = N ? N[i] : 1.0;
-    const cxd uv = u0[i];
-    const bool bad = !finite_cx(hv) || !isfinite(nv) || nv < 0.0 || !finite_cx(uv);
-    const cxd d = bad ? cxd{0.0, 0.0} : scale(hv, FOUR_PI * nv * vol);
+    const bool bad = !finite_cx(hv) || !isfinite(nv) || nv < 0.0;
+    const double c = bad ? 0.0 : FOUR_PI * nv * vol;
+    const cxd d = scale(bad ? cxd{0.0, 0.0} : hv, c);
     const cxd s = csqrt(d);
-    const cxd bv = bad ? cxd{0.0, 0.0} : s * uv;
     D[i] = d;
     S[i] = s;
     if (Sf) Sf[i] = cvt<float>(s);
-    b[i] = bv;
-    u0c[i] = bad ? cxd{0.0, 0.0} : uv;
-    acc[0] += norm2(bv);
-    acc[1] += bad ? 0.0 : norm2(uv);
-    acc[2] += bad ? 1.0 : 0.0;
+    cN[i] = c;
+    acc[0] += bad ? 1.0 : 0.0;
   }
   block_sum4(acc, partials + 4 * static_cast<int64_t>(blockIdx.x));
 }
 
-// Green's table on the padded grid: c(m) = G(spacing |d(m)|) with the
-// wrapped offset d_i = m_i (m_i < n), m_i - L (m_i > n); zero at m = 0 (the
-// excluded self term) and where some m_i = n (never reached by |j - m| < n).
-__global__ void __launch_bounds__(256) k_embed(cxd* __restrict__ g, int L, double k, double spacing) {
-  const int n = L / 2;
-  const int64_t total = static_cast<int64_t>(L) * L * L;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-    const int m3 = static_cast<int>(idx % L);
-    const int m2 = static_cast<int>((idx / L) % L);
-    const int m1 = static_cast<int>(idx / (static_cast<int64_t>(L) * L));
-    cxd v{0.0, 0.0};
-    if (m1 != n && m2 != n && m3 != n && (m1 | m2 | m3) != 0) {
-      const double d1 = m1 < n ? m1 : m1 - L;
-      const double d2 = m2 < n ? m2 : m2 - L;
-      const double d3 = m3 < n ? m3 : m3 - L;
-      const double r = spacing * sqrt(d1 * d1 + d2 * d2 + d3 * d3);
-      double sn, cs;
-      sincos(k * r, &sn, &cs);
-      const double inv = 1.0 / (12.566370614359172954 * r);
-      v = cxd{cs * inv, sn * inv};
-    }
-    g[idx] = v;
-  }
-}
-
-__global__ void __launch_bounds__(256)
-    k_octant(const cxd* __restrict__ g, int L, double scale_, cxd* __restrict__ kh, cxf* __restrict__ khf) {
-  const int n = L / 2, kp = n + 1;
-  const int64_t total = static_cast<int64_t>(kp) * kp * kp;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-    const int64_t m3 = idx % kp, m2 = (idx / kp) % kp, m1 = idx / (static_cast<int64_t>(kp) * kp);
-    const cxd v = scale(g[(m1 * L + m2) * L + m3], scale_);
-    kh[idx] = v;
-    if (khf) khf[idx] = cvt<float>(v);
-  }
-}
-
-// Reduce nblk partial quadruples in a fixed order and update the scalars.
+// a1, right-hand sides: b = S u0 (one batch row per blockIdx.y)
 __global__ void __launch_bounds__(kRedThreads)
-    k_finalize(const double* __restrict__ part, int64_t nblk, ScalarBlock* sc, int32_t mode, double eps) {
+    k_rhs(const cxd* __restrict__ u0, const cxd* __restrict__ S, int64_t P, cxd* __restrict__ b,
+          cxd* __restrict__ u0c, double* __restrict__ partials) {
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  ORI_RHS_LOOP(i) {
+    const cxd uv = u0[off + i];
+    const bool bad = !finite_cx(uv);
+    const cxd bv = bad ? cxd{0.0, 0.0} : S[i] * uv;
+    b[off + i] = bv;
+    u0c[off + i] = bad ? cxd{0.0, 0.0} : uv;
+    acc[0] += norm2(bv);
+    acc[1] += bad ? 0.0 : norm2(uv);
+    acc[2] += bad ? 1.0 : 0.0;
+  }
+  block_sum4(acc, partials + 4 * (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x));
+}
+
+// One workgroup per right-hand side: reduce its nblk partial quadruples in a
+// fixed order and update its scalars.
+__global__ void __launch_bounds__(kRedThreads)
+    k_finalize(const double* __restrict__ partials, int64_t nblk, ScalarBlock* scb, int32_t mode, double eps,
+               double tol2, int32_t tol2_of_bb) {
+  const double* part = partials + 4 * nblk * blockIdx.x;
+  ScalarBlock* sc = scb + blockIdx.x;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t i = threadIdx.x; i < nblk; i += kRedThreads) {
 #pragma unroll
@@ -134,14 +121,23 @@ __global__ void __launch_bounds__(kRedThreads)
       sc->aux = s1;
       sc->flags = s2 > 0.0 ? FLAG_BAD_INPUT : 0;
       break;
+    case FIN_BAD:
+      sc->flags = s0 > 0.0 ? FLAG_BAD_INPUT : 0;
+      break;
     case FIN_INIT: {
       sc->rho_re = s0;
       sc->rho_im = s1;
       sc->rr = s2;
+      sc->rr0 = s2;
       sc->beta_re = 0.0;
       sc->beta_im = 0.0;
+      sc->alpha_re = 0.0;
+      sc->alpha_im = 0.0;
+      sc->iters = 0;
+      sc->rr_target = tol2 * (tol2_of_bb ? sc->bb : s2);
       int f = 0;
       if (s2 == 0.0) f |= FLAG_ZERO_RESIDUAL;
+      else if (s2 <= sc->rr_target) f |= FLAG_CONVERGED;
       else if (hypot(s0, s1) <= eps * s2) f |= FLAG_BREAKDOWN_RHO;
       sc->flags = f;
       break;
@@ -152,16 +148,15 @@ __global__ void __launch_bounds__(kRedThreads)
       sc->pp = s3;
       sc->qq = s2;
       const double mag = hypot(s0, s1);
-      if (s3 == 0.0 || (sc->flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU | FLAG_ZERO_RESIDUAL))) {
-        sc->alpha_re = 0.0;  // nothing left to do (r = p = 0) or already broken down
+      if (s3 == 0.0 || (sc->flags & FLAG_DONE)) {
+        sc->alpha_re = 0.0;  // converged, r = p = 0, or broken down: nothing moves
         sc->alpha_im = 0.0;
       } else if (mag <= eps * sqrt(s2 * s3)) {
         sc->flags |= FLAG_BREAKDOWN_MU;
         sc->alpha_re = 0.0;
         sc->alpha_im = 0.0;
       } else {
-        // alpha = rho / mu
-        const double den = s0 * s0 + s1 * s1;
+        const double den = s0 * s0 + s1 * s1;  // alpha = rho / mu
         sc->alpha_re = (sc->rho_re * s0 + sc->rho_im * s1) / den;
         sc->alpha_im = (sc->rho_im * s0 - sc->rho_re * s1) / den;
       }
@@ -169,21 +164,22 @@ __global__ void __launch_bounds__(kRedThreads)
     }
     case FIN_RHO: {
       int f = sc->flags;
-      if (f & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU)) {
+      if (f & FLAG_DONE) {  // frozen
         sc->beta_re = 0.0;
         sc->beta_im = 0.0;
         break;
       }
+      sc->iters += 1;
       const double ro = sc->rho_re, io = sc->rho_im;
       sc->rr = s2;
+      sc->beta_re = 0.0;
+      sc->beta_im = 0.0;
       if (s2 == 0.0) {
         f |= FLAG_ZERO_RESIDUAL;
-        sc->beta_re = 0.0;
-        sc->beta_im = 0.0;
+      } else if (s2 <= sc->rr_target) {
+        f |= FLAG_CONVERGED;
       } else if (hypot(s0, s1) <= eps * s2) {
         f |= FLAG_BREAKDOWN_RHO;
-        sc->beta_re = 0.0;
-        sc->beta_im = 0.0;
       } else {
         const double den = ro * ro + io * io;  // beta = rho' / rho
         sc->beta_re = (s0 * ro + s1 * io) / den;
@@ -203,67 +199,89 @@ __global__ void __launch_bounds__(kRedThreads)
 template <typename V>
 __global__ void __launch_bounds__(kRedThreads)
     k_update(cx<V>* __restrict__ x, const cx<V>* __restrict__ p, cx<V>* __restrict__ r,
-             const cx<V>* __restrict__ q, int64_t P, const ScalarBlock* __restrict__ sc,
+             const cx<V>* __restrict__ q, int64_t P, const ScalarBlock* __restrict__ scb,
              double* __restrict__ partials) {
+  const ScalarBlock* sc = scb + blockIdx.y;
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
   const cxd al = {sc->alpha_re, sc->alpha_im};
+  const bool moving = al.re != 0.0 || al.im != 0.0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P; i += stride) {
-    const cxd pv = cvt<double>(p[i]);
-    const cxd xv = cvt<double>(x[i]) + al * pv;
-    const cxd rv = cvt<double>(r[i]) - al * cvt<double>(q[i]);
-    x[i] = cvt<V>(xv);
-    const cx<V> rs = cvt<V>(rv);
-    r[i] = rs;
-    const cxd rd = cvt<double>(rs);  // reduce what was stored
+  ORI_RHS_LOOP(i) {
+    cxd rd;
+    if (moving) {
+      const cxd pv = cvt<double>(p[off + i]);
+      x[off + i] = cvt<V>(cvt<double>(x[off + i]) + al * pv);
+      const cx<V> rs = cvt<V>(cvt<double>(r[off + i]) - al * cvt<double>(q[off + i]));
+      r[off + i] = rs;
+      rd = cvt<double>(rs);  // reduce what was stored
+    } else {
+      rd = cvt<double>(r[off + i]);
+    }
     const cxd rr = rd * rd;
     acc[0] += rr.re;
     acc[1] += rr.im;
     acc[2] += norm2(rd);
   }
-  block_sum4(acc, partials + 4 * static_cast<int64_t>(blockIdx.x));
+  block_sum4(acc, partials + 4 * (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x));
 }
 
 template <typename V>
 __global__ void __launch_bounds__(kRedThreads)
-    k_init(const cxd* __restrict__ b, double bscale, cx<V>* __restrict__ x, cx<V>* __restrict__ r, int64_t P,
-           double* __restrict__ partials) {
+    k_init(const cxd* __restrict__ b, const double* __restrict__ m, cx<V>* __restrict__ x, cx<V>* __restrict__ r,
+           int64_t P, double* __restrict__ partials) {
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+  double sc = 1.0;
+  if (m) sc = m[blockIdx.y] > 0.0 ? 1.0 / m[blockIdx.y] : 0.0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P; i += stride) {
-    const cx<V> rs = cvt<V>(scale(b[i], bscale));
-    r[i] = rs;
-    x[i] = cx<V>{};
+  ORI_RHS_LOOP(i) {
+    const cx<V> rs = cvt<V>(scale(b[off + i], sc));
+    r[off + i] = rs;
+    x[off + i] = cx<V>{};
     const cxd rd = cvt<double>(rs);
     const cxd rr = rd * rd;
     acc[0] += rr.re;
     acc[1] += rr.im;
     acc[2] += norm2(rd);
   }
-  block_sum4(acc, partials + 4 * static_cast<int64_t>(blockIdx.x));
-}
-
-template <typename VO>
-__global__ void __launch_bounds__(256) k_scale_into(const cxd* __restrict__ x, double a, cx<VO>* __restrict__ y,
-                                                    int64_t P) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P; i += stride)
-    y[i] = cvt<VO>(scale(x[i], a));
+  block_sum4(acc, partials + 4 * (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x));
 }
 
 template <typename VI>
-__global__ void __launch_bounds__(256) k_axpy_d(double a, const cx<VI>* __restrict__ x, cxd* __restrict__ y,
-                                                int64_t P) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P; i += stride)
-    y[i] = y[i] + scale(cvt<double>(x[i]), a);
+__global__ void __launch_bounds__(256)
+    k_axpy_batch(const double* __restrict__ m, const cx<VI>* __restrict__ x, cxd* __restrict__ y, int64_t P) {
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+  const double a = m[blockIdx.y];
+  if (a == 0.0) return;
+  ORI_RHS_LOOP(i) y[off + i] = y[off + i] + scale(cvt<double>(x[off + i]), a);
 }
 
 __global__ void __launch_bounds__(256) k_mul(const cxd* __restrict__ s, const cxd* __restrict__ x,
                                              cxd* __restrict__ y, int64_t P) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P; i += stride)
-    y[i] = s[i] * x[i];
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+  ORI_RHS_LOOP(i) y[off + i] = s[i] * x[off + i];
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+    k_conj_diff(const cxd* __restrict__ u, const cxd* __restrict__ t, cxd* __restrict__ f, int64_t P,
+                double* __restrict__ partials) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  ORI_RHS_LOOP(i) {
+    const cxd e = u[i] - t[i];
+    f[i] = conj(e);
+    acc[2] += norm2(e);
+  }
+  block_sum4(acc, partials + 4 * static_cast<int64_t>(blockIdx.x));
+}
+
+__global__ void __launch_bounds__(256) k_gradient(const double* __restrict__ c, const cxd* __restrict__ u,
+                                                  const cxd* __restrict__ q, double alpha, cxd* __restrict__ g,
+                                                  int64_t P) {
+  ORI_RHS_LOOP(i) g[i] = scale(u[i] * q[i], alpha * c[i]);
+}
+
+__global__ void __launch_bounds__(256) k_sub_mul(const cxd* __restrict__ f, const cxd* __restrict__ s,
+                                                 const cxd* __restrict__ x, cxd* __restrict__ y, int64_t P) {
+  ORI_RHS_LOOP(i) y[i] = f[i] - s[i] * x[i];
 }
 
 unsigned grid_for(int64_t P, int threads, int64_t cap) {
@@ -273,81 +291,89 @@ unsigned grid_for(int64_t P, int threads, int64_t cap) {
   return static_cast<unsigned>(g);
 }
 
+dim3 red_grid(int64_t P, int64_t nrhs) {
+  return dim3(static_cast<unsigned>(red_blocks(P)), static_cast<unsigned>(nrhs));
+}
+
 }  // namespace
 
-hipError_t launch_coefficients(const void* h, const double* N, const void* u0, double vol, int64_t P, void* D,
-                               void* S, void* Sf, void* b, void* u0c, double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(k_coefficients, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const cxd*>(h), N,
-                     static_cast<const cxd*>(u0), vol, P, static_cast<cxd*>(D), static_cast<cxd*>(S),
-                     static_cast<cxf*>(Sf), static_cast<cxd*>(b), static_cast<cxd*>(u0c), partials);
+hipError_t launch_coefficients(const void* h, const double* N, double vol, int64_t P, void* D, void* S, void* Sf,
+                               double* cN, double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_coefficients, red_grid(P, 1), dim3(kRedThreads), 0, st, static_cast<const cxd*>(h), N, vol, P,
+                     static_cast<cxd*>(D), static_cast<cxd*>(S), static_cast<cxf*>(Sf), cN, partials);
   return hipGetLastError();
 }
 
-hipError_t launch_embed(void* grid, int L, double k, double spacing, hipStream_t st) {
-  const int64_t total = static_cast<int64_t>(L) * L * L;
-  hipLaunchKernelGGL(k_embed, dim3(grid_for(total, 256, 1 << 16)), dim3(256), 0, st, static_cast<cxd*>(grid), L, k,
-                     spacing);
+hipError_t launch_rhs(const void* u0, const void* S, int64_t P, int64_t nrhs, void* b, void* u0c, double* partials,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<const cxd*>(u0),
+                     static_cast<const cxd*>(S), P, static_cast<cxd*>(b), static_cast<cxd*>(u0c), partials);
   return hipGetLastError();
 }
 
-hipError_t launch_octant(const void* grid, int L, double scale_, void* kh, void* khf, hipStream_t st) {
-  const int64_t kp = L / 2 + 1;
-  hipLaunchKernelGGL(k_octant, dim3(grid_for(kp * kp * kp, 256, 1 << 16)), dim3(256), 0, st,
-                     static_cast<const cxd*>(grid), L, scale_, static_cast<cxd*>(kh), static_cast<cxf*>(khf));
+hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, ScalarBlock* sc, int32_t mode,
+                           double eps, double tol2, int32_t tol2_of_bb, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>(nrhs)), dim3(kRedThreads), 0, st, partials, nblk, sc,
+                     mode, eps, tol2, tol2_of_bb);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* partials, int64_t nblk, ScalarBlock* sc, int32_t mode, double eps,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, partials, nblk, sc, mode, eps);
-  return hipGetLastError();
-}
-
-hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* q, int64_t P, const ScalarBlock* sc,
-                         double* partials, hipStream_t st) {
+hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* q, int64_t P, int64_t nrhs,
+                         const ScalarBlock* sc, double* partials, hipStream_t st) {
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_update<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<cxd*>(x),
+    hipLaunchKernelGGL(k_update<double>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<cxd*>(x),
                        static_cast<const cxd*>(p), static_cast<cxd*>(r), static_cast<const cxd*>(q), P, sc, partials);
   else
-    hipLaunchKernelGGL(k_update<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<cxf*>(x),
+    hipLaunchKernelGGL(k_update<float>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<cxf*>(x),
                        static_cast<const cxf*>(p), static_cast<cxf*>(r), static_cast<const cxf*>(q), P, sc, partials);
   return hipGetLastError();
 }
 
-hipError_t launch_init(int prec, const void* b, double bscale, void* x, void* r, int64_t P, double* partials,
-                       hipStream_t st) {
+hipError_t launch_init(int prec, const void* b, const double* m, void* x, void* r, int64_t P, int64_t nrhs,
+                       double* partials, hipStream_t st) {
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_init<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const cxd*>(b), bscale,
+    hipLaunchKernelGGL(k_init<double>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<const cxd*>(b), m,
                        static_cast<cxd*>(x), static_cast<cxd*>(r), P, partials);
   else
-    hipLaunchKernelGGL(k_init<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const cxd*>(b), bscale,
+    hipLaunchKernelGGL(k_init<float>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<const cxd*>(b), m,
                        static_cast<cxf*>(x), static_cast<cxf*>(r), P, partials);
   return hipGetLastError();
 }
 
-hipError_t launch_scale_into(int prec_out, const void* x, double a, void* y, int64_t P, hipStream_t st) {
-  const dim3 g(grid_for(P, 256, 8192));
-  if (prec_out == PREC_F64)
-    hipLaunchKernelGGL(k_scale_into<double>, g, dim3(256), 0, st, static_cast<const cxd*>(x), a,
+hipError_t launch_axpy_batch(int prec_in, const double* m, const void* x, void* y, int64_t P, int64_t nrhs,
+                             hipStream_t st) {
+  const dim3 g(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs));
+  if (prec_in == PREC_F64)
+    hipLaunchKernelGGL(k_axpy_batch<double>, g, dim3(256), 0, st, m, static_cast<const cxd*>(x),
                        static_cast<cxd*>(y), P);
   else
-    hipLaunchKernelGGL(k_scale_into<float>, g, dim3(256), 0, st, static_cast<const cxd*>(x), a,
-                       static_cast<cxf*>(y), P);
+    hipLaunchKernelGGL(k_axpy_batch<float>, g, dim3(256), 0, st, m, static_cast<const cxf*>(x), static_cast<cxd*>(y),
+                       P);
   return hipGetLastError();
 }
 
-hipError_t launch_axpy_d(int prec_in, double a, const void* x, void* y, int64_t P, hipStream_t st) {
-  const dim3 g(grid_for(P, 256, 8192));
-  if (prec_in == PREC_F64)
-    hipLaunchKernelGGL(k_axpy_d<double>, g, dim3(256), 0, st, a, static_cast<const cxd*>(x), static_cast<cxd*>(y), P);
-  else
-    hipLaunchKernelGGL(k_axpy_d<float>, g, dim3(256), 0, st, a, static_cast<const cxf*>(x), static_cast<cxd*>(y), P);
+hipError_t launch_mul(const void* s, const void* x, void* y, int64_t P, int64_t nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_mul, dim3(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs)), dim3(256), 0, st,
+                     static_cast<const cxd*>(s), static_cast<const cxd*>(x), static_cast<cxd*>(y), P);
   return hipGetLastError();
 }
 
-hipError_t launch_mul(const void* s, const void* x, void* y, int64_t P, hipStream_t st) {
-  hipLaunchKernelGGL(k_mul, dim3(grid_for(P, 256, 8192)), dim3(256), 0, st, static_cast<const cxd*>(s),
-                     static_cast<const cxd*>(x), static_cast<cxd*>(y), P);
+hipError_t launch_conj_diff(const void* u, const void* t, void* f, int64_t P, double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_conj_diff, red_grid(P, 1), dim3(kRedThreads), 0, st, static_cast<const cxd*>(u),
+                     static_cast<const cxd*>(t), static_cast<cxd*>(f), P, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient(const double* c, const void* u, const void* q, double alpha, void* g, int64_t P,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_gradient, dim3(grid_for(P, 256, 8192)), dim3(256), 0, st, c, static_cast<const cxd*>(u),
+                     static_cast<const cxd*>(q), alpha, static_cast<cxd*>(g), P);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_mul(const void* f, const void* s, const void* x, void* lam, int64_t P, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub_mul, dim3(grid_for(P, 256, 8192)), dim3(256), 0, st, static_cast<const cxd*>(f),
+                     static_cast<const cxd*>(s), static_cast<const cxd*>(x), static_cast<cxd*>(lam), P);
   return hipGetLastError();
 }
 

@@ -205,6 +205,8 @@ struct LdsPencil {
   __device__ __forceinline__ cx<T>& at(int e) const { return base[e * es]; }
 };
 
+enum Keep : int { KEEP_ALL = 0, KEEP_HALF = 1, KEEP_HALF1 = 2 };
+
 // Stage data: cnt(s) butterflies of radix(s) complex values.
 template <typename T, int C, int R>
 struct Regs {
@@ -299,8 +301,10 @@ struct Engine {
   }
 
   // Last-stage outputs to a functor: store(e, value) for e = b + j L/R_last.
-  // With HALF_OUT only e < L/2 is stored.
-  template <bool HALF_OUT, class Store>
+  // KEEP selects the outputs: KEEP_ALL, KEEP_HALF (e < L/2: the discarded
+  // half of a padded inverse is never written) or KEEP_HALF1 (e <= L/2: the
+  // octant of an even sequence).
+  template <int KEEP, class Store>
   __device__ __forceinline__ static void store_last(const RegsOf<NS - 1>& g, int bt, Store&& store) {
     constexpr int s = NS - 1;
     constexpr int R = St::radix(s);
@@ -312,8 +316,9 @@ struct Engine {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int e = b + j * STRIDE;
-        if (HALF_OUT && (R % 2 == 0) && j >= R / 2) continue;
-        if (HALF_OUT && (R % 2 != 0) && e >= L / 2) continue;
+        if (KEEP == KEEP_HALF && (R % 2 == 0) && j >= R / 2) continue;
+        if (KEEP == KEEP_HALF && e >= L / 2) continue;
+        if (KEEP == KEEP_HALF1 && e > L / 2) continue;
         store(e, g.v[i][j]);
       }
     }

@@ -1,5 +1,10 @@
 // Launch interface between the host runtime and the kernel translation units.
 // Plain structs of device pointers and sizes; no torch types.
+//
+// Every vector may carry a batch of right-hand sides sharing one operator
+// (same k, h, N): vectors are [nrhs][P], the work arrays [nrhs][...], and the
+// diagonals D, S and the spectrum are shared.  Each right-hand side has its
+// own ScalarBlock and its own range of reduction partials.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,46 +13,53 @@
 
 namespace ori {
 
-// COCG scalars, resident in device memory for the whole solve (the host only
-// reads them at convergence checks).  rho = r^T r and mu = p^T A p use the
-// unconjugated bilinear form of COCG.
+// COCG scalars of one right-hand side, resident in device memory for the
+// whole solve (the host only reads them at convergence checks).  rho = r^T r
+// and mu = p^T A p use the unconjugated bilinear form of COCG.
 struct ScalarBlock {
   double rho_re, rho_im;      // r^T r of the current residual
   double mu_re, mu_im;        // p^T q
   double alpha_re, alpha_im;  // rho / mu
   double beta_re, beta_im;    // rho_new / rho_old
   double rr;                  // ||r||^2
-  double bb;                  // ||b||^2 (set by the init reduction)
+  double bb;                  // ||b||^2 of the forward right-hand side (set at load)
   double pp, qq;              // ||p||^2, ||q||^2 of the last product
-  double aux;                 // free slot for one-off reductions (||u0||^2, residual norms)
-  double pad0, pad1, pad2;
+  double aux;                 // one-off reductions (||u0||^2 at load, residual norms)
+  double rr_target;           // converged once rr <= rr_target (set by FIN_INIT)
+  double rr0;                 // rr at FIN_INIT
+  double pad0;
   int32_t flags;              // FLAG_* below
-  int32_t pad3;
+  int32_t iters;              // COCG iterations done while not converged
 };
 
 enum : int32_t {
   FLAG_BREAKDOWN_RHO = 1,  // r^T r ~ 0 while r != 0
   FLAG_BREAKDOWN_MU = 2,   // p^T A p ~ 0 while p != 0
-  FLAG_ZERO_RESIDUAL = 4,  // r == 0 exactly: converged
+  FLAG_ZERO_RESIDUAL = 4,  // r == 0 exactly
   FLAG_BAD_INPUT = 8,      // NaN / Inf / negative N met in ori_load
+  FLAG_CONVERGED = 16,     // rr <= rr_target: alpha = 0 from now on
 };
+constexpr int32_t FLAG_DONE = FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU | FLAG_ZERO_RESIDUAL | FLAG_CONVERGED;
 
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1 };
 
 // F1: forward DFT along the contiguous axis, with the prologue
 //   PLAIN: v = s_in * x            (s_in NULL means 1)
 //   COCG : p = r + beta p (p = r on the first iteration), stored; v = s_in * p
+// Pencils: nrhs * ppr (ppr = n*n per right-hand side); element e of pencil
+// (rhs, l) is vector entry (rhs * ppr + l) * in_pitch + e, and diagonal entry
+// l * in_pitch + e (diagonals are shared by the batch).
 struct ContigFwdArgs {
   const void* x;        // PLAIN input / COCG residual r        (vector type V)
   void* pvec;           // COCG search direction, updated in place (V)
   const void* s_in;     // diagonal scale (V) or NULL
-  const ScalarBlock* sc;
+  const ScalarBlock* sc;  // [nrhs]
   int32_t mode;         // 0 PLAIN, 1 COCG
   int32_t first;        // COCG: first iteration
   int32_t half_in;      // 1: only the first L/2 entries of each pencil are input (zero padding)
   int32_t pad;
   void* out;            // FFT type T, out[pencil * out_pitch + e]
-  int64_t npencils, in_pitch, out_pitch;
+  int64_t nrhs, ppr, in_pitch, out_pitch;
   const void* tw;       // L twiddles exp(-2 pi i m / L) in type T
 };
 
@@ -55,6 +67,8 @@ struct ContigFwdArgs {
 //   y = c0 a0 + c1 a1 + cc (s_out * conv)     (NULL operands are skipped; s_out NULL = 1)
 // and optional per-workgroup partials {dot.re, dot.im, |y|^2, |a0|^2}, with
 // dot = sum a0_j y_j (dot_self = 0) or sum y_j y_j (dot_self = 1), unconjugated.
+// y, a0, a1 are batch vectors; s_out is a shared diagonal.  The workgroups of
+// one right-hand side are consecutive: rhs owns partials [rhs*bpr, (rhs+1)*bpr).
 struct ContigInvArgs {
   const void* in;       // T, in[pencil * in_pitch + e]
   void* y;              // V, y[pencil * out_pitch + e], e < out_pitch
@@ -65,30 +79,61 @@ struct ContigInvArgs {
   double* partials;     // 4 doubles per workgroup, or NULL
   int32_t dot_self;
   int32_t pad;
-  int64_t npencils, in_pitch, out_pitch;
+  int64_t nrhs, ppr, in_pitch, out_pitch;
   const void* tw;
 };
 
-// F2 / I2 / the spectrum passes: DFT along a strided axis.  Pencil (o, c)
-// element e lives at  o * outer + e * axis + c,  c in [0, C) contiguous.
+// F2 / I2: DFT along a strided axis.  Pencil (o, c) element e lives at
+// off(o) + e * axis + c,  c in [0, C) contiguous, with a two-level outer
+// offset  off(o) = (o >> lg) * hi + (o & (2^lg - 1)) * lo  (lg = 0: o * hi).
+// The two levels express the blocked layout of the B array (see ZArgs); a
+// batch of right-hand sides is simply more outer rows (o = rhs * n + i1).
 struct StridedArgs {
   const void* in;
   void* out;
   int64_t n_outer, C;
-  int64_t in_outer, in_axis, out_outer, out_axis;
+  int32_t in_lg, out_lg;
+  int64_t in_hi, in_lo, in_axis;
+  int64_t out_hi, out_lo, out_axis;
   int32_t inverse, half_in, half_out, pad;
   const void* tw;
 };
 
-// Z: forward DFT along the slowest axis (first n inputs), multiply by the
-// kernel spectrum, inverse DFT, keep the first n outputs; in place.
-// Pencil (o = k2, c = k3), element e = i1 / k1 at  e * axis + o * outer + c.
+// Z: forward DFT along i1 (first n inputs), multiply by the kernel spectrum,
+// inverse DFT, keep the first n outputs; in place on B.  B element
+// (rhs, i1, k2, k3) lives at
+//   rhs * batch_stride + (i1 >> e_lg) * e_hi + (i1 & (2^e_lg - 1)) * e_lo + k2 * o_stride + k3
+// i.e. i1 is split into blocks of 2^e_lg rows stored next to each other, so
+// that one pencil of the Z pass spans n / 2^e_lg far-apart regions instead
+// of n.  The spectrum is stored as its octant [0..n]^3 (it is even along
+// every axis); zmap = 1 gives each workgroup a tile of octant rows (m2, m3)
+// and all (up to four) pencils (k2, k3) in {m2, L-m2} x {m3, L-m3} that
+// share them, for every right-hand side, so the octant is read from HBM once
+// per pass.
 struct ZArgs {
   void* buf;
-  int64_t n_outer, C, axis, outer;
+  int64_t n;
+  int32_t e_lg, zmap;
+  int64_t e_hi, e_lo, o_stride;
+  int64_t nrhs, batch_stride;
   const void* khat;     // octant [0..n]^3 of the spectrum (T), pitch kp = n + 1
   int64_t kp;
   const void* tw;
+};
+
+// Kernel spectrum on its octant, in place on kh[(m1 kp + m2) kp + m3],
+// kp = n + 1 (the Green's table of the padded grid is even along every axis,
+// so are its transforms, and [0..n] per axis determines everything):
+//   pass 1: generate the table along m3 for (m1, m2) in [0..n]^2, forward DFT,
+//           keep k3 in [0..n]
+//   pass 2: along m2 for (m1, k3): read [0..n], mirror, DFT, keep [0..n]
+//   pass 3: along m1 for (k2, k3): same, times `scale`; complex64 copy to khf.
+struct SpectrumArgs {
+  void* kh;
+  void* khf;           // pass 3 only, or NULL
+  double k, spacing, scale;
+  int32_t pass, pad;
+  const void* tw;      // complex128 twiddles
 };
 
 // Per-length launchers (one translation unit per L, see passes.hip).
@@ -98,49 +143,65 @@ struct LengthKernels {
   hipError_t (*contig_inv)(int vprec, int fprec, const ContigInvArgs&, hipStream_t);
   hipError_t (*strided)(int fprec, const StridedArgs&, hipStream_t);
   hipError_t (*zpass)(int fprec, const ZArgs&, hipStream_t);
-  int64_t (*contig_blocks)(int64_t npencils);
+  int64_t (*contig_blocks_per_rhs)(int64_t ppr);
   int64_t (*strided_blocks)(int fprec, int64_t n_outer, int64_t C);
+  int64_t (*zpass_blocks)(int fprec, int64_t n, int zmap);
+  hipError_t (*spectrum)(const SpectrumArgs&, hipStream_t);
 };
 
 const LengthKernels* kernels_for_length(int L);
 
 // ---------------------------------------------------------------------------
-// Elementwise / reduction kernels (aux.hip)
+// Elementwise / reduction kernels (aux.hip).  Batched kernels run a grid of
+// (red_blocks(P), nrhs) workgroups; right-hand side rhs writes partials
+// [rhs * red_blocks(P), (rhs + 1) * red_blocks(P)).
 // ---------------------------------------------------------------------------
-constexpr int kRedBlocks = 1024;  // fixed grid of the reduction kernels
 constexpr int kRedThreads = 256;
+constexpr int64_t kRedBlocksMax = 1024;
+inline int64_t red_blocks(int64_t P) {
+  int64_t b = (P + kRedThreads * 4 - 1) / (kRedThreads * 4);
+  if (b > kRedBlocksMax) b = kRedBlocksMax;
+  return b < 1 ? 1 : b;
+}
 
-// a1: D = 4 pi h N vol, S = sqrt(D), b = S u0; copies u0; partials
-// {||b||^2, ||u0||^2, bad-input count, 0}; also complex64 copies of S.
-hipError_t launch_coefficients(const void* h, const double* N, const void* u0, double vol, int64_t P,
-                               void* D, void* S, void* Sf, void* b, void* u0c, double* partials,
-                               hipStream_t st);
-// kernel table c(m) on the L^3 grid [m1][m2][m3] (zero at m = 0 and where a
-// wrapped offset equals n)
-hipError_t launch_embed(void* grid, int L, double k, double spacing, hipStream_t st);
-// kh[m1][m2][m3] = grid[m] * scale for m in [0, n]^3; complex64 copy too
-hipError_t launch_octant(const void* grid, int L, double scale, void* kh, void* khf, hipStream_t st);
-// reduce 4-double partials of nblk workgroups; mode says where the sums go
+// a1 (operator): D = 4 pi h N vol, S = sqrt(D), complex64 S, c = 4 pi N vol;
+// partials {bad-input count, 0, 0, 0} (one range)
+hipError_t launch_coefficients(const void* h, const double* N, double vol, int64_t P, void* D, void* S, void* Sf,
+                               double* cN, double* partials, hipStream_t st);
+// a1 (right-hand sides): b = S u0, u0 copied; partials {||b||^2, ||u0||^2, bad, 0} per rhs
+hipError_t launch_rhs(const void* u0, const void* S, int64_t P, int64_t nrhs, void* b, void* u0c,
+                      double* partials, hipStream_t st);
+// reduce partials (nblk per right-hand side) into sc[rhs]; mode says where
+// the sums go
 enum FinalizeMode : int32_t {
   FIN_SETUP = 0,   // sums = {||b||^2, ||u0||^2, bad, -}: bb, aux, flags
-  FIN_INIT = 1,    // sums = {rho.re, rho.im, rr, -}: rho, rr, beta = 0
+  FIN_INIT = 1,    // sums = {rho.re, rho.im, rr, -}: rho, rr, rr0, beta = 0, flags, rr_target
   FIN_MU = 2,      // sums = {mu.re, mu.im, qq, pp}: mu, alpha = rho / mu
-  FIN_RHO = 3,     // sums = {rho'.re, rho'.im, rr, -}: beta = rho'/rho, rho = rho', rr
+  FIN_RHO = 3,     // sums = {rho'.re, rho'.im, rr, -}: beta = rho'/rho, rho = rho', rr, flags
   FIN_NORM = 4,    // sums = {-, -, ||y||^2, -}: aux
+  FIN_BAD = 5,     // sums = {bad, -, -, -}: flags (operator coefficients)
 };
-hipError_t launch_finalize(const double* partials, int64_t nblk, ScalarBlock* sc, int32_t mode,
-                           double eps, hipStream_t st);
-// x += alpha p; r -= alpha q; partials {r^T r, ||r||^2} (vector type by prec)
-hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* q, int64_t P,
+// FIN_INIT: rr_target = tol2 * (tol2_of_bb ? bb : rr)
+hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, ScalarBlock* sc, int32_t mode,
+                           double eps, double tol2, int32_t tol2_of_bb, hipStream_t st);
+// x += alpha p; r -= alpha q; partials {r^T r, ||r||^2}; converged
+// right-hand sides (alpha = 0) stay as they are
+hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* q, int64_t P, int64_t nrhs,
                          const ScalarBlock* sc, double* partials, hipStream_t st);
-// r = b (converted to prec), x = 0; partials {r^T r, ||r||^2}
-hipError_t launch_init(int prec, const void* b, double bscale, void* x, void* r, int64_t P,
+// r = m_inv[rhs] * b (converted to prec; m NULL: 1), x = 0; partials {r^T r, ||r||^2}
+hipError_t launch_init(int prec, const void* b, const double* m, void* x, void* r, int64_t P, int64_t nrhs,
                        double* partials, hipStream_t st);
-// y = a * x (complex128 x, a real)  -- elementwise helpers
-hipError_t launch_scale_into(int prec_out, const void* x, double a, void* y, int64_t P, hipStream_t st);
-// y += a * x with x of type prec_in, y complex128
-hipError_t launch_axpy_d(int prec_in, double a, const void* x, void* y, int64_t P, hipStream_t st);
-// y = s * x (complex128, elementwise)
-hipError_t launch_mul(const void* s, const void* x, void* y, int64_t P, hipStream_t st);
+// y += m[rhs] * x with x of type prec_in, y complex128
+hipError_t launch_axpy_batch(int prec_in, const double* m, const void* x, void* y, int64_t P, int64_t nrhs,
+                             hipStream_t st);
+// y = s * x (s shared diagonal, x and y batch vectors)
+hipError_t launch_mul(const void* s, const void* x, void* y, int64_t P, int64_t nrhs, hipStream_t st);
+// f = conj(u - t); partials {0, 0, |u - t|^2, 0} (one right-hand side)
+hipError_t launch_conj_diff(const void* u, const void* t, void* f, int64_t P, double* partials, hipStream_t st);
+// g = alpha * c * u * q  (c real)
+hipError_t launch_gradient(const double* c, const void* u, const void* q, double alpha, void* g, int64_t P,
+                           hipStream_t st);
+// lam = f - s * x
+hipError_t launch_sub_mul(const void* f, const void* s, const void* x, void* lam, int64_t P, hipStream_t st);
 
 }  // namespace ori

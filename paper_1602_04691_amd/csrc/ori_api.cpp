@@ -1,6 +1,7 @@
 // Host runtime and C ABI (include/ori.h): context, workspaces, the FFT
 // product with the Green's matrix (Section 3), COCG (van der Vorst &
-// Melissen, cited by the paper) and mixed-precision refinement.
+// Melissen, cited by the paper), mixed-precision refinement, batches of
+// right-hand sides and the adjoint.
 #include "ori.h"
 
 #include <hip/hip_runtime.h>
@@ -10,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -41,6 +43,7 @@ using namespace ori;
 namespace {
 
 constexpr double kBreakdownEps = 1e-13;
+constexpr int64_t kMaxRhs = 1024;
 
 enum ProfKind : int {
   K_F1,
@@ -52,15 +55,12 @@ enum ProfKind : int {
   K_FINALIZE,
   K_INIT,
   K_COEFF,
-  K_EMBED,
   K_SPEC_FFT,
-  K_OCTANT,
   K_ELEMWISE,
   K_NKIND
 };
 const char* const kKindNames[K_NKIND] = {"f1", "f2", "zpass", "i2", "i1", "update", "finalize",
-                                         "init", "coefficients", "embed", "spectrum_fft", "octant",
-                                         "elementwise"};
+                                         "init", "coefficients", "spectrum", "elementwise"};
 
 thread_local std::string g_last_error = "no error";
 
@@ -74,6 +74,7 @@ struct ProfPending {
 struct ori_ctx_s {
   ori_grid grid{};
   int64_t n = 0, L = 0, P = 0;
+  int64_t nrhs = 1;  // right-hand sides per solve (fixed at create)
   int provision = 0;
   double k = 0.0;
   bool loaded = false;
@@ -81,21 +82,29 @@ struct ori_ctx_s {
   hipStream_t stream = nullptr;
   int device = 0;
   const LengthKernels* K = nullptr;
+  int blk_lg = 0;  // log2 of the i1 block of the B layout
+  int zmap = 1;    // Z-pass workgroup mapping (ZArgs)
   std::string err = "no error";
-  double u0norm2 = 0.0, bnorm2 = 0.0;
+  std::vector<double> u0norm2, bnorm2;     // per right-hand side
+  std::vector<ori_solve_info> last_info;  // per right-hand side, last solve
 
-  void* arena = nullptr;  // L^3 complex128: spectrum grid, then the A/B work arrays
-  cxd *D = nullptr, *S = nullptr, *b = nullptr, *u0 = nullptr;
-  cxd *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
-  cxf *Sf = nullptr, *xf = nullptr, *rf = nullptr, *pf = nullptr, *qf = nullptr;
+  void* arena = nullptr;                      // A/B work arrays of the FFT passes, nrhs of them
+  cxd *D = nullptr, *S = nullptr;             // shared diagonals
+  double* cN = nullptr;                       // 4 pi N |Delta| (real, shared)
+  cxf* Sf = nullptr;
+  cxd *b = nullptr, *u0 = nullptr;            // [nrhs][P]
+  cxd *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;  // [nrhs][P]
+  cxf *xf = nullptr, *rf = nullptr, *pf = nullptr, *qf = nullptr;
+  cxd *t1 = nullptr, *t2 = nullptr;           // adjoint work vectors (one right-hand side)
   cxd* kh = nullptr;
   cxf* khf = nullptr;
   cxd* twd = nullptr;
   cxf* twf = nullptr;
   double* partials = nullptr;
-  int64_t npartials = 0;  // quadruples
-  ScalarBlock* sc = nullptr;
-  ScalarBlock* sc_host = nullptr;  // pinned
+  ScalarBlock* sc = nullptr;       // [nrhs]
+  ScalarBlock* sc_host = nullptr;  // pinned mirror
+  double* outer_m = nullptr;       // [nrhs] refinement multipliers
+  double* outer_m_host = nullptr;  // pinned
   std::vector<void*> allocs;
 
   // profiling
@@ -123,16 +132,16 @@ ori_status set_err(ori_ctx c, ori_status st, const char* fmt, ...) {
   return st;
 }
 
-#define ORI_HIP(c, call)                                                                            \
-  do {                                                                                              \
-    hipError_t e_ = (call);                                                                         \
+#define ORI_HIP(c, call)                                                                                     \
+  do {                                                                                                       \
+    hipError_t e_ = (call);                                                                                  \
     if (e_ != hipSuccess) return set_err((c), ORI_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-#define ORI_TRY(expr)               \
-  do {                              \
-    ori_status s_ = (expr);         \
-    if (s_ != ORI_OK) return s_;    \
+#define ORI_TRY(expr)            \
+  do {                           \
+    ori_status s_ = (expr);      \
+    if (s_ != ORI_OK) return s_; \
   } while (0)
 
 bool finite(double v) { return std::isfinite(v); }
@@ -152,30 +161,29 @@ ori_status check_grid(const ori_grid* g, int64_t* L_out) {
   return ORI_OK;
 }
 
-struct Layout {
-  int64_t arena, vec_d, vec_f, kh, khf, tw, partials, nvec_d, nvec_f, npart;
-  int64_t total;
-};
-
 int64_t align_up(int64_t v) { return (v + 255) / 256 * 256; }
 
-Layout layout_for(int64_t n, int provision) {
-  const int64_t L = 2 * n, P = n * n * n, kp = n + 1;
+struct Layout {
+  int64_t arena, vec_d, vec_f, kh, khf, npart, total;
+};
+
+// Device bytes for n and a batch of nrhs.  Partial quadruples cover the
+// largest reducing grid: I1 (at most n*n workgroups per right-hand side) and
+// the reduction kernels (red_blocks(P) per right-hand side).
+Layout layout_for(int64_t n, int64_t nrhs, int provision) {
+  const int64_t P = n * n * n, kp = n + 1;
+  const bool mixed = provision & ORI_PROVISION_MIXED;
   Layout l{};
-  l.arena = align_up(L * L * L * 16);
+  l.arena = align_up(nrhs * 6 * P * 16);  // A (n*n*L) + B (n*L*L), complex128
   l.vec_d = align_up(P * 16);
   l.vec_f = align_up(P * 8);
-  l.nvec_d = 8;  // D, S, b, u0, x, r, p, q
-  l.nvec_f = (provision & ORI_PROVISION_MIXED) ? 5 : 0;  // Sf, xf, rf, pf, qf
   l.kh = align_up(kp * kp * kp * 16);
-  l.khf = (provision & ORI_PROVISION_MIXED) ? align_up(kp * kp * kp * 8) : 0;
-  l.tw = align_up(L * 16) + align_up(L * 8);
-  // partial quadruples: the largest grid of a reducing kernel (I1 has at
-  // most n*n workgroups; the exact count is used at create time)
-  l.npart = std::max<int64_t>(kRedBlocks, n * n);
-  l.partials = align_up(l.npart * 4 * 8);
-  l.total = l.arena + l.nvec_d * l.vec_d + l.nvec_f * l.vec_f + l.kh + l.khf + l.tw + l.partials +
-            align_up(sizeof(ScalarBlock));
+  l.khf = mixed ? align_up(kp * kp * kp * 8) : 0;
+  l.npart = nrhs * std::max<int64_t>(red_blocks(P), n * n);
+  const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
+  const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
+  l.total = l.arena + shared + batch + l.kh + l.khf + align_up(2 * n * 16) + align_up(2 * n * 8) +
+            align_up(l.npart * 4 * 8) + align_up(nrhs * (int64_t)sizeof(ScalarBlock)) + align_up(nrhs * 8);
   return l;
 }
 
@@ -238,7 +246,8 @@ ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
     ORI_HIP(c, hipEventRecord(c->ev[2 * evi], c->stream));
   }
   hipError_t e = f();
-  if (e != hipSuccess) return set_err(c, ORI_ERR_DEVICE, "kernel %s launch failed: %s", kKindNames[kind], hipGetErrorString(e));
+  if (e != hipSuccess)
+    return set_err(c, ORI_ERR_DEVICE, "kernel %s launch failed: %s", kKindNames[kind], hipGetErrorString(e));
   if (c->prof) {
     ORI_HIP(c, hipEventRecord(c->ev[2 * evi + 1], c->stream));
     c->pend.push_back(ProfPending{kind * 2 + (fprec == PREC_F32 ? 1 : 0), evi});
@@ -247,51 +256,61 @@ ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
 }
 
 ori_status sync_scalars(ori_ctx c) {
-  ORI_HIP(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScalarBlock), hipMemcpyDeviceToHost, c->stream));
+  ORI_HIP(c, hipMemcpyAsync(c->sc_host, c->sc, c->nrhs * sizeof(ScalarBlock), hipMemcpyDeviceToHost, c->stream));
   ORI_HIP(c, hipStreamSynchronize(c->stream));
   return ORI_OK;
 }
 
-ori_status finalize(ori_ctx c, int64_t nblk, int mode) {
-  return launch(c, K_FINALIZE, PREC_F64,
-                [&] { return launch_finalize(c->partials, nblk, c->sc, mode, kBreakdownEps, c->stream); });
+ori_status finalize(ori_ctx c, int64_t nblk, int mode, double tol2 = 0.0, int tol2_of_bb = 0) {
+  return launch(c, K_FINALIZE, PREC_F64, [&] {
+    return launch_finalize(c->partials, nblk, c->nrhs, c->sc, mode, kBreakdownEps, tol2, tol2_of_bb, c->stream);
+  });
 }
 
+int64_t rblocks(ori_ctx c) { return red_blocks(c->P); }
+
 // ---------------------------------------------------------------------------
-// the FFT product: F1 -> F2 -> Z -> I2 -> I1 (prologue / epilogue in f1, i1)
+// the FFT product: F1 -> F2 -> Z -> I2 -> I1 (prologue / epilogue in f1, i1),
+// over all right-hand sides of the context at once
 // ---------------------------------------------------------------------------
 ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvArgs i1, int64_t* nblk_out) {
-  const int64_t n = c->n, L = c->L;
+  const int64_t n = c->n, L = c->L, R = c->nrhs;
   const int64_t elem = fprec == PREC_F64 ? 16 : 8;
   char* A = static_cast<char*>(c->arena);
-  char* B = A + n * n * L * elem;
+  char* B = A + R * n * n * L * elem;
   const void* tw = fprec == PREC_F64 ? static_cast<const void*>(c->twd) : static_cast<const void*>(c->twf);
   const void* kh = fprec == PREC_F64 ? static_cast<const void*>(c->kh) : static_cast<const void*>(c->khf);
   if (!kh) return set_err(c, ORI_ERR_INVALID_ARG, "complex64 workspaces were not provisioned");
 
   f1.half_in = 1;
   f1.out = A;
-  f1.npencils = n * n;
+  f1.nrhs = R;
+  f1.ppr = n * n;
   f1.in_pitch = n;
   f1.out_pitch = L;
   f1.tw = tw;
   ORI_TRY(launch(c, K_F1, fprec, [&] { return c->K->contig_fwd(vprec, fprec, f1, c->stream); }));
 
-  StridedArgs f2{A, B, n, L, n * L, L, L * L, L, 0, 1, 0, 0, tw};
+  // B layout: i1 split into blocks of 2^lg rows (see ZArgs); the batch is
+  // just more outer rows
+  const int lg = c->blk_lg;
+  const int64_t Bk = int64_t{1} << lg;
+  StridedArgs f2{A, B, R * n, L, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, 0, tw};
   ORI_TRY(launch(c, K_F2, fprec, [&] { return c->K->strided(fprec, f2, c->stream); }));
 
-  ZArgs z{B, L, L, L * L, L, kh, n + 1, tw};
+  ZArgs z{B, n, lg, c->zmap, L * L * Bk, L, Bk * L, R, n * L * L, kh, n + 1, tw};
   ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, z, c->stream); }));
 
-  StridedArgs i2{B, A, n, L, L * L, L, n * L, L, 1, 0, 1, 0, tw};
+  StridedArgs i2{B, A, R * n, L, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, 0, tw};
   ORI_TRY(launch(c, K_I2, fprec, [&] { return c->K->strided(fprec, i2, c->stream); }));
 
   i1.in = A;
-  i1.npencils = n * n;
+  i1.nrhs = R;
+  i1.ppr = n * n;
   i1.in_pitch = L;
   i1.out_pitch = n;
   i1.tw = tw;
-  if (nblk_out) *nblk_out = c->K->contig_blocks(n * n);
+  if (nblk_out) *nblk_out = c->K->contig_blocks_per_rhs(n * n);
   ORI_TRY(launch(c, K_I1, fprec, [&] { return c->K->contig_inv(vprec, fprec, i1, c->stream); }));
   return ORI_OK;
 }
@@ -320,29 +339,16 @@ ContigInvArgs epi(void* y, const void* a0, double c0, const void* a1, double c1,
 }
 
 // ---------------------------------------------------------------------------
-// setup: spectrum of the Green's table (a2) and the coefficients (a1)
+// setup: the kernel spectrum (a2), three in-place passes on its octant
 // ---------------------------------------------------------------------------
 ori_status compute_spectrum(ori_ctx c) {
-  const int L = static_cast<int>(c->L);
-  const int64_t L2 = c->L * c->L;
-  const double spacing = c->grid.side / static_cast<double>(c->n);
-  ORI_TRY(launch(c, K_EMBED, PREC_F64, [&] { return launch_embed(c->arena, L, c->k, spacing, c->stream); }));
-  ContigFwdArgs f{};
-  f.x = c->arena;
-  f.mode = 0;
-  f.half_in = 0;
-  f.out = c->arena;
-  f.npencils = L2;
-  f.in_pitch = L;
-  f.out_pitch = L;
-  f.tw = c->twd;
-  ORI_TRY(launch(c, K_SPEC_FFT, PREC_F64, [&] { return c->K->contig_fwd(PREC_F64, PREC_F64, f, c->stream); }));
-  StridedArgs s2{c->arena, c->arena, L, L, L2, L, L2, L, 0, 0, 0, 0, c->twd};
-  ORI_TRY(launch(c, K_SPEC_FFT, PREC_F64, [&] { return c->K->strided(PREC_F64, s2, c->stream); }));
-  StridedArgs s1{c->arena, c->arena, L, L, L, L2, L, L2, 0, 0, 0, 0, c->twd};
-  ORI_TRY(launch(c, K_SPEC_FFT, PREC_F64, [&] { return c->K->strided(PREC_F64, s1, c->stream); }));
-  const double scale = 1.0 / (static_cast<double>(L) * L * L);  // inverse DFT normalisation, folded in once
-  ORI_TRY(launch(c, K_OCTANT, PREC_F64, [&] { return launch_octant(c->arena, L, scale, c->kh, c->khf, c->stream); }));
+  const double L = static_cast<double>(c->L);
+  SpectrumArgs a{c->kh, nullptr, c->k, c->grid.side / static_cast<double>(c->n), 1.0 / (L * L * L), 1, 0, c->twd};
+  for (int pass = 1; pass <= 3; ++pass) {
+    a.pass = pass;
+    a.khf = pass == 3 ? c->khf : nullptr;  // 1/L^3 of the inverse DFT is folded in by pass 3
+    ORI_TRY(launch(c, K_SPEC_FFT, PREC_F64, [&] { return c->K->spectrum(a, c->stream); }));
+  }
   return ORI_OK;
 }
 
@@ -351,10 +357,9 @@ void fill_twiddles(int64_t L, std::vector<cxd>& d, std::vector<cxf>& f) {
   f.resize(L);
   const long double two_pi = 6.283185307179586476925286766559L;
   for (int64_t m = 0; m < L; ++m) {
-    // exp(-2 pi i m / L), argument reduced to [0, pi/4] by symmetry for accuracy
+    // exp(-2 pi i m / L) in long double, exact at the quarter turns
     const long double a = two_pi * static_cast<long double>(m) / static_cast<long double>(L);
     long double cs = cosl(a), sn = sinl(a);
-    // exact values where known
     if (4 * m % L == 0) {
       const int64_t q = 4 * m / L;
       cs = (q == 0) ? 1 : (q == 2) ? -1 : 0;
@@ -366,27 +371,30 @@ void fill_twiddles(int64_t L, std::vector<cxd>& d, std::vector<cxf>& f) {
 }
 
 // ---------------------------------------------------------------------------
-// COCG on (I + S G0 S) w = rhs, vectors of type vprec, FFTs of type fprec.
-// Expects x, r initialised and the scalars set by FIN_INIT.
+// COCG on (I + S G0 S) w = rhs for every right-hand side in lockstep,
+// vectors of type prec (FFTs too).  Expects x, r initialised and FIN_INIT
+// done (per right-hand side targets set); a right-hand side that converges
+// or breaks down is frozen on the device (alpha = 0) while the others go on.
 // ---------------------------------------------------------------------------
 struct CocgOut {
-  int iters = 0;
+  int iters = 0;  // batched iterations run
   int64_t matvecs = 0;
-  double rr = 0.0;
-  int flags = 0;
-  bool converged = false;
+  bool all_done = false;
 };
 
-ori_status run_cocg(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, double rr_target,
-                    int max_iter, int check_every, CocgOut* out) {
+bool all_done(ori_ctx c) {
+  for (int64_t i = 0; i < c->nrhs; ++i)
+    if (!(c->sc_host[i].flags & FLAG_DONE)) return false;
+  return true;
+}
+
+ori_status run_cocg(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
+                    int check_every, CocgOut* out) {
   ORI_TRY(sync_scalars(c));
-  out->rr = c->sc_host->rr;
-  out->flags = c->sc_host->flags;
-  if ((out->flags & FLAG_ZERO_RESIDUAL) || out->rr <= rr_target) {
-    out->converged = true;
+  if (all_done(c)) {
+    out->all_done = true;
     return ORI_OK;
   }
-  if (out->flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU)) return ORI_OK;
   const int64_t P = c->P;
   for (int it = 0; it < max_iter; ++it) {
     ContigFwdArgs f1{};
@@ -401,16 +409,15 @@ ori_status run_cocg(ori_ctx c, int prec, void* x, void* r, void* p, void* q, con
     ORI_TRY(matvec(c, prec, prec, f1, i1, &nblk));
     out->matvecs++;
     ORI_TRY(finalize(c, nblk, FIN_MU));
-    ORI_TRY(launch(c, K_UPDATE, prec, [&] { return launch_update(prec, x, p, r, q, P, c->sc, c->partials, c->stream); }));
-    ORI_TRY(finalize(c, kRedBlocks, FIN_RHO));
+    ORI_TRY(launch(c, K_UPDATE, prec, [&] {
+      return launch_update(prec, x, p, r, q, P, c->nrhs, c->sc, c->partials, c->stream);
+    }));
+    ORI_TRY(finalize(c, rblocks(c), FIN_RHO));
     out->iters++;
     if ((it + 1) % check_every == 0 || it + 1 == max_iter) {
       ORI_TRY(sync_scalars(c));
-      out->rr = c->sc_host->rr;
-      out->flags = c->sc_host->flags;
-      if (out->flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU)) return ORI_OK;
-      if ((out->flags & FLAG_ZERO_RESIDUAL) || out->rr <= rr_target) {
-        out->converged = true;
+      if (all_done(c)) {
+        out->all_done = true;
         return ORI_OK;
       }
     }
@@ -418,12 +425,12 @@ ori_status run_cocg(ori_ctx c, int prec, void* x, void* r, void* p, void* q, con
   return ORI_OK;
 }
 
-// r = b - (I + S G0 S) x in FP64; returns ||r||^2 and r^T r via FIN_INIT
-ori_status true_residual_sym(ori_ctx c, const cxd* x, cxd* r) {
+// r = rhs - (I + S G0 S) x in FP64 (batch), then FIN_INIT (rr, rho, targets)
+ori_status true_residual_sym(ori_ctx c, const cxd* rhs, const cxd* x, cxd* r, double tol2, int tol2_of_bb) {
   int64_t nblk = 0;
-  ORI_TRY(matvec(c, PREC_F64, PREC_F64, plain_f1(x, c->S), epi(r, c->b, 1.0, x, -1.0, c->S, -1.0, c->partials, 1),
+  ORI_TRY(matvec(c, PREC_F64, PREC_F64, plain_f1(x, c->S), epi(r, rhs, 1.0, x, -1.0, c->S, -1.0, c->partials, 1),
                  &nblk));
-  return finalize(c, nblk, FIN_INIT);
+  return finalize(c, nblk, FIN_INIT, tol2, tol2_of_bb);
 }
 
 // u = u0 - G0 S w (recovery of the solution of eq. 2.19 from w)
@@ -432,22 +439,236 @@ ori_status recover(ori_ctx c, const cxd* w, cxd* u) {
                 nullptr);
 }
 
-// ||u0 - u - G0 D u|| / ||u0||
-ori_status true_residual_orig(ori_ctx c, const cxd* u, double* rel) {
+// ||u0 - u - G0 D u|| / ||u0|| per right-hand side
+ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel) {
   int64_t nblk = 0;
   ORI_TRY(matvec(c, PREC_F64, PREC_F64, plain_f1(u, c->D),
                  epi(c->q, c->u0, 1.0, u, -1.0, nullptr, -1.0, c->partials, 1), &nblk));
   ORI_TRY(finalize(c, nblk, FIN_NORM));
   ORI_TRY(sync_scalars(c));
-  *rel = c->u0norm2 > 0 ? std::sqrt(c->sc_host->aux / c->u0norm2) : std::sqrt(c->sc_host->aux);
+  rel->resize(c->nrhs);
+  for (int64_t i = 0; i < c->nrhs; ++i) {
+    const double a = c->sc_host[i].aux;
+    (*rel)[i] = c->u0norm2[i] > 0 ? std::sqrt(a / c->u0norm2[i]) : std::sqrt(a);
+  }
   return ORI_OK;
+}
+
+// Layout knobs of the FFT work arrays.  Defaults are the measured best on
+// MI355X; ORI_TUNE_BLK_LG / ORI_TUNE_ZMAP override them for tuning runs.
+void choose_layout(ori_ctx c) {
+  int lg = 4, zmap = 1;
+  if (const char* e = std::getenv("ORI_TUNE_BLK_LG")) lg = std::atoi(e);
+  if (const char* e = std::getenv("ORI_TUNE_ZMAP")) zmap = std::atoi(e);
+  if (lg < 0) lg = 0;
+  while (lg > 0 && (c->n % (int64_t{1} << lg)) != 0) --lg;
+  c->blk_lg = lg;
+  c->zmap = zmap == 0 ? 0 : 1;
 }
 
 ori_status guard(ori_ctx c) {
   if (!c) return set_err(nullptr, ORI_ERR_INVALID_ARG, "context is NULL");
-  if (c->poisoned) return set_err(c, ORI_ERR_DEVICE, "context is poisoned by an earlier device error: %s", c->err.c_str());
+  if (c->poisoned)
+    return set_err(c, ORI_ERR_DEVICE, "context is poisoned by an earlier device error: %s", c->err.c_str());
   ORI_HIP(c, hipSetDevice(c->device));
   return ORI_OK;
+}
+
+ori_status check_opts(ori_ctx c, const ori_solve_opts* in, ori_solve_opts* o) {
+  if (!c->loaded) return set_err(c, ORI_ERR_INVALID_ARG, "ori_load has not succeeded on this context");
+  if (in)
+    *o = *in;
+  else
+    ori_default_opts(o);
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return set_err(c, ORI_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  if (o->max_iter < 0) return set_err(c, ORI_ERR_INVALID_ARG, "max_iter must be >= 0");
+  if (o->precision != ORI_FP64 && o->precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
+  if (o->precision == ORI_MIXED && !(c->provision & ORI_PROVISION_MIXED))
+    return set_err(c, ORI_ERR_INVALID_ARG, "complex64 workspaces were not provisioned");
+  if (o->check_every < 0) return set_err(c, ORI_ERR_INVALID_ARG, "check_every must be >= 0");
+  if (o->check_every == 0) o->check_every = 1;
+  if (o->inner_tol <= 0.0) o->inner_tol = 1e-5;
+  if (!std::isfinite(o->inner_tol) || o->inner_tol >= 1.0)
+    return set_err(c, ORI_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
+  if (o->max_outer <= 0) o->max_outer = 10;
+  return ORI_OK;
+}
+
+// Per right-hand side outcome of a solve.
+struct Outcome {
+  std::vector<ori_solve_info> info;
+  std::vector<int> state;  // 0 converged, 1 not converged, 2 breakdown
+};
+
+ori_status end_status(ori_ctx c, const Outcome& oc, const char* what) {
+  int nb = 0, nn = 0;
+  for (int s : oc.state) {
+    nb += s == 2;
+    nn += s == 1;
+  }
+  if (nb) return set_err(c, ORI_ERR_BREAKDOWN, "%s breakdown in %d of %zu right-hand sides", what, nb, oc.state.size());
+  if (nn)
+    return set_err(c, ORI_ERR_NOT_CONVERGED, "%s not converged in %d of %zu right-hand sides (relative residual %.3e)",
+                   what, nn, oc.state.size(), oc.info.empty() ? 0.0 : oc.info[0].rel_res_recursive);
+  return ORI_OK;
+}
+
+ori_solve_info aggregate(const Outcome& oc) {
+  ori_solve_info a{};
+  a.rel_res_true = -1.0;
+  for (const ori_solve_info& i : oc.info) {
+    a.iterations = std::max(a.iterations, i.iterations);
+    a.refinements = std::max(a.refinements, i.refinements);
+    a.matvecs = std::max(a.matvecs, i.matvecs);
+    a.matvecs_c64 = std::max(a.matvecs_c64, i.matvecs_c64);
+    a.rel_res_recursive = std::max(a.rel_res_recursive, i.rel_res_recursive);
+    a.rel_res_true = std::max(a.rel_res_true, i.rel_res_true);
+  }
+  return a;
+}
+
+// Solve (I + S G0 S) w = rhs into c->x for every right-hand side.  On entry
+// c->x and c->r hold the initial iterate and its residual, FIN_INIT done with
+// the stopping targets; bb[i] = ||rhs_i||^2 (host) sets the same targets for
+// the refinement loop.  Counts go to oc (added).
+ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const std::vector<double>& bb, Outcome* oc) {
+  const int64_t P = c->P, R = c->nrhs;
+  std::vector<double> target(R);
+  for (int64_t i = 0; i < R; ++i) target[i] = o.tol * o.tol * bb[i];
+  if (o.precision == ORI_FP64) {
+    CocgOut co;
+    ORI_TRY(run_cocg(c, PREC_F64, c->x, c->r, c->p, c->q, c->S, o.max_iter, o.check_every, &co));
+    for (int64_t i = 0; i < R; ++i) {
+      const ScalarBlock& s = c->sc_host[i];
+      oc->info[i].iterations += s.iters;
+      oc->info[i].matvecs += s.iters;
+      oc->info[i].rel_res_recursive = bb[i] > 0 ? std::sqrt(s.rr / bb[i]) : 0.0;
+      const bool conv = (s.flags & (FLAG_CONVERGED | FLAG_ZERO_RESIDUAL)) != 0;
+      oc->state[i] = conv ? 0 : (s.flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU)) ? 2 : 1;
+    }
+    return ORI_OK;
+  }
+  // iterative refinement: FP64 true residual, complex64 inner COCG on the
+  // normalised correction equation of every unconverged right-hand side
+  ORI_TRY(sync_scalars(c));
+  std::vector<int> done(R, 0);
+  int inner_left = o.max_iter;
+  for (int outer = 0;; ++outer) {
+    bool all = true;
+    for (int64_t i = 0; i < R; ++i) {
+      const ScalarBlock& s = c->sc_host[i];
+      oc->info[i].rel_res_recursive = bb[i] > 0 ? std::sqrt(s.rr / bb[i]) : 0.0;
+      if (done[i] == 0 && (s.rr <= target[i] || s.rr == 0.0)) done[i] = 1;
+      if (done[i] == 0 && outer == 0 && (s.flags & FLAG_BREAKDOWN_RHO)) done[i] = 2;
+      c->outer_m_host[i] = done[i] ? 0.0 : std::sqrt(s.rr);
+      all = all && done[i];
+    }
+    if (all || outer >= o.max_outer || inner_left <= 0) break;
+    ORI_HIP(c, hipMemcpyAsync(c->outer_m, c->outer_m_host, R * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    ORI_TRY(launch(c, K_INIT, PREC_F32, [&] {
+      return launch_init(PREC_F32, c->r, c->outer_m, c->xf, c->rf, P, R, c->partials, c->stream);
+    }));
+    ORI_TRY(finalize(c, rblocks(c), FIN_INIT, o.inner_tol * o.inner_tol, 0));
+    CocgOut co;
+    ORI_TRY(run_cocg(c, PREC_F32, c->xf, c->rf, c->pf, c->qf, c->Sf, inner_left, o.check_every, &co));
+    inner_left -= co.iters;
+    bool progress = false;
+    for (int64_t i = 0; i < R; ++i) {
+      if (done[i]) continue;
+      const ScalarBlock& s = c->sc_host[i];
+      oc->info[i].iterations += s.iters;
+      oc->info[i].matvecs += s.iters;
+      oc->info[i].matvecs_c64 += s.iters;
+      if (s.iters == 0 && (s.flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU))) done[i] = 2;
+      progress = progress || s.iters > 0;
+    }
+    ORI_TRY(launch(c, K_ELEMWISE, PREC_F32, [&] {
+      return launch_axpy_batch(PREC_F32, c->outer_m, c->xf, c->x, P, R, c->stream);
+    }));
+    ORI_TRY(true_residual_sym(c, rhs, c->x, c->r, 0.0, 0));
+    for (int64_t i = 0; i < R; ++i) {
+      if (done[i]) continue;
+      oc->info[i].matvecs++;
+      oc->info[i].refinements++;
+    }
+    ORI_TRY(sync_scalars(c));
+    if (!progress) break;
+  }
+  for (int64_t i = 0; i < R; ++i) oc->state[i] = done[i] == 1 ? 0 : done[i] == 2 ? 2 : 1;
+  return ORI_OK;
+}
+
+// Forward problem for every right-hand side: w = S u (guess) or 0, solve,
+// u = u0 - G0 S w, true residual.
+ori_status forward_solve(ori_ctx c, const ori_solve_opts& o, cxd* u, Outcome* oc) {
+  const int64_t P = c->P, R = c->nrhs;
+  oc->info.assign(R, ori_solve_info{});
+  oc->state.assign(R, 1);
+  const double tol2 = o.tol * o.tol;
+  if (o.use_x0) {
+    ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_mul(c->S, u, c->x, P, R, c->stream); }));
+    ORI_TRY(true_residual_sym(c, c->b, c->x, c->r, tol2, 1));
+    for (auto& i : oc->info) i.matvecs++;
+  } else {
+    ORI_TRY(launch(c, K_INIT, PREC_F64, [&] {
+      return launch_init(PREC_F64, c->b, nullptr, c->x, c->r, P, R, c->partials, c->stream);
+    }));
+    ORI_TRY(finalize(c, rblocks(c), FIN_INIT, tol2, 1));
+  }
+  ORI_TRY(solve_sym(c, o, c->b, c->bnorm2, oc));
+  ORI_TRY(recover(c, c->x, u));
+  for (auto& i : oc->info) {
+    i.matvecs++;
+    i.rel_res_true = -1.0;
+  }
+  if (o.true_residual) {
+    std::vector<double> rel;
+    ORI_TRY(true_residual_orig(c, u, &rel));
+    for (int64_t i = 0; i < R; ++i) {
+      oc->info[i].matvecs++;
+      oc->info[i].rel_res_true = rel[i];
+    }
+  }
+  return ORI_OK;
+}
+
+// Adjoint problem A^T lam = f with A^T = I + D G0 (one right-hand side),
+// division free:
+//   lam = f - S z,  (I + S G0 S) z = S G0 f,
+//   G0 lam = G0 f - G0 S z,
+//   g = -scale * c u (G0 lam),   c = 4 pi N |Delta|.
+ori_status adjoint_solve(ori_ctx c, const ori_solve_opts& o, const cxd* u, const cxd* f, double scale, cxd* g,
+                         cxd* lam, Outcome* oc) {
+  const int64_t P = c->P;
+  oc->info.assign(1, ori_solve_info{});
+  oc->state.assign(1, 1);
+  // t1 = G0 f
+  ORI_TRY(matvec(c, PREC_F64, PREC_F64, plain_f1(f, nullptr),
+                 epi(c->t1, nullptr, 0.0, nullptr, 0.0, nullptr, 1.0, nullptr, 0), nullptr));
+  oc->info[0].matvecs++;
+  // t2 = S t1 (right-hand side); x = 0, r = t2
+  ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_mul(c->S, c->t1, c->t2, P, 1, c->stream); }));
+  ORI_TRY(launch(c, K_INIT, PREC_F64, [&] {
+    return launch_init(PREC_F64, c->t2, nullptr, c->x, c->r, P, 1, c->partials, c->stream);
+  }));
+  ORI_TRY(finalize(c, rblocks(c), FIN_INIT, o.tol * o.tol, 0));
+  ORI_TRY(sync_scalars(c));
+  const std::vector<double> bb(1, c->sc_host[0].rr0);
+  ORI_TRY(solve_sym(c, o, c->t2, bb, oc));
+  // q = G0 lam = t1 - G0 S z
+  ORI_TRY(matvec(c, PREC_F64, PREC_F64, plain_f1(c->x, c->S),
+                 epi(c->q, c->t1, 1.0, nullptr, 0.0, nullptr, -1.0, nullptr, 0), nullptr));
+  oc->info[0].matvecs++;
+  if (g)
+    ORI_TRY(launch(c, K_ELEMWISE, PREC_F64,
+                   [&] { return launch_gradient(c->cN, u, c->q, -scale, g, P, c->stream); }));
+  if (lam)
+    ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_sub_mul(f, c->S, c->x, lam, P, c->stream); }));
+  return ORI_OK;
+}
+
+double elapsed(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 }  // namespace
@@ -469,23 +690,28 @@ void ori_default_opts(ori_solve_opts* o) {
   o->true_residual = 1;
 }
 
-const char* ori_version(void) { return "ori 0.1 (gfx950)"; }
+const char* ori_version(void) { return "ori 0.2 (gfx950)"; }
 
-ori_status ori_workspace_bytes(const ori_grid* g, int32_t provision, int64_t* bytes) {
+ori_status ori_workspace_bytes(const ori_grid* g, int32_t nrhs, int32_t provision, int64_t* bytes) {
   int64_t L = 0;
   ORI_TRY(check_grid(g, &L));
+  if (nrhs < 1 || nrhs > kMaxRhs) return set_err(nullptr, ORI_ERR_INVALID_ARG, "nrhs = %d out of [1, %lld]", nrhs,
+                                                  (long long)kMaxRhs);
   if (!bytes) return set_err(nullptr, ORI_ERR_INVALID_ARG, "bytes is NULL");
-  *bytes = layout_for(g->n, provision | ORI_PROVISION_FP64).total;
+  *bytes = layout_for(g->n, nrhs, provision | ORI_PROVISION_FP64).total;
   return ORI_OK;
 }
 
-ori_status ori_create(const ori_grid* g, int32_t provision, int64_t mem_limit_bytes, void* stream, ori_ctx* out) {
+ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_t mem_limit_bytes, void* stream,
+                      ori_ctx* out) {
   if (!out) return set_err(nullptr, ORI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   int64_t L = 0;
   ORI_TRY(check_grid(g, &L));
+  if (nrhs < 1 || nrhs > kMaxRhs)
+    return set_err(nullptr, ORI_ERR_INVALID_ARG, "nrhs = %d out of [1, %lld]", nrhs, (long long)kMaxRhs);
   provision |= ORI_PROVISION_FP64;
-  const Layout lay = layout_for(g->n, provision);
+  const Layout lay = layout_for(g->n, nrhs, provision);
   if (mem_limit_bytes > 0 && lay.total > mem_limit_bytes)
     return set_err(nullptr, ORI_ERR_OUT_OF_MEMORY, "workspace of %lld bytes exceeds the limit of %lld bytes",
                    (long long)lay.total, (long long)mem_limit_bytes);
@@ -497,8 +723,12 @@ ori_status ori_create(const ori_grid* g, int32_t provision, int64_t mem_limit_by
   c->n = g->n;
   c->L = L;
   c->P = g->n * g->n * g->n;
+  c->nrhs = nrhs;
   c->provision = provision;
   c->K = K;
+  c->u0norm2.assign(nrhs, 0.0);
+  c->bnorm2.assign(nrhs, 0.0);
+  choose_layout(c);
   c->stream = static_cast<hipStream_t>(stream);
   auto fail = [&](ori_status st) {
     g_last_error = c->err;
@@ -525,49 +755,55 @@ ori_status ori_create(const ori_grid* g, int32_t provision, int64_t mem_limit_by
   };
   ori_status st = ORI_OK;
   void* v = nullptr;
-#define ORI_ALLOC(bytes, dst, type)                 \
-  do {                                              \
-    st = alloc((bytes), &v);                        \
-    if (st != ORI_OK) return fail(st);              \
-    dst = static_cast<type>(v);                     \
+  const bool mixed = provision & ORI_PROVISION_MIXED;
+  const int64_t R = nrhs;
+#define ORI_ALLOC(bytes, dst, type)    \
+  do {                                 \
+    st = alloc((bytes), &v);           \
+    if (st != ORI_OK) return fail(st); \
+    dst = static_cast<type>(v);        \
   } while (0)
   ORI_ALLOC(lay.arena, c->arena, void*);
   ORI_ALLOC(lay.vec_d, c->D, cxd*);
   ORI_ALLOC(lay.vec_d, c->S, cxd*);
-  ORI_ALLOC(lay.vec_d, c->b, cxd*);
-  ORI_ALLOC(lay.vec_d, c->u0, cxd*);
-  ORI_ALLOC(lay.vec_d, c->x, cxd*);
-  ORI_ALLOC(lay.vec_d, c->r, cxd*);
-  ORI_ALLOC(lay.vec_d, c->p, cxd*);
-  ORI_ALLOC(lay.vec_d, c->q, cxd*);
-  if (provision & ORI_PROVISION_MIXED) {
+  ORI_ALLOC(lay.vec_f, c->cN, double*);
+  ORI_ALLOC(lay.vec_d, c->t1, cxd*);
+  ORI_ALLOC(lay.vec_d, c->t2, cxd*);
+  ORI_ALLOC(R * lay.vec_d, c->b, cxd*);
+  ORI_ALLOC(R * lay.vec_d, c->u0, cxd*);
+  ORI_ALLOC(R * lay.vec_d, c->x, cxd*);
+  ORI_ALLOC(R * lay.vec_d, c->r, cxd*);
+  ORI_ALLOC(R * lay.vec_d, c->p, cxd*);
+  ORI_ALLOC(R * lay.vec_d, c->q, cxd*);
+  if (mixed) {
     ORI_ALLOC(lay.vec_f, c->Sf, cxf*);
-    ORI_ALLOC(lay.vec_f, c->xf, cxf*);
-    ORI_ALLOC(lay.vec_f, c->rf, cxf*);
-    ORI_ALLOC(lay.vec_f, c->pf, cxf*);
-    ORI_ALLOC(lay.vec_f, c->qf, cxf*);
+    ORI_ALLOC(R * lay.vec_f, c->xf, cxf*);
+    ORI_ALLOC(R * lay.vec_f, c->rf, cxf*);
+    ORI_ALLOC(R * lay.vec_f, c->pf, cxf*);
+    ORI_ALLOC(R * lay.vec_f, c->qf, cxf*);
     ORI_ALLOC(lay.khf, c->khf, cxf*);
   }
   ORI_ALLOC(lay.kh, c->kh, cxd*);
-  ORI_ALLOC(align_up(L * 16), c->twd, cxd*);
-  ORI_ALLOC(align_up(L * 8), c->twf, cxf*);
-  const int64_t npart = std::max<int64_t>(kRedBlocks, K->contig_blocks(c->n * c->n));
-  c->npartials = npart;
-  ORI_ALLOC(npart * 4 * 8, c->partials, double*);
-  ORI_ALLOC(static_cast<int64_t>(sizeof(ScalarBlock)), c->sc, ScalarBlock*);
+  ORI_ALLOC(align_up(2 * g->n * 16), c->twd, cxd*);
+  ORI_ALLOC(align_up(2 * g->n * 8), c->twf, cxf*);
+  ORI_ALLOC(align_up(lay.npart * 4 * 8), c->partials, double*);
+  ORI_ALLOC(align_up(R * (int64_t)sizeof(ScalarBlock)), c->sc, ScalarBlock*);
+  ORI_ALLOC(align_up(R * 8), c->outer_m, double*);
 #undef ORI_ALLOC
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->sc_host), sizeof(ScalarBlock), hipHostMallocDefault) != hipSuccess) {
-    c->sc_host = nullptr;
-    set_err(c, ORI_ERR_OUT_OF_MEMORY, "hipHostMalloc of the scalar mirror failed");
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->sc_host), R * sizeof(ScalarBlock), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->outer_m_host), R * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess) {
+    set_err(c, ORI_ERR_OUT_OF_MEMORY, "hipHostMalloc of the scalar mirrors failed");
     return fail(ORI_ERR_OUT_OF_MEMORY);
   }
+  std::memset(c->sc_host, 0, R * sizeof(ScalarBlock));
   std::vector<cxd> twd;
   std::vector<cxf> twf;
   fill_twiddles(L, twd, twf);
   if (hipMemcpy(c->twd, twd.data(), L * sizeof(cxd), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->twf, twf.data(), L * sizeof(cxf), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemsetAsync(c->sc, 0, sizeof(ScalarBlock), c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
+      hipMemcpy(c->sc, c->sc_host, R * sizeof(ScalarBlock), hipMemcpyHostToDevice) != hipSuccess) {
     set_err(c, ORI_ERR_DEVICE, "initial copies failed");
     return fail(ORI_ERR_DEVICE);
   }
@@ -578,30 +814,40 @@ ori_status ori_create(const ori_grid* g, int32_t provision, int64_t mem_limit_by
 ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const void* u0) {
   ORI_TRY(guard(c));
   if (!(k > 0.0) || !std::isfinite(k)) return set_err(c, ORI_ERR_INVALID_ARG, "k must be finite and > 0");
-  const int64_t P = c->P;
+  const int64_t P = c->P, R = c->nrhs;
   ORI_TRY(check_dev_ptr(c, h, P * 16, "h"));
   if (N) ORI_TRY(check_dev_ptr(c, N, P * 8, "N"));
-  ORI_TRY(check_dev_ptr(c, u0, P * 16, "u0"));
+  ORI_TRY(check_dev_ptr(c, u0, R * P * 16, "u0"));
   c->loaded = false;
   c->k = k;
   ORI_TRY(compute_spectrum(c));
   const double vol = std::pow(c->grid.side / static_cast<double>(c->n), 3);
+  // operator coefficients: the bad-input count lands in sc[0]
   ORI_TRY(launch(c, K_COEFF, PREC_F64, [&] {
-    return launch_coefficients(h, N, u0, vol, P, c->D, c->S, c->Sf, c->b, c->u0, c->partials, c->stream);
+    return launch_coefficients(h, N, vol, P, c->D, c->S, c->Sf, c->cN, c->partials, c->stream);
   }));
-  ORI_TRY(finalize(c, kRedBlocks, FIN_SETUP));
+  ORI_HIP(c, hipMemsetAsync(c->sc, 0, R * sizeof(ScalarBlock), c->stream));
+  ORI_TRY(launch(c, K_FINALIZE, PREC_F64, [&] {
+    return launch_finalize(c->partials, rblocks(c), 1, c->sc, FIN_BAD, kBreakdownEps, 0.0, 0, c->stream);
+  }));
   ORI_TRY(sync_scalars(c));
-  if (c->sc_host->flags & FLAG_BAD_INPUT)
-    return set_err(c, ORI_ERR_INVALID_ARG, "h, N or u0 holds NaN/Inf, or N < 0");
-  c->bnorm2 = c->sc_host->bb;
-  c->u0norm2 = c->sc_host->aux;
+  if (c->sc_host[0].flags & FLAG_BAD_INPUT) return set_err(c, ORI_ERR_INVALID_ARG, "h or N holds NaN/Inf, or N < 0");
+  ORI_TRY(launch(c, K_COEFF, PREC_F64, [&] { return launch_rhs(u0, c->S, P, R, c->b, c->u0, c->partials, c->stream); }));
+  ORI_TRY(finalize(c, rblocks(c), FIN_SETUP));
+  ORI_TRY(sync_scalars(c));
+  for (int64_t i = 0; i < R; ++i) {
+    if (c->sc_host[i].flags & FLAG_BAD_INPUT)
+      return set_err(c, ORI_ERR_INVALID_ARG, "u0 (right-hand side %lld) holds NaN/Inf", (long long)i);
+    c->bnorm2[i] = c->sc_host[i].bb;
+    c->u0norm2[i] = c->sc_host[i].aux;
+  }
   c->loaded = true;
   return ORI_OK;
 }
 
 ori_status ori_setup(const ori_grid* g, double k, const void* h, const double* N, const void* u0, void* stream,
                      ori_ctx* out) {
-  ORI_TRY(ori_create(g, ORI_PROVISION_FP64 | ORI_PROVISION_MIXED, 0, stream, out));
+  ORI_TRY(ori_create(g, 1, ORI_PROVISION_FP64 | ORI_PROVISION_MIXED, 0, stream, out));
   ori_status st = ori_load(*out, k, h, N, u0);
   if (st != ORI_OK) {
     g_last_error = (*out)->err;
@@ -617,8 +863,8 @@ ori_status ori_matvec(ori_ctx c, int32_t op, int32_t precision, const void* x, v
   if (precision != ORI_FP64 && precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
   if (precision == ORI_MIXED && !(c->provision & ORI_PROVISION_MIXED))
     return set_err(c, ORI_ERR_INVALID_ARG, "complex64 workspaces were not provisioned");
-  ORI_TRY(check_dev_ptr(c, x, c->P * 16, "x"));
-  ORI_TRY(check_dev_ptr(c, y, c->P * 16, "y"));
+  ORI_TRY(check_dev_ptr(c, x, c->nrhs * c->P * 16, "x"));
+  ORI_TRY(check_dev_ptr(c, y, c->nrhs * c->P * 16, "y"));
   const int fp = precision == ORI_MIXED ? PREC_F32 : PREC_F64;
   ContigFwdArgs f1;
   ContigInvArgs i1;
@@ -646,117 +892,103 @@ ori_status ori_matvec(ori_ctx c, int32_t op, int32_t precision, const void* x, v
 ori_status ori_solve(ori_ctx c, const ori_solve_opts* opts_in, void* u_out, ori_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
   ORI_TRY(guard(c));
-  if (!c->loaded) return set_err(c, ORI_ERR_INVALID_ARG, "ori_load has not succeeded on this context");
   ori_solve_opts o;
-  if (opts_in)
-    o = *opts_in;
-  else
-    ori_default_opts(&o);
-  if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return set_err(c, ORI_ERR_INVALID_ARG, "tol must be finite and >= 0");
-  if (o.max_iter < 0) return set_err(c, ORI_ERR_INVALID_ARG, "max_iter must be >= 0");
-  if (o.precision != ORI_FP64 && o.precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
-  if (o.precision == ORI_MIXED && !(c->provision & ORI_PROVISION_MIXED))
-    return set_err(c, ORI_ERR_INVALID_ARG, "complex64 workspaces were not provisioned");
-  if (o.check_every < 0) return set_err(c, ORI_ERR_INVALID_ARG, "check_every must be >= 0");
-  const int check_every = o.check_every == 0 ? 1 : o.check_every;
-  const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol : 1e-5;
-  if (!std::isfinite(inner_tol) || inner_tol >= 1.0) return set_err(c, ORI_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
-  const int max_outer = o.max_outer > 0 ? o.max_outer : 10;
-  ORI_TRY(check_dev_ptr(c, u_out, c->P * 16, "u"));
-  cxd* u = static_cast<cxd*>(u_out);
-  const int64_t P = c->P;
-
-  ori_solve_info inf{};
-  inf.rel_res_true = -1.0;
-  const double bb = c->bnorm2;
-  const double rr_target = o.tol * o.tol * bb;
-  bool breakdown = false, converged = false;
-
-  // initial residual r = b - A_sym x0
-  if (o.use_x0) {
-    ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_mul(c->S, u, c->x, P, c->stream); }));
-    ORI_TRY(true_residual_sym(c, c->x, c->r));
-    inf.matvecs++;
-  } else {
-    ORI_TRY(launch(c, K_INIT, PREC_F64, [&] { return launch_init(PREC_F64, c->b, 1.0, c->x, c->r, P, c->partials, c->stream); }));
-    ORI_TRY(finalize(c, kRedBlocks, FIN_INIT));
-  }
-
-  if (o.precision == ORI_FP64) {
-    CocgOut co;
-    ORI_TRY(run_cocg(c, PREC_F64, c->x, c->r, c->p, c->q, c->S, rr_target, o.max_iter, check_every, &co));
-    inf.iterations = co.iters;
-    inf.matvecs += co.matvecs;
-    inf.rel_res_recursive = bb > 0 ? std::sqrt(co.rr / bb) : 0.0;
-    converged = co.converged;
-    breakdown = !converged && (co.flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU));
-  } else {
-    // iterative refinement: FP64 true residual, complex64 inner COCG on the correction
-    ORI_TRY(sync_scalars(c));
-    double rr = c->sc_host->rr;
-    int flags = c->sc_host->flags;
-    if (flags & FLAG_BREAKDOWN_RHO) breakdown = true;
-    int inner_left = o.max_iter;
-    for (int outer = 0; !breakdown; ++outer) {
-      if (rr <= rr_target || (flags & FLAG_ZERO_RESIDUAL)) {
-        converged = true;
-        break;
-      }
-      if (outer >= max_outer || inner_left <= 0) break;
-      const double scale = 1.0 / std::sqrt(rr);
-      ORI_TRY(launch(c, K_INIT, PREC_F32,
-                     [&] { return launch_init(PREC_F32, c->r, scale, c->xf, c->rf, P, c->partials, c->stream); }));
-      ORI_TRY(finalize(c, kRedBlocks, FIN_INIT));
-      CocgOut co;
-      ORI_TRY(run_cocg(c, PREC_F32, c->xf, c->rf, c->pf, c->qf, c->Sf, inner_tol * inner_tol, inner_left,
-                       check_every, &co));
-      inner_left -= co.iters;
-      inf.iterations += co.iters;
-      inf.matvecs += co.matvecs;
-      inf.matvecs_c64 += co.matvecs;
-      if (co.iters == 0 && (co.flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU))) {
-        breakdown = true;
-        break;
-      }
-      ORI_TRY(launch(c, K_ELEMWISE, PREC_F32,
-                     [&] { return launch_axpy_d(PREC_F32, 1.0 / scale, c->xf, c->x, P, c->stream); }));
-      ORI_TRY(true_residual_sym(c, c->x, c->r));
-      inf.matvecs++;
-      inf.refinements++;
-      ORI_TRY(sync_scalars(c));
-      rr = c->sc_host->rr;
-      flags = c->sc_host->flags & ~(FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU);
-    }
-    inf.rel_res_recursive = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-  }
-
-  ORI_TRY(recover(c, c->x, u));
-  inf.matvecs++;
-  if (o.true_residual) {
-    ORI_TRY(true_residual_orig(c, u, &inf.rel_res_true));
-    inf.matvecs++;
-  }
+  ORI_TRY(check_opts(c, opts_in, &o));
+  ORI_TRY(check_dev_ptr(c, u_out, c->nrhs * c->P * 16, "u"));
+  Outcome oc;
+  ORI_TRY(forward_solve(c, o, static_cast<cxd*>(u_out), &oc));
   ORI_HIP(c, hipStreamSynchronize(c->stream));
-  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (info) *info = inf;
-  if (breakdown) return set_err(c, ORI_ERR_BREAKDOWN, "COCG breakdown after %d iterations", inf.iterations);
-  if (!converged)
-    return set_err(c, ORI_ERR_NOT_CONVERGED, "not converged: relative residual %.3e after %d iterations",
-                   inf.rel_res_recursive, inf.iterations);
+  const double secs = elapsed(t0);
+  for (auto& i : oc.info) i.seconds = secs;
+  c->last_info = oc.info;
+  if (info) {
+    *info = aggregate(oc);
+    info->seconds = secs;
+  }
+  return end_status(c, oc, "COCG");
+}
+
+ori_status ori_batch_info(ori_ctx c, int32_t i, ori_solve_info* info) {
+  if (!c) return set_err(nullptr, ORI_ERR_INVALID_ARG, "context is NULL");
+  if (!info) return set_err(c, ORI_ERR_INVALID_ARG, "info is NULL");
+  if (i < 0 || i >= static_cast<int32_t>(c->last_info.size()))
+    return set_err(c, ORI_ERR_INVALID_ARG, "no solve result for right-hand side %d", i);
+  *info = c->last_info[i];
   return ORI_OK;
+}
+
+ori_status ori_adjoint(ori_ctx c, const ori_solve_opts* opts_in, const void* u_in, const void* f_in, void* g_out,
+                       void* lam_out, ori_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  ORI_TRY(guard(c));
+  if (c->nrhs != 1) return set_err(c, ORI_ERR_UNSUPPORTED, "the adjoint needs a context with one right-hand side");
+  ori_solve_opts o;
+  ORI_TRY(check_opts(c, opts_in, &o));
+  o.use_x0 = 0;
+  ORI_TRY(check_dev_ptr(c, u_in, c->P * 16, "u"));
+  ORI_TRY(check_dev_ptr(c, f_in, c->P * 16, "f"));
+  if (!g_out && !lam_out) return set_err(c, ORI_ERR_INVALID_ARG, "g and lam are both NULL");
+  if (g_out) ORI_TRY(check_dev_ptr(c, g_out, c->P * 16, "g"));
+  if (lam_out) ORI_TRY(check_dev_ptr(c, lam_out, c->P * 16, "lam"));
+  Outcome oc;
+  ORI_TRY(adjoint_solve(c, o, static_cast<const cxd*>(u_in), static_cast<const cxd*>(f_in), 1.0,
+                        static_cast<cxd*>(g_out), static_cast<cxd*>(lam_out), &oc));
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    *info = oc.info[0];
+    info->seconds = elapsed(t0);
+  }
+  return end_status(c, oc, "adjoint COCG");
+}
+
+ori_status ori_gradient(ori_ctx c, const ori_solve_opts* opts_in, const void* target, void* u_out, double* J,
+                        void* g_out, ori_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  ORI_TRY(guard(c));
+  if (c->nrhs != 1) return set_err(c, ORI_ERR_UNSUPPORTED, "the gradient needs a context with one right-hand side");
+  ori_solve_opts o;
+  ORI_TRY(check_opts(c, opts_in, &o));
+  ORI_TRY(check_dev_ptr(c, target, c->P * 16, "u_target"));
+  ORI_TRY(check_dev_ptr(c, u_out, c->P * 16, "u"));
+  ORI_TRY(check_dev_ptr(c, g_out, c->P * 16, "dJdh"));
+  if (!J) return set_err(c, ORI_ERR_INVALID_ARG, "J is NULL");
+  cxd* u = static_cast<cxd*>(u_out);
+  Outcome fw;
+  ORI_TRY(forward_solve(c, o, u, &fw));
+  ori_solve_info inf = fw.info[0];
+  if (fw.state[0] != 0) {
+    ORI_HIP(c, hipStreamSynchronize(c->stream));
+    inf.seconds = elapsed(t0);
+    if (info) *info = inf;
+    return end_status(c, fw, "forward COCG");
+  }
+  // f = conj(u - t) (in t2), J = ||u - t||^2
+  ORI_TRY(launch(c, K_ELEMWISE, PREC_F64,
+                 [&] { return launch_conj_diff(u, target, c->t2, c->P, c->partials, c->stream); }));
+  ORI_TRY(finalize(c, rblocks(c), FIN_NORM));
+  ORI_TRY(sync_scalars(c));
+  *J = c->sc_host[0].aux;
+  o.use_x0 = 0;
+  Outcome ad;
+  ORI_TRY(adjoint_solve(c, o, u, c->t2, 2.0, static_cast<cxd*>(g_out), nullptr, &ad));
+  inf.iterations += ad.info[0].iterations;
+  inf.refinements += ad.info[0].refinements;
+  inf.matvecs += ad.info[0].matvecs;
+  inf.matvecs_c64 += ad.info[0].matvecs_c64;
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  inf.seconds = elapsed(t0);
+  if (info) *info = inf;
+  return end_status(c, ad, "adjoint COCG");
 }
 
 ori_status ori_profile_enable(ori_ctx c, int32_t enable) {
   ORI_TRY(guard(c));
+  ORI_TRY(prof_fold(c));
   if (enable) {
-    ORI_TRY(prof_fold(c));
     std::fill(std::begin(c->prof_ms), std::end(c->prof_ms), 0.0);
     std::fill(std::begin(c->prof_n), std::end(c->prof_n), 0);
-    c->prof = true;
-  } else {
-    ORI_TRY(prof_fold(c));
-    c->prof = false;
   }
+  c->prof = enable != 0;
   return ORI_OK;
 }
 
@@ -765,10 +997,10 @@ ori_status ori_profile_read(ori_ctx c, int32_t max, const char** names, double* 
   ORI_TRY(guard(c));
   ORI_TRY(prof_fold(c));
   static const char* const full[2 * K_NKIND] = {
-      "f1.c128", "f1.c64", "f2.c128", "f2.c64", "zpass.c128", "zpass.c64", "i2.c128", "i2.c64",
-      "i1.c128", "i1.c64", "update.c128", "update.c64", "finalize", "finalize.c64", "init.c128", "init.c64",
-      "coefficients", "coefficients.c64", "embed", "embed.c64", "spectrum_fft", "spectrum_fft.c64",
-      "octant", "octant.c64", "elementwise.c128", "elementwise.c64"};
+      "f1.c128",          "f1.c64",          "f2.c128",      "f2.c64",          "zpass.c128",       "zpass.c64",
+      "i2.c128",          "i2.c64",          "i1.c128",      "i1.c64",          "update.c128",      "update.c64",
+      "finalize",         "finalize.c64",    "init.c128",    "init.c64",        "coefficients",     "coefficients.c64",
+      "spectrum",         "spectrum.c64",    "elementwise.c128", "elementwise.c64"};
   int w = 0;
   for (int s = 0; s < 2 * K_NKIND; ++s) {
     if (c->prof_n[s] == 0) continue;
@@ -786,11 +1018,14 @@ ori_status ori_profile_read(ori_ctx c, int32_t max, const char** names, double* 
 void ori_destroy(ori_ctx c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  else (void)hipDeviceSynchronize();
+  if (c->stream)
+    (void)hipStreamSynchronize(c->stream);
+  else
+    (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
+  if (c->outer_m_host) (void)hipHostFree(c->outer_m_host);
   delete c;
 }
 

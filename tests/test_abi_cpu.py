@@ -49,8 +49,7 @@ def test_version_and_defaults():
 @pytest.mark.parametrize("n", [1, 2, 3, 16, 64, 128, 256, 512])
 def test_workspace_bytes_supported(n):
     b = ori.ori_workspace_bytes(n)
-    L = 2 * n
-    assert b >= (L ** 3) * 16 + 8 * n ** 3 * 16
+    assert b >= 6 * n ** 3 * 16 + 8 * n ** 3 * 16
     # FP64-only provisioning is smaller
     assert ori.ori_workspace_bytes(n, ori.ORI_PROVISION_FP64) < b
 
@@ -59,6 +58,9 @@ def test_workspace_bytes_metric_size_fits_hbm():
     # n = 256 (16.8 M unknowns): a few GB; n = 512 stays far below 288 GB
     assert ori.ori_workspace_bytes(256) < 8e9
     assert ori.ori_workspace_bytes(512) < 60e9
+    # a batch of 32 right-hand sides at n = 64 shares the operator buffers
+    one, many = ori.ori_workspace_bytes(64), ori.ori_workspace_bytes(64, nrhs=32)
+    assert one < many < 32 * one
 
 
 @pytest.mark.parametrize("n,status", [(0, ori.ORI_ERR_INVALID_ARG), (-3, ori.ORI_ERR_INVALID_ARG),
@@ -75,12 +77,15 @@ def test_bad_side_and_null_grid():
     lib = ori.lib()
     g = ori._grid(8, side=float("nan"))
     out = ctypes.c_int64()
-    assert lib.ori_workspace_bytes(ctypes.byref(g), 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
-    assert lib.ori_workspace_bytes(None, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_workspace_bytes(ctypes.byref(g), 1, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_workspace_bytes(None, 1, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
     g = ori._grid(8, side=-1.0)
-    assert lib.ori_workspace_bytes(ctypes.byref(g), 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_workspace_bytes(ctypes.byref(g), 1, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
     g = ori._grid(8, origin=(0.0, float("inf"), 0.0))
-    assert lib.ori_workspace_bytes(ctypes.byref(g), 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_workspace_bytes(ctypes.byref(g), 1, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    g = ori._grid(8)
+    assert lib.ori_workspace_bytes(ctypes.byref(g), 0, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_workspace_bytes(ctypes.byref(g), 4096, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
 
 
 def test_memory_limit_rejected_before_any_device_call():
@@ -88,7 +93,7 @@ def test_memory_limit_rejected_before_any_device_call():
     lib = ori.lib()
     h = ctypes.c_void_p()
     g = ori._grid(512)
-    st = lib.ori_create(ctypes.byref(g), 3, 1 << 30, None, ctypes.byref(h))
+    st = lib.ori_create(ctypes.byref(g), 1, 3, 1 << 30, None, ctypes.byref(h))
     assert st == ori.ORI_ERR_OUT_OF_MEMORY
     assert h.value is None
     assert "exceeds the limit" in ori.ori_last_error()
@@ -101,7 +106,8 @@ def test_null_context_calls_fail_cleanly():
     assert lib.ori_matvec(None, 0, 0, None, None) == ori.ORI_ERR_INVALID_ARG
     assert lib.ori_profile_enable(None, 1) == ori.ORI_ERR_INVALID_ARG
     lib.ori_destroy(None)
-    assert lib.ori_create(None, 3, 0, None, None) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_create(None, 1, 3, 0, None, None) == ori.ORI_ERR_INVALID_ARG
+    assert lib.ori_batch_info(None, 0, None) == ori.ORI_ERR_INVALID_ARG
 
 
 def test_no_oracle_in_product_path():

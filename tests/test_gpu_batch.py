@@ -1,0 +1,127 @@
+"""Batches of right-hand sides sharing one operator, through the C ABI."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1602_04691_amd as ori  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def fields(n, k, dirs):
+    return np.stack([workloads.plane_wave(n, k, d) for d in dirs])
+
+
+def test_batch_equals_single_solves_bitwise():
+    n, k = 8, 5.0
+    say("[batch == single] n=8, 4 rhs")
+    case = workloads.make_case(n, k, seed=4)
+    U0 = fields(n, k, workloads.fibonacci_directions(4))
+    hg, Ng = gpu(case["h"]), gpu(case["N"])
+    with ori.ori_create(n, nrhs=4) as ctx:
+        ori.ori_load(ctx, k, hg, Ng, gpu(U0.reshape(-1)))
+        ub = torch.empty(4 * n ** 3, dtype=torch.complex128, device="cuda")
+        _, agg = ori.ori_solve(ctx, ub, tol=1e-11)
+        per = [ori.ori_batch_info(ctx, i) for i in range(4)]
+        # the product of a batch equals the single products too
+        xb = gpu(U0.reshape(-1) * 1.5)
+        yb = torch.empty_like(xb)
+        ori.ori_matvec(ctx, xb, yb, ori.ORI_OP_SYMMETRIC)
+    ub = ub.cpu().numpy().reshape(4, -1)
+    yb = yb.cpu().numpy().reshape(4, -1)
+    for i in range(4):
+        with ori.ori_setup(n, k, hg, Ng, gpu(U0[i])) as c1:
+            u1 = torch.empty(n ** 3, dtype=torch.complex128, device="cuda")
+            _, info1 = ori.ori_solve(c1, u1, tol=1e-11)
+            y1 = torch.empty_like(u1)
+            ori.ori_matvec(c1, gpu(U0[i] * 1.5), y1, ori.ORI_OP_SYMMETRIC)
+        assert np.array_equal(ub[i], u1.cpu().numpy()), i
+        assert np.array_equal(yb[i], y1.cpu().numpy()), i
+        assert per[i]["iterations"] == info1["iterations"]
+    assert agg["iterations"] == max(p["iterations"] for p in per)
+
+
+@pytest.mark.parametrize("prec", [ori.ORI_FP64, ori.ORI_MIXED])
+def test_batch_vs_lu(prec):
+    n, k, R = 8, 4.0, 5
+    say(f"[batch vs LU] prec={prec}")
+    case = workloads.make_case(n, k, seed=7)
+    U0 = fields(n, k, workloads.fibonacci_directions(R))
+    pts = O.cell_points(n)
+    D = O.coupling(case["h"], case["N"], n)
+    Uref = O.solve_direct(O.system_matrix(pts, k, D), U0.T).T
+    with ori.ori_create(n, nrhs=R) as ctx:
+        ori.ori_load(ctx, k, gpu(case["h"]), gpu(case["N"]), gpu(U0.reshape(-1)))
+        ub = torch.empty(R * n ** 3, dtype=torch.complex128, device="cuda")
+        tol = 1e-12 if prec == ori.ORI_FP64 else 1e-9
+        _, info = ori.ori_solve(ctx, ub, tol=tol, precision=prec)
+    U = ub.cpu().numpy().reshape(R, -1)
+    bar = 1e-10 if prec == ori.ORI_FP64 else 1e-6
+    for i in range(R):
+        assert rel(U[i], Uref[i]) <= bar, (i, rel(U[i], Uref[i]))
+
+
+def test_config2_fibonacci_block_mixed_reciprocity():
+    # n = 64, k = 5, 32 incident directions on a Fibonacci sphere solved as one
+    # block with complex64 products and FP64 refinement (tol 1e-8).  No dense
+    # oracle at this size: reciprocity F_ij = u0_j^T D u_i = F_ji, and sampled
+    # true-residual rows of two right-hand sides from the oracle.
+    n, k, R = 64, 5.0, 32
+    say("[config2] n=64 x 32 rhs")
+    case = workloads.make_case(n, k, seed=2)
+    dirs = workloads.fibonacci_directions(R)
+    U0 = fields(n, k, dirs)
+    with ori.ori_create(n, nrhs=R) as ctx:
+        ori.ori_load(ctx, k, gpu(case["h"]), gpu(case["N"]), gpu(U0.reshape(-1)))
+        ub = torch.empty(R * n ** 3, dtype=torch.complex128, device="cuda")
+        _, info = ori.ori_solve(ctx, ub, tol=1e-8, precision=ori.ORI_MIXED)
+        say(f"   inner={info['iterations']} refinements={info['refinements']} true={info['rel_res_true']:.2e}")
+        assert info["rel_res_true"] < 1e-7
+        ub64 = torch.empty_like(ub)
+        _, i64 = ori.ori_solve(ctx, ub64, tol=1e-8)
+    U = ub.cpu().numpy().reshape(R, -1)
+    U64 = ub64.cpu().numpy().reshape(R, -1)
+    assert rel(U, U64) <= 1e-6
+    D = O.coupling(case["h"], case["N"], n)
+    F = U0 @ (D[None, :] * U).T          # F[j, i] = u0_j^T D u_i
+    asym = np.max(np.abs(F - F.T)) / np.max(np.abs(F))
+    say(f"   reciprocity asymmetry {asym:.2e}")
+    assert asym <= 1e-7
+    pts = O.cell_points(n)
+    rows = np.array([0, 4321, n ** 3 - 1])
+    for i in (0, R - 1):
+        r = O.sample_residual_rows(pts, k, D, U[i], U0[i], rows)
+        assert np.linalg.norm(r) / np.linalg.norm(U0[i][rows]) <= 1e-7
+
+
+def test_uneven_batch_of_independent_problems():
+    # four problems of different sizes solved concurrently on their own
+    # streams; each result equals its sequential solve bit for bit
+    say("[uneven] n in {32, 48, 64, 96}")
+    probs = []
+    for j, n in enumerate((32, 48, 64, 96)):
+        c = workloads.make_case(n, 5.0, seed=20 + j)
+        probs.append(dict(n=n, k=5.0, h=gpu(c["h"]), N=gpu(c["N"]), u0=gpu(c["u0"])))
+    results = ori.solve_many(probs, tol=1e-8, precision=ori.ORI_MIXED)
+    for p, (u, info) in zip(probs, results):
+        u_seq, info_seq = ori.solve(p["n"], p["k"], p["h"], p["N"], p["u0"], tol=1e-8, precision=ori.ORI_MIXED)
+        assert torch.equal(u, u_seq), p["n"]
+        assert info["rel_res_true"] < 1e-7
