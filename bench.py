@@ -275,10 +275,12 @@ def main():
         log(f"[bench] cpu oracle: {len(rows)} rows in {dt:.1f}s -> {rate:.3e} matvecs/s; GPU err {err:.2e}")
 
     if a.calib_copy_mib > 0:
-        src = torch.empty(a.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        # a plain streaming kernel of known traffic (reads and writes exactly
+        # calib_copy_mib MiB) to scale the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.ones(a.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
 
     ctx.close()

@@ -197,13 +197,21 @@ struct Stages {
   static constexpr int cnt(int s) { return (nbf(s) + TPP - 1) / TPP; }  // per thread
 };
 
-// One thread's view of its pencil in LDS: element e lives at base[e * ES].
+// One thread's view of its pencil in LDS.  Strided passes interleave NP
+// pencils element by element (element e at base[e * es], es = NP): every
+// LDS access of a wavefront is then a run of NP consecutive slots.  Contiguous
+// passes keep each pencil in one row with one padding slot after every 8
+// elements (element e at base[e + e / 8]), which breaks the power-of-two
+// strides of the Stockham writes across the LDS banks.
 template <typename T>
 struct LdsPencil {
   cx<T>* base;
-  int es;
-  __device__ __forceinline__ cx<T>& at(int e) const { return base[e * es]; }
+  int es;  // 0: padded contiguous row; otherwise the interleave stride
+  __device__ __forceinline__ cx<T>& at(int e) const { return es ? base[e * es] : base[e + (e >> 3)]; }
 };
+
+// LDS slots of one padded contiguous pencil row
+constexpr int padded_row(int L) { return L + L / 8; }
 
 enum Keep : int { KEEP_ALL = 0, KEEP_HALF = 1, KEEP_HALF1 = 2 };
 
@@ -222,6 +230,24 @@ struct Engine {
   template <int s>
   using RegsOf = Regs<T, St::cnt(s), St::radix(s)>;
 
+  // Twiddles w^r, r = 1..R-1, of butterfly b in stage s, w = exp(-2 pi i k / (Ns R)),
+  // k = b mod Ns: the powers r = 1, 2, 4, 8 come from the table, the others
+  // are products of two of them (a few ulps), which cuts the table loads from
+  // R - 1 to log2 R per butterfly.
+  template <int R, int TS>
+  __device__ __forceinline__ static void twiddles(cx<T> (&w)[R], int k, const cx<T>* __restrict__ tw) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      if ((r & (r - 1)) == 0) {
+        w[r] = tw[r * k * TS];
+      } else {
+        const int low = r & -r;
+        const cx<T> a = w[r - low], c = w[low];
+        w[r] = cx<T>{a.re * c.re - a.im * c.im, a.re * c.im + a.im * c.re};
+      }
+    }
+  }
+
   // twiddle + butterfly of stage s, in registers
   template <int s, bool HALF_IN>
   __device__ __forceinline__ static void compute(RegsOf<s>& g, int bt, const cx<T>* __restrict__ tw) {
@@ -234,8 +260,10 @@ struct Engine {
       if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
       if constexpr (NSs > 1) {
         const int k = b % NSs;
+        cx<T> w[R];
+        twiddles<R, TS>(w, k, tw);
 #pragma unroll
-        for (int r = 1; r < R; ++r) g.v[i][r] = twiddle<INV>(g.v[i][r], tw[r * k * TS]);
+        for (int r = 1; r < R; ++r) g.v[i][r] = twiddle<INV>(g.v[i][r], w[r]);
       }
       if constexpr (HALF_IN && s == 0 && (R % 2 == 0)) {
         Dft<INV, R, T>::run_half(g.v[i]);

@@ -95,7 +95,7 @@ struct StridedArgs {
   int32_t in_lg, out_lg;
   int64_t in_hi, in_lo, in_axis;
   int64_t out_hi, out_lo, out_axis;
-  int32_t inverse, half_in, half_out, pad;
+  int32_t inverse, half_in, half_out, np_sel;  // np_sel: 0 wide tiles, 1 narrow tiles
   const void* tw;
 };
 
@@ -105,32 +105,34 @@ struct StridedArgs {
 //   rhs * batch_stride + (i1 >> e_lg) * e_hi + (i1 & (2^e_lg - 1)) * e_lo + k2 * o_stride + k3
 // i.e. i1 is split into blocks of 2^e_lg rows stored next to each other, so
 // that one pencil of the Z pass spans n / 2^e_lg far-apart regions instead
-// of n.  The spectrum is stored as its octant [0..n]^3 (it is even along
-// every axis); zmap = 1 gives each workgroup a tile of octant rows (m2, m3)
-// and all (up to four) pencils (k2, k3) in {m2, L-m2} x {m3, L-m3} that
-// share them, for every right-hand side, so the octant is read from HBM once
-// per pass.
+// of n.  The spectrum is even along every axis; it is stored for
+// m1, m2 in [0..n] and all k3: khat[(m1 * kp + m2) * L + k3], kp = n + 1, so
+// a tile of consecutive k3 is one aligned run.
 struct ZArgs {
   void* buf;
   int64_t n;
-  int32_t e_lg, zmap;
+  int32_t e_lg, np_sel;  // np_sel: 0 wide tiles, 1 narrow tiles
   int64_t e_hi, e_lo, o_stride;
   int64_t nrhs, batch_stride;
-  const void* khat;     // octant [0..n]^3 of the spectrum (T), pitch kp = n + 1
+  int32_t prefetch, pad2;  // 1: load the next tile while transforming the current one
+  const void* khat;     // spectrum (T), [n+1][n+1][L]
   int64_t kp;
   const void* tw;
 };
 
-// Kernel spectrum on its octant, in place on kh[(m1 kp + m2) kp + m3],
-// kp = n + 1 (the Green's table of the padded grid is even along every axis,
-// so are its transforms, and [0..n] per axis determines everything):
+// Kernel spectrum: passes 1 and 2 in place on an octant scratch
+// kh[(m1 kp + m2) kp + m3], kp = n + 1 (the Green's table of the padded grid
+// is even along every axis, so are its transforms, and [0..n] per axis
+// determines everything); pass 3 writes the Z-pass layout kout (ZArgs):
 //   pass 1: generate the table along m3 for (m1, m2) in [0..n]^2, forward DFT,
 //           keep k3 in [0..n]
 //   pass 2: along m2 for (m1, k3): read [0..n], mirror, DFT, keep [0..n]
-//   pass 3: along m1 for (k2, k3): same, times `scale`; complex64 copy to khf.
+//   pass 3: along m1 for (k2, k3): same, times `scale`, stored at k3 and
+//           L - k3 of kout (complex128) and koutf (complex64, or NULL).
 struct SpectrumArgs {
   void* kh;
-  void* khf;           // pass 3 only, or NULL
+  void* kout;
+  void* koutf;
   double k, spacing, scale;
   int32_t pass, pad;
   const void* tw;      // complex128 twiddles
@@ -144,8 +146,8 @@ struct LengthKernels {
   hipError_t (*strided)(int fprec, const StridedArgs&, hipStream_t);
   hipError_t (*zpass)(int fprec, const ZArgs&, hipStream_t);
   int64_t (*contig_blocks_per_rhs)(int64_t ppr);
-  int64_t (*strided_blocks)(int fprec, int64_t n_outer, int64_t C);
-  int64_t (*zpass_blocks)(int fprec, int64_t n, int zmap);
+  int64_t (*strided_blocks)(int fprec, int np_sel, int64_t n_outer, int64_t C);
+  int64_t (*zpass_blocks)(int fprec, int np_sel, int64_t n);
   hipError_t (*spectrum)(const SpectrumArgs&, hipStream_t);
 };
 

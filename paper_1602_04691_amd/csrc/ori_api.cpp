@@ -83,7 +83,8 @@ struct ori_ctx_s {
   int device = 0;
   const LengthKernels* K = nullptr;
   int blk_lg = 0;  // log2 of the i1 block of the B layout
-  int zmap = 1;    // Z-pass workgroup mapping (ZArgs)
+  int np_sel = 0;  // strided / Z tile width: 0 wide, 1 narrow
+  int zpf = 0;     // Z pass: prefetch the next tile
   std::string err = "no error";
   std::vector<double> u0norm2, bnorm2;     // per right-hand side
   std::vector<ori_solve_info> last_info;  // per right-hand side, last solve
@@ -174,11 +175,13 @@ Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   const int64_t P = n * n * n, kp = n + 1;
   const bool mixed = provision & ORI_PROVISION_MIXED;
   Layout l{};
-  l.arena = align_up(nrhs * 6 * P * 16);  // A (n*n*L) + B (n*L*L), complex128
+  // A (n*n*L) + B (n*L*L) complex128 per right-hand side; also the octant
+  // scratch of the spectrum passes at load time
+  l.arena = align_up(std::max<int64_t>(nrhs * 6 * P, kp * kp * kp) * 16);
   l.vec_d = align_up(P * 16);
   l.vec_f = align_up(P * 8);
-  l.kh = align_up(kp * kp * kp * 16);
-  l.khf = mixed ? align_up(kp * kp * kp * 8) : 0;
+  l.kh = align_up(kp * kp * 2 * n * 16);  // [n+1][n+1][L]
+  l.khf = mixed ? align_up(kp * kp * 2 * n * 8) : 0;
   l.npart = nrhs * std::max<int64_t>(red_blocks(P), n * n);
   const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
   const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
@@ -295,13 +298,14 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   // just more outer rows
   const int lg = c->blk_lg;
   const int64_t Bk = int64_t{1} << lg;
-  StridedArgs f2{A, B, R * n, L, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, 0, tw};
+  const int ns = c->np_sel;
+  StridedArgs f2{A, B, R * n, L, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, ns, tw};
   ORI_TRY(launch(c, K_F2, fprec, [&] { return c->K->strided(fprec, f2, c->stream); }));
 
-  ZArgs z{B, n, lg, c->zmap, L * L * Bk, L, Bk * L, R, n * L * L, kh, n + 1, tw};
+  ZArgs z{B, n, lg, ns, L * L * Bk, L, Bk * L, R, n * L * L, c->zpf, 0, kh, n + 1, tw};
   ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, z, c->stream); }));
 
-  StridedArgs i2{B, A, R * n, L, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, 0, tw};
+  StridedArgs i2{B, A, R * n, L, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};
   ORI_TRY(launch(c, K_I2, fprec, [&] { return c->K->strided(fprec, i2, c->stream); }));
 
   i1.in = A;
@@ -343,10 +347,11 @@ ContigInvArgs epi(void* y, const void* a0, double c0, const void* a1, double c1,
 // ---------------------------------------------------------------------------
 ori_status compute_spectrum(ori_ctx c) {
   const double L = static_cast<double>(c->L);
-  SpectrumArgs a{c->kh, nullptr, c->k, c->grid.side / static_cast<double>(c->n), 1.0 / (L * L * L), 1, 0, c->twd};
-  for (int pass = 1; pass <= 3; ++pass) {
+  // the octant scratch of passes 1-2 lives in the (idle) FFT work arena
+  SpectrumArgs a{c->arena, c->kh, c->khf, c->k, c->grid.side / static_cast<double>(c->n), 1.0 / (L * L * L), 1, 0,
+                 c->twd};
+  for (int pass = 1; pass <= 3; ++pass) {  // 1/L^3 of the inverse DFT is folded in by pass 3
     a.pass = pass;
-    a.khf = pass == 3 ? c->khf : nullptr;  // 1/L^3 of the inverse DFT is folded in by pass 3
     ORI_TRY(launch(c, K_SPEC_FFT, PREC_F64, [&] { return c->K->spectrum(a, c->stream); }));
   }
   return ORI_OK;
@@ -454,16 +459,19 @@ ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel)
   return ORI_OK;
 }
 
-// Layout knobs of the FFT work arrays.  Defaults are the measured best on
-// MI355X; ORI_TUNE_BLK_LG / ORI_TUNE_ZMAP override them for tuning runs.
+// Layout knobs: the i1 blocking of the B work array (ZArgs) and the tile
+// width of the strided passes.  Defaults are the measured best on MI355X;
+// ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF override them for tuning runs.
 void choose_layout(ori_ctx c) {
-  int lg = 4, zmap = 1;
+  int lg = 4, np = 0, pf = 0;
   if (const char* e = std::getenv("ORI_TUNE_BLK_LG")) lg = std::atoi(e);
-  if (const char* e = std::getenv("ORI_TUNE_ZMAP")) zmap = std::atoi(e);
+  if (const char* e = std::getenv("ORI_TUNE_NP")) np = std::atoi(e);
+  if (const char* e = std::getenv("ORI_TUNE_ZPF")) pf = std::atoi(e);
+  c->zpf = pf ? 1 : 0;
   if (lg < 0) lg = 0;
   while (lg > 0 && (c->n % (int64_t{1} << lg)) != 0) --lg;
   c->blk_lg = lg;
-  c->zmap = zmap == 0 ? 0 : 1;
+  c->np_sel = np ? 1 : 0;
 }
 
 ori_status guard(ori_ctx c) {

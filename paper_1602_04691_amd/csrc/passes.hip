@@ -79,7 +79,7 @@ __device__ __forceinline__ int64_t two_level(int64_t o, int lg, int64_t hi, int6
 // ---------------------------------------------------------------------------
 template <typename V, typename T, bool HALF>
 __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
-  __shared__ cx<T> lds[NPC * L];
+  __shared__ cx<T> lds[NPC * padded_row(L)];
   using E = Engine<T, L, false>;
   const int tid = threadIdx.x;
   const int bt = tid % TPP, t = tid / TPP;
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
   };
   typename E::template RegsOf<0> g;
   E::template load_first<HALF>(g, bt, load);
-  LdsPencil<T> lp{lds + t * L, 1};
+  LdsPencil<T> lp{lds + t * padded_row(L), 0};
   E::template run<HALF>(g, bt, lp, tw, [&](auto& gl) {
     E::template store_last<KEEP_ALL>(gl, bt, [&](int e, cx<T> v) {
       if (act) out[ob + e] = v;
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
 // ---------------------------------------------------------------------------
 template <typename V, typename T>
 __global__ void __launch_bounds__(BLOCK_C) k_contig_inv(ContigInvArgs a) {
-  __shared__ cx<T> lds[NPC * L];
+  __shared__ cx<T> lds[NPC * padded_row(L)];
   using E = Engine<T, L, true>;
   const int tid = threadIdx.x;
   const int bt = tid % TPP, t = tid / TPP;
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_inv(ContigInvArgs a) {
   auto load = [&](int e) -> cx<T> { return act ? in[ib + e] : cx<T>{}; };
   typename E::template RegsOf<0> g;
   E::template load_first<false>(g, bt, load);
-  LdsPencil<T> lp{lds + t * L, 1};
+  LdsPencil<T> lp{lds + t * padded_row(L), 0};
   E::template run<false>(g, bt, lp, tw, [&](auto& gl) {
     E::template store_last<KEEP_HALF>(gl, bt, [&](int e, cx<T> c) {
       if (!act) return;
@@ -179,18 +179,28 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_inv(ContigInvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// F2 / I2 / spectrum passes: strided axis, NP adjacent pencils per workgroup
+// F2 / I2: strided axis, NP adjacent pencils per workgroup
 // ---------------------------------------------------------------------------
-template <typename T, bool INV, bool HIN, bool HOUT>
-__global__ void __launch_bounds__(block_s<T>()) k_strided(StridedArgs a) {
-  constexpr int NP = nps<T>();
+// Workgroups go round-robin over the 8 XCDs (workgroup b runs on XCD b % 8,
+// each XCD with its own L2).  xcd_order renumbers them so that each XCD walks
+// one contiguous range of tiles: neighbouring tiles, which share cache lines
+// and spectrum rows, then meet in the same L2.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t G) {
+  constexpr int64_t X = 8;
+  const int64_t q = G / X, r = G % X, x = b % X, j = b / X;
+  return x * q + (x < r ? x : r) + j;
+}
+
+template <typename T, int NP, bool INV, bool HIN, bool HOUT>
+__global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
   __shared__ cx<T> lds[NP * L];
   using E = Engine<T, L, INV>;
   const int tid = threadIdx.x;
   const int t = tid % NP, bt = tid / NP;
   const int64_t CT = (a.C + NP - 1) / NP;
-  const int64_t o = blockIdx.x / CT;
-  const int64_t c = (blockIdx.x % CT) * NP + t;
+  const int64_t w = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t o = w / CT;
+  const int64_t c = (w % CT) * NP + t;
   const bool act = c < a.C;
   const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(a.tw);
   const cx<T>* in = static_cast<const cx<T>*>(a.in);
@@ -210,99 +220,105 @@ __global__ void __launch_bounds__(block_s<T>()) k_strided(StridedArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Z: forward along i1 (n inputs), times the spectrum octant, inverse, keep n
+// Z: forward along i1 (n inputs), times the spectrum, inverse, keep n
 // ---------------------------------------------------------------------------
-// One pencil tile: NP pencils (k2, k3_t) of one workgroup, t = thread's
-// pencil.  kb is the thread's octant offset m2 * kp + m3.
+// The spectrum is even along every axis, so the pencils (k2, k3) and
+// (L - k2, k3) multiply by the same values K(m1, m2, k3), m = min(k, L - k).
+// A workgroup takes the octant row m2 and a tile of NP consecutive k3: it
+// loads its K values once into registers (the shape of the last forward
+// stage, so element e = b + j L/R of the transform meets K(min(e, L-e), m2,
+// k3) in place) and runs the tiles (k2 = m2 | L - m2) x (right-hand sides)
+// one after the other, loading the inputs of the next tile before it
+// transforms the current one.  Every spectrum value is read from HBM once
+// per pass.
 template <typename T>
-__device__ __forceinline__ void z_tile(const ZArgs& a, cx<T>* lds, int t, int bt, bool act, int64_t rhs, int64_t k2,
-                                       int64_t k3, int64_t kb) {
-  constexpr int NP = nps<T>();
+using ZRegs = typename Engine<T, L, false>::template RegsOf<Stages<L, false>::NS - 1>;
+
+template <typename T, int NP, bool PF>
+__global__ void __launch_bounds__(NP * TPP) k_zpass(ZArgs a) {
+  constexpr int n = L / 2;
   using EF = Engine<T, L, false>;
   using EI = Engine<T, L, true>;
   using St = Stages<L, false>;
+  using G0 = typename EF::template RegsOf<0>;
   constexpr int SL = St::NS - 1;
   constexpr int RL = St::radix(SL);
   constexpr int STRIDE = L / RL;
-  const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(a.tw);
+  constexpr int64_t CT = (L + NP - 1) / NP;
+  __shared__ cx<T> lds[NP * L];
+  const int tid = threadIdx.x;
+  const int t = tid % NP, bt = tid / NP;
+  const int64_t w = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t m2 = w / CT;
+  const int64_t k3 = (w % CT) * NP + t;
+  const bool act = k3 < L;
   const cx<T>* __restrict__ kh = static_cast<const cx<T>*>(a.khat);
+  const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(a.tw);
   cx<T>* buf = static_cast<cx<T>*>(a.buf);
-  const int64_t base = rhs * a.batch_stride + k2 * a.o_stride + k3;
+  ZRegs<T> kv;
+#pragma unroll
+  for (int i = 0; i < St::cnt(SL); ++i) {
+    const int b = bt + i * TPP;
+#pragma unroll
+    for (int j = 0; j < RL; ++j) {
+      const int e = b + j * STRIDE;
+      const int m1 = e <= L - e ? e : L - e;
+      const bool ok = act && (St::nbf(SL) % TPP == 0 || b < St::nbf(SL));
+      kv.v[i][j] = ok ? kh[(m1 * a.kp + m2) * L + k3] : cx<T>{};
+    }
+  }
+  const int64_t nvar = (m2 != 0 && m2 != n) ? 2 : 1;  // uniform over the workgroup
+  const int64_t ntile = nvar * a.nrhs;
   const int64_t emask = (int64_t{1} << a.e_lg) - 1;
-  auto addr = [&](int e) -> int64_t { return base + (e >> a.e_lg) * a.e_hi + (e & emask) * a.e_lo; };
-  auto load = [&](int e) -> cx<T> { return act ? buf[addr(e)] : cx<T>{}; };
-  typename EF::template RegsOf<0> g;
-  EF::template load_first<true>(g, bt, load);
+  auto tile_base = [&](int64_t it) -> int64_t {
+    const int64_t rhs = it % a.nrhs;
+    const int64_t k2 = (it / a.nrhs) ? L - m2 : m2;
+    return rhs * a.batch_stride + k2 * a.o_stride + k3;
+  };
+  auto addr = [&](int64_t base, int e) -> int64_t {
+    return base + (e >> a.e_lg) * a.e_hi + (e & emask) * a.e_lo;
+  };
+  auto fetch = [&](G0& g, int64_t it) {
+    const int64_t base = tile_base(it);
+    EF::template load_first<true>(g, bt, [&](int e) -> cx<T> { return act ? buf[addr(base, e)] : cx<T>{}; });
+  };
   LdsPencil<T> lp{lds + t, NP};
-  EF::template run<true>(g, bt, lp, tw, [&](auto& gl) {
-    if (act) {
+  auto transform = [&](G0& g, int64_t it) {
+    const int64_t base = tile_base(it);
+    EF::template run<true>(g, bt, lp, tw, [&](auto& gl) {
 #pragma unroll
       for (int i = 0; i < St::cnt(SL); ++i) {
-        const int b = bt + i * TPP;
-        if (St::nbf(SL) % TPP != 0 && b >= St::nbf(SL)) continue;
 #pragma unroll
-        for (int j = 0; j < RL; ++j) {
-          const int e = b + j * STRIDE;
-          const int m1 = e <= L - e ? e : L - e;
-          gl.v[i][j] = gl.v[i][j] * kh[m1 * a.kp * a.kp + kb];
-        }
+        for (int j = 0; j < RL; ++j) gl.v[i][j] = gl.v[i][j] * kv.v[i][j];
       }
-    }
-    EI::template run<false>(gl, bt, lp, tw, [&](auto& gi) {
-      EI::template store_last<KEEP_HALF>(gi, bt, [&](int e, cx<T> v) {
-        if (act) buf[addr(e)] = v;
+      EI::template run<false>(gl, bt, lp, tw, [&](auto& gi) {
+        EI::template store_last<KEEP_HALF>(gi, bt, [&](int e, cx<T> v) {
+          if (act) buf[addr(base, e)] = v;
+        });
       });
     });
-  });
-}
-
-// zmap 0: workgroup = (k2, tile of NP consecutive k3)
-template <typename T>
-__global__ void __launch_bounds__(block_s<T>()) k_zpass(ZArgs a) {
-  constexpr int NP = nps<T>();
-  __shared__ cx<T> lds[NP * L];
-  const int tid = threadIdx.x;
-  const int t = tid % NP, bt = tid / NP;
-  constexpr int64_t CT = (L + NP - 1) / NP;
-  const int64_t k2 = blockIdx.x / CT;
-  const int64_t k3 = (blockIdx.x % CT) * NP + t;
-  const bool act = k3 < L;
-  const int64_t m2 = k2 <= L - k2 ? k2 : L - k2;
-  const int64_t m3 = act ? (k3 <= L - k3 ? k3 : L - k3) : 0;
-#pragma unroll 1
-  for (int64_t rhs = 0; rhs < a.nrhs; ++rhs) {
-    z_tile<T>(a, lds, t, bt, act, rhs, k2, k3, m2 * a.kp + m3);
     __syncthreads();
-  }
-}
-
-// zmap 1: workgroup = (m2, tile of NP consecutive m3) of the octant; it runs
-// the pencils (m2 | L-m2) x (m3 | L-m3) one after the other, so the octant
-// rows it reads serve up to four pencils from cache.
-template <typename T>
-__global__ void __launch_bounds__(block_s<T>()) k_zpass_octant(ZArgs a) {
-  constexpr int NP = nps<T>();
-  constexpr int n = L / 2;
-  __shared__ cx<T> lds[NP * L];
-  const int tid = threadIdx.x;
-  const int t = tid % NP, bt = tid / NP;
-  constexpr int64_t CT = (n + 1 + NP - 1) / NP;
-  const int64_t m2 = blockIdx.x / CT;
-  const int64_t m3 = (blockIdx.x % CT) * NP + t;
-  const bool in_oct = m3 <= n;
-  const int64_t kb = m2 * a.kp + (in_oct ? m3 : 0);
-  const bool mirror2 = m2 != 0 && m2 != n;
-  const bool mirror3 = m3 != 0 && m3 < n;
+  };
+  if constexpr (PF) {
+    // two register sets in turn: the loads of tile it + 1 are in flight while
+    // tile it is transformed
+    G0 ga, gb;
+    fetch(ga, 0);
 #pragma unroll 1
-  for (int v = 0; v < 4; ++v) {
-    if ((v & 2) && !mirror2) continue;  // uniform over the workgroup
-    const int64_t k2 = (v & 2) ? L - m2 : m2;
-    const int64_t k3 = (v & 1) ? L - m3 : m3;
-    const bool act = in_oct && (!(v & 1) || mirror3);
+    for (int64_t it = 0; it < ntile; it += 2) {
+      if (it + 1 < ntile) fetch(gb, it + 1);
+      transform(ga, it);
+      if (it + 1 < ntile) {
+        if (it + 2 < ntile) fetch(ga, it + 2);
+        transform(gb, it + 1);
+      }
+    }
+  } else {
+    G0 g;
 #pragma unroll 1
-    for (int64_t rhs = 0; rhs < a.nrhs; ++rhs) {
-      z_tile<T>(a, lds, t, bt, act, rhs, k2, k3, kb);
-      __syncthreads();
+    for (int64_t it = 0; it < ntile; ++it) {
+      fetch(g, it);
+      transform(g, it);
     }
   }
 }
@@ -329,7 +345,7 @@ __device__ __forceinline__ cxd green_table(int m1, int m2, int m3, double k, dou
 // pass 1: pencils (m1, m2) in [0..n]^2 along the contiguous m3
 __global__ void __launch_bounds__(BLOCK_C) k_spectrum_first(SpectrumArgs a) {
   constexpr int n = L / 2, kp = n + 1;
-  __shared__ cxd lds[NPC * L];
+  __shared__ cxd lds[NPC * padded_row(L)];
   using E = Engine<double, L, false>;
   const int tid = threadIdx.x;
   const int bt = tid % TPP, t = tid / TPP;
@@ -341,7 +357,7 @@ __global__ void __launch_bounds__(BLOCK_C) k_spectrum_first(SpectrumArgs a) {
   auto load = [&](int e) -> cxd { return act ? green_table(m1, m2, e, a.k, a.spacing) : cxd{}; };
   typename E::template RegsOf<0> g;
   E::template load_first<false>(g, bt, load);
-  LdsPencil<double> lp{lds + t * L, 1};
+  LdsPencil<double> lp{lds + t * padded_row(L), 0};
   E::template run<false>(g, bt, lp, static_cast<const cxd*>(a.tw), [&](auto& gl) {
     E::template store_last<KEEP_HALF1>(gl, bt, [&](int e, cxd v) {
       if (act) kh[pid * kp + e] = v;
@@ -365,7 +381,8 @@ __global__ void __launch_bounds__(block_s<double>()) k_spectrum_strided(Spectrum
   const int64_t axis = a.pass == 2 ? kp : int64_t{kp} * kp;
   const int64_t base = o * ostride + c;
   cxd* kh = static_cast<cxd*>(a.kh);
-  cxf* khf = static_cast<cxf*>(a.khf);
+  cxd* kout = static_cast<cxd*>(a.kout);
+  cxf* koutf = static_cast<cxf*>(a.koutf);
   auto load = [&](int e) -> cxd {
     const int em = e <= n ? e : L - e;  // even sequence: mirror
     return act ? kh[base + em * axis] : cxd{};
@@ -376,12 +393,19 @@ __global__ void __launch_bounds__(block_s<double>()) k_spectrum_strided(Spectrum
   E::template run<false>(g, bt, lp, static_cast<const cxd*>(a.tw), [&](auto& gl) {
     E::template store_last<KEEP_HALF1>(gl, bt, [&](int e, cxd v) {
       if (!act) return;
-      const int64_t i = base + e * axis;
-      if (a.pass == 3) {
-        v = scale(v, a.scale);
-        if (khf) khf[i] = cvt<float>(v);
+      if (a.pass == 2) {
+        kh[base + e * axis] = v;
+        return;
       }
-      kh[i] = v;
+      // pass 3: K(k1 = e, k2 = o, k3 = c) and its mirror k3 -> L - k3
+      v = scale(v, a.scale);
+      const int64_t row = (static_cast<int64_t>(e) * kp + o) * L;
+      kout[row + c] = v;
+      if (koutf) koutf[row + c] = cvt<float>(v);
+      if (c != 0 && c != n) {
+        kout[row + L - c] = v;
+        if (koutf) koutf[row + L - c] = cvt<float>(v);
+      }
     });
   });
 }
@@ -390,8 +414,19 @@ __global__ void __launch_bounds__(block_s<double>()) k_spectrum_strided(Spectrum
 // launchers
 // ---------------------------------------------------------------------------
 
-int64_t strided_blocks(int fprec, int64_t n_outer, int64_t C) {
-  const int np = fprec == PREC_F64 ? nps<double>() : nps<float>();
+// Tile widths: "wide" (nps, 128-byte rows) and "narrow" (half as many pencils
+// per workgroup, twice as many workgroups per CU).
+template <typename T>
+constexpr int np_narrow() {
+  return whole_waves(nps<T>() / 2 > 0 ? nps<T>() / 2 : 1, TPP);
+}
+template <typename T>
+int np_of(int sel) {
+  return sel ? np_narrow<T>() : nps<T>();
+}
+
+int64_t strided_blocks(int fprec, int np_sel, int64_t n_outer, int64_t C) {
+  const int np = fprec == PREC_F64 ? np_of<double>(np_sel) : np_of<float>(np_sel);
   return n_outer * ((C + np - 1) / np);
 }
 
@@ -423,32 +458,37 @@ hipError_t contig_inv(int vp, int fp, const ContigInvArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t strided(int fp, const StridedArgs& a, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(strided_blocks(fp, a.n_outer, a.C)));
-  if (fp == PREC_F64) {
-    const dim3 block(block_s<double>());
-    if (!a.inverse && a.half_in && !a.half_out)
-      hipLaunchKernelGGL((k_strided<double, false, true, false>), grid, block, 0, st, a);
-    else if (a.inverse && !a.half_in && a.half_out)
-      hipLaunchKernelGGL((k_strided<double, true, false, true>), grid, block, 0, st, a);
-    else
-      return hipErrorInvalidValue;
-  } else {
-    const dim3 block(block_s<float>());
-    if (!a.inverse && a.half_in && !a.half_out)
-      hipLaunchKernelGGL((k_strided<float, false, true, false>), grid, block, 0, st, a);
-    else if (a.inverse && !a.half_in && a.half_out)
-      hipLaunchKernelGGL((k_strided<float, true, false, true>), grid, block, 0, st, a);
-    else
-      return hipErrorInvalidValue;
-  }
+template <typename T, int NP>
+hipError_t strided_t(const StridedArgs& a, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(a.n_outer * ((a.C + NP - 1) / NP))), block(NP * TPP);
+  if (!a.inverse && a.half_in && !a.half_out)
+    hipLaunchKernelGGL((k_strided<T, NP, false, true, false>), grid, block, 0, st, a);
+  else if (a.inverse && !a.half_in && a.half_out)
+    hipLaunchKernelGGL((k_strided<T, NP, true, false, true>), grid, block, 0, st, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-int64_t zpass_blocks(int fprec, int64_t n, int zmap) {
-  const int64_t np = fprec == PREC_F64 ? nps<double>() : nps<float>();
-  if (zmap == 1) return (n + 1) * ((n + 1 + np - 1) / np);
-  return (2 * n) * ((2 * n + np - 1) / np);
+hipError_t strided(int fp, const StridedArgs& a, hipStream_t st) {
+  if (fp == PREC_F64)
+    return a.np_sel ? strided_t<double, np_narrow<double>()>(a, st) : strided_t<double, nps<double>()>(a, st);
+  return a.np_sel ? strided_t<float, np_narrow<float>()>(a, st) : strided_t<float, nps<float>()>(a, st);
+}
+
+int64_t zpass_blocks(int fprec, int np_sel, int64_t n) {
+  const int64_t np = fprec == PREC_F64 ? np_of<double>(np_sel) : np_of<float>(np_sel);
+  return (n + 1) * ((2 * n + np - 1) / np);
+}
+
+template <typename T, int NP>
+hipError_t zpass_t(const ZArgs& a, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>((a.n + 1) * ((2 * a.n + NP - 1) / NP))), block(NP * TPP);
+  if (a.prefetch)
+    hipLaunchKernelGGL((k_zpass<T, NP, true>), grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_zpass<T, NP, false>), grid, block, 0, st, a);
+  return hipGetLastError();
 }
 
 hipError_t spectrum(const SpectrumArgs& a, hipStream_t st) {
@@ -468,19 +508,8 @@ hipError_t spectrum(const SpectrumArgs& a, hipStream_t st) {
 
 hipError_t zpass(int fp, const ZArgs& a, hipStream_t st) {
   if (a.n != L / 2) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>(zpass_blocks(fp, a.n, a.zmap)));
-  if (fp == PREC_F64) {
-    if (a.zmap == 1)
-      hipLaunchKernelGGL((k_zpass_octant<double>), grid, dim3(block_s<double>()), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_zpass<double>), grid, dim3(block_s<double>()), 0, st, a);
-  } else {
-    if (a.zmap == 1)
-      hipLaunchKernelGGL((k_zpass_octant<float>), grid, dim3(block_s<float>()), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_zpass<float>), grid, dim3(block_s<float>()), 0, st, a);
-  }
-  return hipGetLastError();
+  if (fp == PREC_F64) return a.np_sel ? zpass_t<double, np_narrow<double>()>(a, st) : zpass_t<double, nps<double>()>(a, st);
+  return a.np_sel ? zpass_t<float, np_narrow<float>()>(a, st) : zpass_t<float, nps<float>()>(a, st);
 }
 
 }  // namespace

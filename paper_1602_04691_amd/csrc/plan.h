@@ -18,8 +18,11 @@ struct RadixPlan {
 };
 
 // The first forward radix is even so that the zero upper half of a padded
-// input is skipped at compile time; few stages (radix 8 / 16) keep the LDS
-// exchanges between stages to a minimum.
+// input is skipped at compile time.  Radix 8 is the sweet spot on gfx950 in
+// complex128: 8 values (32 VGPRs) per butterfly leave room for the spectrum
+// and twiddles of the fused Z pass at 4 waves per SIMD, where radix 16 needs
+// over 200 VGPRs; radix 16 survives only where a single stage is the whole
+// transform (L = 16).
 constexpr RadixPlan radix_plan(int L) {
   switch (L) {
     case 2: return {1, {2, 0, 0, 0}};
@@ -33,16 +36,16 @@ constexpr RadixPlan radix_plan(int L) {
     case 24: return {2, {8, 3, 0, 0}};
     case 32: return {2, {8, 4, 0, 0}};
     case 40: return {2, {8, 5, 0, 0}};
-    case 48: return {2, {16, 3, 0, 0}};
+    case 48: return {3, {8, 2, 3, 0}};
     case 64: return {2, {8, 8, 0, 0}};
-    case 80: return {2, {16, 5, 0, 0}};
+    case 80: return {3, {8, 2, 5, 0}};
     case 96: return {3, {8, 4, 3, 0}};
-    case 128: return {2, {16, 8, 0, 0}};
+    case 128: return {3, {8, 4, 4, 0}};
     case 192: return {3, {8, 8, 3, 0}};
-    case 256: return {2, {16, 16, 0, 0}};
-    case 384: return {3, {16, 8, 3, 0}};
+    case 256: return {3, {8, 8, 4, 0}};
+    case 384: return {4, {8, 4, 4, 3}};
     case 512: return {3, {8, 8, 8, 0}};
-    case 1024: return {3, {16, 8, 8, 0}};
+    case 1024: return {4, {8, 8, 4, 4}};
     default: return {0, {0, 0, 0, 0}};
   }
 }
@@ -50,7 +53,8 @@ constexpr RadixPlan radix_plan(int L) {
 constexpr bool supported_length(int L) { return radix_plan(L).n > 0; }
 
 // Threads per pencil: the smallest butterfly count over the stages, so that
-// no stage leaves threads idle in its widest configuration.
+// no stage leaves threads idle in its widest configuration, capped at one
+// wavefront (longer pencils give each thread several butterflies).
 constexpr int threads_per_pencil(int L) {
   RadixPlan p = radix_plan(L);
   int t = L;
@@ -58,7 +62,7 @@ constexpr int threads_per_pencil(int L) {
     int b = L / p.r[s];
     if (b < t) t = b;
   }
-  return t;
+  return t > 64 ? 64 : t;
 }
 
 constexpr int pow2_floor(int x) {
