@@ -91,6 +91,12 @@ typedef struct {
   double inner_tol;      /* mixed: relative tolerance of each inner solve (0: 1e-5)  */
   int32_t max_outer;     /* mixed: refinement cycles (0: 10)                         */
   int32_t true_residual; /* 1: also compute ||u0 - A u|| / ||u0|| (one extra matvec) */
+  int32_t graph;         /* 1: after the first check_every iterations, run each block
+                            of check_every COCG iterations as one replay of a HIP
+                            graph captured once per context and precision (same
+                            kernels and arguments, so results are bitwise those of
+                            0: one launch per kernel).  Ignored while per-kernel
+                            profiling is enabled.                                   */
 } ori_solve_opts;
 
 typedef struct {
@@ -104,7 +110,7 @@ typedef struct {
 } ori_solve_info;
 
 /* Fill opts with the defaults: tol 1e-10, max_iter 1000, FP64, check_every 1,
- * no x0, inner_tol 1e-5, max_outer 10, true_residual 1. */
+ * no x0, inner_tol 1e-5, max_outer 10, true_residual 1, graph 1. */
 void ori_default_opts(ori_solve_opts* opts);
 
 /* Device bytes that ori_create would allocate for this grid, batch size and
@@ -182,6 +188,35 @@ ori_status ori_gradient(ori_ctx ctx, const ori_solve_opts* opts, const void* u_t
  * precision ORI_MIXED runs the FFT stages in complex64 (inputs and outputs
  * stay complex128).  Used by tests and the benchmark. */
 ori_status ori_matvec(ori_ctx ctx, int32_t op, int32_t precision, const void* x, void* y);
+
+/* Layout of the FFT passes of one precision.  Performance only: blk_lg and
+ * prefetch leave every result bitwise unchanged; narrow tiles may change
+ * results at the level of rounding. */
+typedef struct {
+  int32_t blk_lg;   /* log2 of the row block (along i1) of the work array between
+                       the strided and Z passes, 0..6, n divisible by 2^blk_lg  */
+  int32_t narrow;   /* 1: narrow pencil tiles in the strided and Z passes      */
+  int32_t prefetch; /* 1: the Z pass loads its next tile while it transforms one */
+} ori_layout;
+
+/* Layout in use for precision ORI_FP64 (complex128 FFTs) or ORI_MIXED
+ * (complex64 FFTs). */
+ori_status ori_get_layout(ori_ctx ctx, int32_t precision, ori_layout* out);
+
+/* Set the layout of one precision; ORI_ERR_INVALID_ARG for an invalid one
+ * (the layout in use is kept).  Synchronises the context stream. */
+ori_status ori_set_layout(ori_ctx ctx, int32_t precision, const ori_layout* layout);
+
+/* Autotuner.  On a loaded context, times the COCG product of each
+ * provisioned precision (reps timed products after one warm-up per
+ * candidate, reps = 0 means 3) for every valid layout, keeps the fastest on
+ * ctx, and records it in a process-wide table keyed by (device, n, nrhs)
+ * from which later ori_create calls on that key start.  Overwrites the
+ * context's iterate and work vectors (not its loaded data), so call it
+ * between solves.  best[2] and ms_per_product[2] (FP64, complex64; either
+ * may be NULL) receive the winners and their time per product (-1 for a
+ * precision that is not provisioned).  Synchronises the context stream. */
+ori_status ori_tune(ori_ctx ctx, int32_t reps, ori_layout* best, double* ms_per_product);
 
 /* Per-kernel timing with HIP events on the context stream.  enable = 1
  * clears the counters and starts recording every launch; 0 stops. */

@@ -54,7 +54,7 @@ class Grid(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_x0", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("max_outer", ctypes.c_int32), ("true_residual", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("true_residual", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -62,6 +62,13 @@ class SolveInfo(ctypes.Structure):
                 ("matvecs", ctypes.c_int64), ("matvecs_c64", ctypes.c_int64),
                 ("rel_res_recursive", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("blk_lg", ctypes.c_int32), ("narrow", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -94,6 +101,9 @@ def lib():
             "ori_profile_enable": (ctypes.c_int, [P, I32]),
             "ori_profile_read": (ctypes.c_int, [P, I32, ctypes.POINTER(ctypes.c_char_p),
                                                 ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(I32)]),
+            "ori_get_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout)]),
+            "ori_set_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout)]),
+            "ori_tune": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout), ctypes.POINTER(D)]),
             "ori_destroy": (None, [P]),
             "ori_last_error": (ctypes.c_char_p, [P]),
         }
@@ -224,16 +234,16 @@ def ori_setup(n, k, h, N, u0, side=1.0, origin=(0.0, 0.0, 0.0), cell_offset=0.5,
 
 
 def _opts(tol=1e-10, max_iter=1000, precision=ORI_FP64, check_every=1, use_x0=False, inner_tol=1e-5,
-          max_outer=10, true_residual=True):
+          max_outer=10, true_residual=True, graph=True):
     return SolveOpts(float(tol), int(max_iter), int(precision), int(check_every), int(bool(use_x0)),
-                     float(inner_tol), int(max_outer), int(bool(true_residual)))
+                     float(inner_tol), int(max_outer), int(bool(true_residual)), int(bool(graph)))
 
 
 def ori_solve(ctx, u, tol=1e-10, max_iter=1000, precision=ORI_FP64, check_every=1, use_x0=False,
-              inner_tol=1e-5, max_outer=10, true_residual=True, raise_on_error=True):
+              inner_tol=1e-5, max_outer=10, true_residual=True, graph=True, raise_on_error=True):
     """Solve into u (complex128 CUDA tensor, n^3).  Returns (status, info dict)."""
     import torch
-    o = _opts(tol, max_iter, precision, check_every, use_x0, inner_tol, max_outer, true_residual)
+    o = _opts(tol, max_iter, precision, check_every, use_x0, inner_tol, max_outer, true_residual, graph)
     info = SolveInfo()
     st = lib().ori_solve(ctx.handle, ctypes.byref(o), _dev(u, torch.complex128, ctx.nrhs * ctx.P, "u"),
                          ctypes.byref(info))
@@ -286,6 +296,27 @@ def ori_batch_info(ctx, i):
 
 def ori_destroy(ctx):
     ctx.close()
+
+
+def ori_get_layout(ctx, precision=ORI_FP64):
+    out = Layout()
+    _check(lib().ori_get_layout(ctx.handle, int(precision), ctypes.byref(out)), ctx)
+    return out.as_dict()
+
+
+def ori_set_layout(ctx, precision=ORI_FP64, blk_lg=4, narrow=0, prefetch=0):
+    lay = Layout(int(blk_lg), int(narrow), int(prefetch))
+    _check(lib().ori_set_layout(ctx.handle, int(precision), ctypes.byref(lay)), ctx)
+
+
+def ori_tune(ctx, reps=0):
+    """Autotune the pass layouts of a loaded context.  Returns
+    {"fp64": (layout dict, ms per product), "c64": (...)}; the complex64 entry
+    has ms = -1 when complex64 workspaces were not provisioned."""
+    best = (Layout * 2)()
+    ms = (ctypes.c_double * 2)()
+    _check(lib().ori_tune(ctx.handle, int(reps), best, ms), ctx)
+    return {"fp64": (best[0].as_dict(), ms[0]), "c64": (best[1].as_dict(), ms[1])}
 
 
 def ori_profile_enable(ctx, enable=True):

@@ -56,13 +56,14 @@ __device__ __forceinline__ bool finite_cx(cxd z) { return isfinite(z.re) && isfi
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P;                 \
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
 
-// a1, operator part: D = 4 pi h N vol, S = sqrt(D), c = 4 pi N vol
+// a1, operator part: D = 4 pi h N vol, S = sqrt(D), c = 4 pi N vol.
+// Partials per workgroup: {bad-input count, min |S|^2, max |S|^2, 0}.
 __global__ void __launch_bounds__(kRedThreads)
     k_coefficients(const cxd* __restrict__ h, const double* __restrict__ N, double vol, int64_t P,
                    cxd* __restrict__ D, cxd* __restrict__ S, cxf* __restrict__ Sf, double* __restrict__ cN,
                    double* __restrict__ partials) {
   constexpr double FOUR_PI = 12.566370614359172954;  // c_S for spheres
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double bad_n = 0.0, mn = INFINITY, mx = 0.0;
   ORI_RHS_LOOP(i) {
     const cxd hv = h[i];
     const double nv = N ? N[i] : 1.0;
@@ -74,9 +75,62 @@ __global__ void __launch_bounds__(kRedThreads)
     S[i] = s;
     if (Sf) Sf[i] = cvt<float>(s);
     cN[i] = c;
-    acc[0] += bad ? 1.0 : 0.0;
+    bad_n += bad ? 1.0 : 0.0;
+    const double s2 = norm2(s);
+    mn = fmin(mn, s2);
+    mx = fmax(mx, s2);
   }
-  block_sum4(acc, partials + 4 * static_cast<int64_t>(blockIdx.x));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    bad_n += __shfl_xor(bad_n, off, 64);
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+  }
+  __shared__ double sh[(kRedThreads / 64) * 3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[3 * w] = bad_n;
+    sh[3 * w + 1] = mn;
+    sh[3 * w + 2] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kRedThreads / 64; ++i) {
+      sh[0] += sh[3 * i];
+      sh[1] = fmin(sh[1], sh[3 * i + 1]);
+      sh[2] = fmax(sh[2], sh[3 * i + 2]);
+    }
+    double* out = partials + 4 * static_cast<int64_t>(blockIdx.x);
+    out[0] = sh[0];
+    out[1] = sh[1];
+    out[2] = sh[2];
+    out[3] = 0.0;
+  }
+}
+
+// {bad count, min |S|^2, max |S|^2} over nblk partials -> sc[0]
+__global__ void __launch_bounds__(64) k_finalize_coeff(const double* __restrict__ part, int64_t nblk, ScalarBlock* sc) {
+  if (threadIdx.x != 0) return;
+  double bad = 0.0, mn = INFINITY, mx = 0.0;
+  for (int64_t i = 0; i < nblk; ++i) {
+    bad += part[4 * i];
+    mn = fmin(mn, part[4 * i + 1]);
+    mx = fmax(mx, part[4 * i + 2]);
+  }
+  sc->flags = bad > 0.0 ? FLAG_BAD_INPUT : 0;
+  sc->s2_min = mn;
+  sc->s2_max = mx;
+}
+
+// u = w / S, per right-hand side (S shared)
+__global__ void __launch_bounds__(256) k_div(const cxd* __restrict__ w, const cxd* __restrict__ s,
+                                             cxd* __restrict__ u, int64_t P) {
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+  ORI_RHS_LOOP(i) {
+    const cxd d = s[i];
+    const double inv = 1.0 / norm2(d);
+    u[off + i] = scale(w[off + i] * conj(d), inv);
+  }
 }
 
 // a1, right-hand sides: b = S u0 (one batch row per blockIdx.y)
@@ -120,9 +174,6 @@ __global__ void __launch_bounds__(kRedThreads)
       sc->bb = s0;
       sc->aux = s1;
       sc->flags = s2 > 0.0 ? FLAG_BAD_INPUT : 0;
-      break;
-    case FIN_BAD:
-      sc->flags = s0 > 0.0 ? FLAG_BAD_INPUT : 0;
       break;
     case FIN_INIT: {
       sc->rho_re = s0;
@@ -301,6 +352,17 @@ hipError_t launch_coefficients(const void* h, const double* N, double vol, int64
                                double* cN, double* partials, hipStream_t st) {
   hipLaunchKernelGGL(k_coefficients, red_grid(P, 1), dim3(kRedThreads), 0, st, static_cast<const cxd*>(h), N, vol, P,
                      static_cast<cxd*>(D), static_cast<cxd*>(S), static_cast<cxf*>(Sf), cN, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_coeff(const double* partials, int64_t nblk, ScalarBlock* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_coeff, dim3(1), dim3(64), 0, st, partials, nblk, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_div(const void* w, const void* s, void* u, int64_t P, int64_t nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_div, dim3(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs)), dim3(256), 0, st,
+                     static_cast<const cxd*>(w), static_cast<const cxd*>(s), static_cast<cxd*>(u), P);
   return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ struct ScalarBlock {
   double aux;                 // one-off reductions (||u0||^2 at load, residual norms)
   double rr_target;           // converged once rr <= rr_target (set by FIN_INIT)
   double rr0;                 // rr at FIN_INIT
-  double pad0;
+  double s2_min, s2_max;      // min / max |S_p|^2 over the grid (operator coefficients, sc[0])
   int32_t flags;              // FLAG_* below
   int32_t iters;              // COCG iterations done while not converged
 };
@@ -167,9 +167,13 @@ inline int64_t red_blocks(int64_t P) {
 }
 
 // a1 (operator): D = 4 pi h N vol, S = sqrt(D), complex64 S, c = 4 pi N vol;
-// partials {bad-input count, 0, 0, 0} (one range)
+// partials {bad-input count, min |S|^2, max |S|^2, 0} (one range), reduced
+// into sc[0] by launch_finalize_coeff
 hipError_t launch_coefficients(const void* h, const double* N, double vol, int64_t P, void* D, void* S, void* Sf,
                                double* cN, double* partials, hipStream_t st);
+hipError_t launch_finalize_coeff(const double* partials, int64_t nblk, ScalarBlock* sc, hipStream_t st);
+// u = w / S (w, u batch vectors; S shared, nonzero)
+hipError_t launch_div(const void* w, const void* s, void* u, int64_t P, int64_t nrhs, hipStream_t st);
 // a1 (right-hand sides): b = S u0, u0 copied; partials {||b||^2, ||u0||^2, bad, 0} per rhs
 hipError_t launch_rhs(const void* u0, const void* S, int64_t P, int64_t nrhs, void* b, void* u0c,
                       double* partials, hipStream_t st);
@@ -181,7 +185,6 @@ enum FinalizeMode : int32_t {
   FIN_MU = 2,      // sums = {mu.re, mu.im, qq, pp}: mu, alpha = rho / mu
   FIN_RHO = 3,     // sums = {rho'.re, rho'.im, rr, -}: beta = rho'/rho, rho = rho', rr, flags
   FIN_NORM = 4,    // sums = {-, -, ||y||^2, -}: aux
-  FIN_BAD = 5,     // sums = {bad, -, -, -}: flags (operator coefficients)
 };
 // FIN_INIT: rr_target = tol2 * (tol2_of_bb ? bb : rr)
 hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, ScalarBlock* sc, int32_t mode,

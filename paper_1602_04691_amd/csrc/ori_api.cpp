@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -64,6 +66,30 @@ const char* const kKindNames[K_NKIND] = {"f1", "f2", "zpass", "i2", "i1", "updat
 
 thread_local std::string g_last_error = "no error";
 
+// Layout knobs of the FFT passes (performance only)
+struct Knobs {
+  int blk_lg = 4;  // log2 of the i1 block of the B layout (n divisible by 2^blk_lg)
+  int np_sel = 0;  // strided / Z tile width: 0 wide, 1 narrow
+  int zpf = 0;     // Z pass: prefetch the next tile
+  bool operator==(const Knobs& o) const { return blk_lg == o.blk_lg && np_sel == o.np_sel && zpf == o.zpf; }
+};
+
+// Tuned layouts, process-wide, by (device, n, nrhs): a context created on a
+// tuned key starts from the tuned layout.
+struct TuneKey {
+  int device;
+  int64_t n, nrhs;
+  bool operator<(const TuneKey& o) const {
+    return device != o.device ? device < o.device : n != o.n ? n < o.n : nrhs < o.nrhs;
+  }
+};
+struct Tuned {
+  Knobs k[2];
+  bool have[2] = {false, false};
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuned> g_tuned;
+
 struct ProfPending {
   int slot;  // kind * 2 + (fprec == F32)
   int ev;
@@ -82,9 +108,8 @@ struct ori_ctx_s {
   hipStream_t stream = nullptr;
   int device = 0;
   const LengthKernels* K = nullptr;
-  int blk_lg = 0;  // log2 of the i1 block of the B layout
-  int np_sel = 0;  // strided / Z tile width: 0 wide, 1 narrow
-  int zpf = 0;     // Z pass: prefetch the next tile
+  Knobs knob[2];   // layout of the FFT passes, [0] complex128 FFTs, [1] complex64
+  bool recover_by_division = false;  // u = w / S (no S_p near zero)
   std::string err = "no error";
   std::vector<double> u0norm2, bnorm2;     // per right-hand side
   std::vector<ori_solve_info> last_info;  // per right-hand side, last solve
@@ -107,6 +132,14 @@ struct ori_ctx_s {
   double* outer_m = nullptr;       // [nrhs] refinement multipliers
   double* outer_m_host = nullptr;  // pinned
   std::vector<void*> allocs;
+
+  // captured COCG iteration blocks, one per vector precision
+  struct IterGraph {
+    hipGraphExec_t exec = nullptr;
+    int iters = 0;
+    const void* key[5] = {};
+  } graphs[2];
+  hipStream_t cap_stream = nullptr;  // capture stream (the context stream may be the null stream)
 
   // profiling
   bool prof = false;
@@ -296,13 +329,14 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
 
   // B layout: i1 split into blocks of 2^lg rows (see ZArgs); the batch is
   // just more outer rows
-  const int lg = c->blk_lg;
+  const Knobs& kn = c->knob[fprec == PREC_F32 ? 1 : 0];
+  const int lg = kn.blk_lg;
   const int64_t Bk = int64_t{1} << lg;
-  const int ns = c->np_sel;
+  const int ns = kn.np_sel;
   StridedArgs f2{A, B, R * n, L, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, ns, tw};
   ORI_TRY(launch(c, K_F2, fprec, [&] { return c->K->strided(fprec, f2, c->stream); }));
 
-  ZArgs z{B, n, lg, ns, L * L * Bk, L, Bk * L, R, n * L * L, c->zpf, 0, kh, n + 1, tw};
+  ZArgs z{B, n, lg, ns, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, 0, kh, n + 1, tw};
   ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, z, c->stream); }));
 
   StridedArgs i2{B, A, R * n, L, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};
@@ -393,38 +427,97 @@ bool all_done(ori_ctx c) {
   return true;
 }
 
+// One COCG iteration on every right-hand side: p = r + beta p (p = r when
+// first), q = (I + S G0 S) p with <p,q>, then alpha, x, r and rho.  No
+// memset and no host work, so it can be captured.
+ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, bool first) {
+  ContigFwdArgs f1{};
+  f1.x = r;
+  f1.pvec = p;
+  f1.s_in = S;
+  f1.sc = c->sc;
+  f1.mode = 1;
+  f1.first = first;
+  ContigInvArgs i1 = epi(q, p, 1.0, nullptr, 0.0, S, 1.0, c->partials, 0);
+  int64_t nblk = 0;
+  ORI_TRY(matvec(c, prec, prec, f1, i1, &nblk));
+  ORI_TRY(finalize(c, nblk, FIN_MU));
+  ORI_TRY(launch(c, K_UPDATE, prec, [&] {
+    return launch_update(prec, x, p, r, q, c->P, c->nrhs, c->sc, c->partials, c->stream);
+  }));
+  return finalize(c, rblocks(c), FIN_RHO);
+}
+
+// The graph of `iters` non-first iterations on (x, r, p, q, S), captured on
+// the context's capture stream and cached per precision.
+ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int iters,
+                           hipGraphExec_t* out) {
+  auto& g = c->graphs[prec == PREC_F32 ? 1 : 0];
+  const void* key[5] = {x, r, p, q, S};
+  if (g.exec && g.iters == iters && std::equal(key, key + 5, g.key)) {
+    *out = g.exec;
+    return ORI_OK;
+  }
+  if (g.exec) {
+    ORI_HIP(c, hipGraphExecDestroy(g.exec));
+    g.exec = nullptr;
+  }
+  if (!c->cap_stream) ORI_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t own = c->stream;
+  c->stream = c->cap_stream;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  ori_status st = e == hipSuccess ? ORI_OK : set_err(c, ORI_ERR_DEVICE, "hipStreamBeginCapture: %s",
+                                                     hipGetErrorString(e));
+  if (st == ORI_OK) {
+    for (int it = 0; it < iters && st == ORI_OK; ++it) st = cocg_iteration(c, prec, x, r, p, q, S, false);
+    e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (st == ORI_OK && e != hipSuccess)
+      st = set_err(c, ORI_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  c->stream = own;
+  if (st == ORI_OK) {
+    e = hipGraphInstantiateWithFlags(&g.exec, graph, 0);
+    if (e != hipSuccess) {
+      g.exec = nullptr;
+      st = set_err(c, ORI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  if (st != ORI_OK) return st;
+  g.iters = iters;
+  std::copy(key, key + 5, g.key);
+  *out = g.exec;
+  return ORI_OK;
+}
+
 ori_status run_cocg(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
-                    int check_every, CocgOut* out) {
+                    int check_every, bool use_graph, CocgOut* out) {
   ORI_TRY(sync_scalars(c));
   if (all_done(c)) {
     out->all_done = true;
     return ORI_OK;
   }
-  const int64_t P = c->P;
-  for (int it = 0; it < max_iter; ++it) {
-    ContigFwdArgs f1{};
-    f1.x = r;
-    f1.pvec = p;
-    f1.s_in = S;
-    f1.sc = c->sc;
-    f1.mode = 1;
-    f1.first = it == 0;
-    ContigInvArgs i1 = epi(q, p, 1.0, nullptr, 0.0, S, 1.0, c->partials, 0);
-    int64_t nblk = 0;
-    ORI_TRY(matvec(c, prec, prec, f1, i1, &nblk));
-    out->matvecs++;
-    ORI_TRY(finalize(c, nblk, FIN_MU));
-    ORI_TRY(launch(c, K_UPDATE, prec, [&] {
-      return launch_update(prec, x, p, r, q, P, c->nrhs, c->sc, c->partials, c->stream);
-    }));
-    ORI_TRY(finalize(c, rblocks(c), FIN_RHO));
-    out->iters++;
-    if ((it + 1) % check_every == 0 || it + 1 == max_iter) {
-      ORI_TRY(sync_scalars(c));
-      if (all_done(c)) {
-        out->all_done = true;
-        return ORI_OK;
-      }
+  use_graph = use_graph && !c->prof;
+  int it = 0;
+  while (it < max_iter) {
+    // the first block runs eagerly (it holds the first iteration); later
+    // full blocks replay the captured graph
+    const int blk = std::min(check_every, max_iter - it);
+    if (use_graph && it > 0 && blk == check_every) {
+      hipGraphExec_t exec = nullptr;
+      ORI_TRY(iteration_graph(c, prec, x, r, p, q, S, blk, &exec));
+      ORI_HIP(c, hipGraphLaunch(exec, c->stream));
+    } else {
+      for (int j = 0; j < blk; ++j) ORI_TRY(cocg_iteration(c, prec, x, r, p, q, S, it + j == 0));
+    }
+    it += blk;
+    out->iters += blk;
+    out->matvecs += blk;
+    ORI_TRY(sync_scalars(c));
+    if (all_done(c)) {
+      out->all_done = true;
+      return ORI_OK;
     }
   }
   return ORI_OK;
@@ -438,8 +531,15 @@ ori_status true_residual_sym(ori_ctx c, const cxd* rhs, const cxd* x, cxd* r, do
   return finalize(c, nblk, FIN_INIT, tol2, tol2_of_bb);
 }
 
-// u = u0 - G0 S w (recovery of the solution of eq. 2.19 from w)
-ori_status recover(ori_ctx c, const cxd* w, cxd* u) {
+// Recovery of the solution of eq. 2.19 from w = S u: u = w / S when every
+// |S_p| is within 1e3 of the largest, else u = u0 - G0 S w (one product,
+// valid for any S, zeros included).  Returns the products used.
+ori_status recover(ori_ctx c, const cxd* w, cxd* u, int* products) {
+  if (c->recover_by_division) {
+    *products = 0;
+    return launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_div(w, c->S, u, c->P, c->nrhs, c->stream); });
+  }
+  *products = 1;
   return matvec(c, PREC_F64, PREC_F64, plain_f1(w, c->S), epi(u, c->u0, 1.0, nullptr, 0.0, nullptr, -1.0, nullptr, 0),
                 nullptr);
 }
@@ -459,19 +559,48 @@ ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel)
   return ORI_OK;
 }
 
-// Layout knobs: the i1 blocking of the B work array (ZArgs) and the tile
-// width of the strided passes.  Defaults are the measured best on MI355X;
-// ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF override them for tuning runs.
+// Layout knobs: the i1 blocking of the B work array (ZArgs), the tile width
+// of the strided and Z passes and the Z-pass prefetch.  Start from the
+// measured defaults, or from the tuned layout of this (device, n, nrhs);
+// ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF override both for tuning runs.
+bool valid_knobs(int64_t n, const Knobs& k) {
+  return k.blk_lg >= 0 && k.blk_lg <= 6 && n % (int64_t{1} << k.blk_lg) == 0 && (k.np_sel == 0 || k.np_sel == 1) &&
+         (k.zpf == 0 || k.zpf == 1);
+}
+
 void choose_layout(ori_ctx c) {
-  int lg = 4, np = 0, pf = 0;
-  if (const char* e = std::getenv("ORI_TUNE_BLK_LG")) lg = std::atoi(e);
-  if (const char* e = std::getenv("ORI_TUNE_NP")) np = std::atoi(e);
-  if (const char* e = std::getenv("ORI_TUNE_ZPF")) pf = std::atoi(e);
-  c->zpf = pf ? 1 : 0;
-  if (lg < 0) lg = 0;
-  while (lg > 0 && (c->n % (int64_t{1} << lg)) != 0) --lg;
-  c->blk_lg = lg;
-  c->np_sel = np ? 1 : 0;
+  for (int f = 0; f < 2; ++f) {
+    Knobs k;
+    while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
+    c->knob[f] = k;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(TuneKey{c->device, c->n, c->nrhs});
+    if (it != g_tuned.end())
+      for (int f = 0; f < 2; ++f)
+        if (it->second.have[f]) c->knob[f] = it->second.k[f];
+  }
+  for (int f = 0; f < 2; ++f) {
+    Knobs k = c->knob[f];
+    if (const char* e = std::getenv("ORI_TUNE_BLK_LG")) k.blk_lg = std::atoi(e);
+    if (const char* e = std::getenv("ORI_TUNE_NP")) k.np_sel = std::atoi(e) ? 1 : 0;
+    if (const char* e = std::getenv("ORI_TUNE_ZPF")) k.zpf = std::atoi(e) ? 1 : 0;
+    if (k.blk_lg < 0) k.blk_lg = 0;
+    if (k.blk_lg > 6) k.blk_lg = 6;
+    while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
+    c->knob[f] = k;
+  }
+}
+
+// Captured graphs bake the layout into their kernel arguments.
+ori_status drop_graphs(ori_ctx c) {
+  for (auto& g : c->graphs) {
+    if (g.exec) ORI_HIP(c, hipGraphExecDestroy(g.exec));
+    g.exec = nullptr;
+    g.iters = 0;
+  }
+  return ORI_OK;
 }
 
 ori_status guard(ori_ctx c) {
@@ -545,7 +674,7 @@ ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const s
   for (int64_t i = 0; i < R; ++i) target[i] = o.tol * o.tol * bb[i];
   if (o.precision == ORI_FP64) {
     CocgOut co;
-    ORI_TRY(run_cocg(c, PREC_F64, c->x, c->r, c->p, c->q, c->S, o.max_iter, o.check_every, &co));
+    ORI_TRY(run_cocg(c, PREC_F64, c->x, c->r, c->p, c->q, c->S, o.max_iter, o.check_every, o.graph != 0, &co));
     for (int64_t i = 0; i < R; ++i) {
       const ScalarBlock& s = c->sc_host[i];
       oc->info[i].iterations += s.iters;
@@ -578,7 +707,7 @@ ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const s
     }));
     ORI_TRY(finalize(c, rblocks(c), FIN_INIT, o.inner_tol * o.inner_tol, 0));
     CocgOut co;
-    ORI_TRY(run_cocg(c, PREC_F32, c->xf, c->rf, c->pf, c->qf, c->Sf, inner_left, o.check_every, &co));
+    ORI_TRY(run_cocg(c, PREC_F32, c->xf, c->rf, c->pf, c->qf, c->Sf, inner_left, o.check_every, o.graph != 0, &co));
     inner_left -= co.iters;
     bool progress = false;
     for (int64_t i = 0; i < R; ++i) {
@@ -624,9 +753,10 @@ ori_status forward_solve(ori_ctx c, const ori_solve_opts& o, cxd* u, Outcome* oc
     ORI_TRY(finalize(c, rblocks(c), FIN_INIT, tol2, 1));
   }
   ORI_TRY(solve_sym(c, o, c->b, c->bnorm2, oc));
-  ORI_TRY(recover(c, c->x, u));
+  int rec = 0;
+  ORI_TRY(recover(c, c->x, u, &rec));
   for (auto& i : oc->info) {
-    i.matvecs++;
+    i.matvecs += rec;
     i.rel_res_true = -1.0;
   }
   if (o.true_residual) {
@@ -696,6 +826,7 @@ void ori_default_opts(ori_solve_opts* o) {
   o->inner_tol = 1e-5;
   o->max_outer = 10;
   o->true_residual = 1;
+  o->graph = 1;
 }
 
 const char* ori_version(void) { return "ori 0.2 (gfx950)"; }
@@ -835,11 +966,14 @@ ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const v
     return launch_coefficients(h, N, vol, P, c->D, c->S, c->Sf, c->cN, c->partials, c->stream);
   }));
   ORI_HIP(c, hipMemsetAsync(c->sc, 0, R * sizeof(ScalarBlock), c->stream));
-  ORI_TRY(launch(c, K_FINALIZE, PREC_F64, [&] {
-    return launch_finalize(c->partials, rblocks(c), 1, c->sc, FIN_BAD, kBreakdownEps, 0.0, 0, c->stream);
-  }));
+  ORI_TRY(launch(c, K_FINALIZE, PREC_F64,
+                 [&] { return launch_finalize_coeff(c->partials, rblocks(c), c->sc, c->stream); }));
   ORI_TRY(sync_scalars(c));
   if (c->sc_host[0].flags & FLAG_BAD_INPUT) return set_err(c, ORI_ERR_INVALID_ARG, "h or N holds NaN/Inf, or N < 0");
+  // u = w / S is exact and free when no S_p vanishes; with |S| spread over
+  // more than 1e3 the division would amplify the error of w in small-S
+  // cells, so the recovery u = u0 - G0 S w (one product) is used instead
+  c->recover_by_division = c->sc_host[0].s2_min > 0.0 && c->sc_host[0].s2_min >= 1e-6 * c->sc_host[0].s2_max;
   ORI_TRY(launch(c, K_COEFF, PREC_F64, [&] { return launch_rhs(u0, c->S, P, R, c->b, c->u0, c->partials, c->stream); }));
   ORI_TRY(finalize(c, rblocks(c), FIN_SETUP));
   ORI_TRY(sync_scalars(c));
@@ -894,6 +1028,111 @@ ori_status ori_matvec(ori_ctx c, int32_t op, int32_t precision, const void* x, v
   }
   ORI_TRY(matvec(c, PREC_F64, fp, f1, i1, nullptr));
   ORI_HIP(c, hipStreamSynchronize(c->stream));
+  return ORI_OK;
+}
+
+ori_status ori_get_layout(ori_ctx c, int32_t precision, ori_layout* out) {
+  ORI_TRY(guard(c));
+  if (!out) return set_err(c, ORI_ERR_INVALID_ARG, "out is NULL");
+  if (precision != ORI_FP64 && precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
+  const Knobs& k = c->knob[precision == ORI_MIXED ? 1 : 0];
+  out->blk_lg = k.blk_lg;
+  out->narrow = k.np_sel;
+  out->prefetch = k.zpf;
+  return ORI_OK;
+}
+
+ori_status ori_set_layout(ori_ctx c, int32_t precision, const ori_layout* in) {
+  ORI_TRY(guard(c));
+  if (!in) return set_err(c, ORI_ERR_INVALID_ARG, "layout is NULL");
+  if (precision != ORI_FP64 && precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
+  const Knobs k{in->blk_lg, in->narrow, in->prefetch};
+  if (!valid_knobs(c->n, k))
+    return set_err(c, ORI_ERR_INVALID_ARG, "layout {blk_lg %d, narrow %d, prefetch %d} is not valid for n = %lld",
+                   in->blk_lg, in->narrow, in->prefetch, (long long)c->n);
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  ORI_TRY(drop_graphs(c));
+  c->knob[precision == ORI_MIXED ? 1 : 0] = k;
+  return ORI_OK;
+}
+
+ori_status ori_tune(ori_ctx c, int32_t reps, ori_layout* best, double* ms_per_product) {
+  ORI_TRY(guard(c));
+  if (!c->loaded) return set_err(c, ORI_ERR_INVALID_ARG, "ori_load has not succeeded on this context");
+  if (reps < 0) return set_err(c, ORI_ERR_INVALID_ARG, "reps must be >= 0");
+  if (reps == 0) reps = 3;
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  ORI_TRY(drop_graphs(c));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ORI_HIP(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_err(c, ORI_ERR_DEVICE, "hipEventCreate failed");
+  }
+  ori_status st = ORI_OK;
+  Tuned found;
+  const bool mixed = c->provision & ORI_PROVISION_MIXED;
+  for (int f = 0; f < (mixed ? 2 : 1) && st == ORI_OK; ++f) {
+    // the COCG product of this precision: q = (I + S G0 S) x on the batch
+    const int fp = f ? PREC_F32 : PREC_F64;
+    void* x = f ? static_cast<void*>(c->xf) : static_cast<void*>(c->x);
+    void* y = f ? static_cast<void*>(c->qf) : static_cast<void*>(c->q);
+    const void* S = f ? static_cast<const void*>(c->Sf) : static_cast<const void*>(c->S);
+    if (f) {
+      ORI_HIP(c, hipMemsetAsync(x, 0, c->nrhs * c->P * 8, c->stream));
+    } else {
+      ORI_HIP(c, hipMemcpyAsync(x, c->b, c->nrhs * c->P * 16, hipMemcpyDeviceToDevice, c->stream));
+    }
+    const Knobs start = c->knob[f];
+    Knobs win = start;
+    double win_ms = INFINITY;
+    for (int lg = 0; lg <= 6 && st == ORI_OK; ++lg)
+      for (int np = 0; np <= 1 && st == ORI_OK; ++np)
+        for (int pf = 0; pf <= 1 && st == ORI_OK; ++pf) {
+          const Knobs k{lg, np, pf};
+          if (!valid_knobs(c->n, k)) continue;
+          c->knob[f] = k;
+          auto product = [&] {
+            return matvec(c, fp, fp, plain_f1(x, S), epi(y, x, 1.0, nullptr, 0.0, S, 1.0, nullptr, 0), nullptr);
+          };
+          st = product();  // warm-up
+          if (st == ORI_OK && hipEventRecord(e0, c->stream) != hipSuccess)
+            st = set_err(c, ORI_ERR_DEVICE, "hipEventRecord failed");
+          for (int i = 0; i < reps && st == ORI_OK; ++i) st = product();
+          if (st == ORI_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            st = set_err(c, ORI_ERR_DEVICE, "timing events failed");
+          float ms = 0.f;
+          if (st == ORI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            st = set_err(c, ORI_ERR_DEVICE, "hipEventElapsedTime failed");
+          if (st == ORI_OK && ms / reps < win_ms) {
+            win_ms = ms / reps;
+            win = k;
+          }
+        }
+    c->knob[f] = st == ORI_OK ? win : start;
+    found.k[f] = win;
+    found.have[f] = st == ORI_OK;
+    if (best) {
+      best[f].blk_lg = win.blk_lg;
+      best[f].narrow = win.np_sel;
+      best[f].prefetch = win.zpf;
+    }
+    if (ms_per_product) ms_per_product[f] = st == ORI_OK ? win_ms : -1.0;
+  }
+  if (!mixed) {
+    if (best) best[1] = ori_layout{c->knob[1].blk_lg, c->knob[1].np_sel, c->knob[1].zpf};
+    if (ms_per_product) ms_per_product[1] = -1.0;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ORI_OK) return st;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  Tuned& t = g_tuned[TuneKey{c->device, c->n, c->nrhs}];
+  for (int f = 0; f < 2; ++f)
+    if (found.have[f]) {
+      t.k[f] = found.k[f];
+      t.have[f] = true;
+    }
   return ORI_OK;
 }
 
@@ -1031,6 +1270,9 @@ void ori_destroy(ori_ctx c) {
   else
     (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (auto& g : c->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   if (c->outer_m_host) (void)hipHostFree(c->outer_m_host);

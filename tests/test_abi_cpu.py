@@ -43,7 +43,8 @@ def test_version_and_defaults():
     assert "gfx950" in ori.ori_version()
     o = ori.ori_default_opts()
     assert o.tol == 1e-10 and o.max_iter == 1000 and o.precision == ori.ORI_FP64
-    assert o.check_every == 1 and o.true_residual == 1
+    assert o.check_every == 1 and o.true_residual == 1 and o.graph == 1
+    assert o.inner_tol == 1e-5 and o.max_outer == 10 and o.use_x0 == 0
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 16, 64, 128, 256, 512])

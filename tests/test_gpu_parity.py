@@ -126,7 +126,36 @@ def test_solve_fp64_vs_lu(n, k):
         assert err <= 1e-10
         assert info["rel_res_recursive"] < 1e-12
         assert 0 <= info["rel_res_true"] < 1e-11
+        # one product for the initial residual, one per iteration; no S_p
+        # vanishes, so u is recovered as w / S without a product
+        assert info["matvecs"] == info["iterations"] + 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_ball_body_vs_lu(precision):
+    # particles only inside a ball: N_p = 0 (S_p = 0) outside, so u is
+    # recovered as u0 - G0 S w (one more product), and u = u0 where S = 0
+    say(f"[ball body] {precision}")
+    n, k = 12, 4.0
+    case = workloads.make_case(n, k, seed=21)
+    pts = O.cell_points(n)
+    N = np.where(np.linalg.norm(pts - 0.5, axis=1) < 0.4, 1.5, 0.0)
+    D = O.coupling(case["h"], N, n)
+    u_ref = O.solve_direct(O.system_matrix(pts, k, D), case["u0"])
+    prec = ori.ORI_FP64 if precision == "fp64" else ori.ORI_MIXED
+    with context(n, k, case["h"], N, case["u0"]) as ctx:
+        ug = torch.empty(n ** 3, dtype=torch.complex128, device="cuda")
+        _, info = ori.ori_solve(ctx, ug, tol=1e-12 if prec == ori.ORI_FP64 else 1e-8, precision=prec)
+        u = cpu(ug)
+    err = rel(u, u_ref)
+    say(f"   iters={info['iterations']} matvecs={info['matvecs']} err={err:.2e}")
+    assert err <= (1e-10 if prec == ori.ORI_FP64 else 1e-6)
+    outside = N == 0.0
+    assert outside.sum() > 0 and (~outside).sum() > 0
+    if prec == ori.ORI_FP64:
         assert info["matvecs"] == info["iterations"] + 2
+        # where S_p = 0 the row of eq. 2.19 still couples to the body
+        assert rel(u[outside], u_ref[outside]) <= 1e-10
 
 
 @pytest.mark.parametrize("n,k", [(4, 5.0), (8, 5.0), (16, 1.0)])
