@@ -69,9 +69,10 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel, n):
+def read_traffic(kernel, n, layout):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current kernel sources with the same pass layout; else
+    None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_n{n}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -80,7 +81,7 @@ def read_traffic(kernel, n):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != kernel_sources_sha():
+    if kv.get("source_sha") != kernel_sources_sha() or kv.get("layout") != layout:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -119,6 +120,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle rows for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--layout", default="auto",
+                    help="pass layout: auto (ori_tune before timing), default, or LG,NP,PF[/LG,NP,PF] "
+                         "(complex128 / complex64 passes)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain 1-to-1 copy of this many MiB (counter calibration)")
     a = ap.parse_args()
@@ -151,6 +155,23 @@ def main():
 
     ctx = ori.ori_create(n)
     stream = torch.cuda.current_stream()
+
+    # pass layout: tuned once before timing (like an FFT plan), or given
+    if a.layout == "auto":
+        ori.ori_load(ctx, k, h, N, u0)
+        tuned = ori.ori_tune(ctx)
+        log(f"[bench] tuned layout: {tuned}")
+    elif a.layout != "default":
+        parts = a.layout.split("/")
+        for prec, spec in zip((ori.ORI_FP64, ori.ORI_MIXED), parts if len(parts) == 2 else parts * 2):
+            lg, nar, pf = (int(v) for v in spec.split(","))
+            ori.ori_set_layout(ctx, prec, blk_lg=lg, narrow=nar, prefetch=pf)
+
+    def lay_str(prec):
+        d = ori.ori_get_layout(ctx, prec)
+        return f"{d['blk_lg']},{d['narrow']},{d['prefetch']}"
+    layout = {"fp64": lay_str(ori.ORI_FP64), "c64": lay_str(ori.ORI_MIXED)}
+    log(f"[bench] layout (blk_lg,narrow,prefetch): {layout}")
 
     def step(precision):
         ori.ori_load(ctx, k, h, N, u0)
@@ -250,7 +271,7 @@ def main():
     bytes64 = pass_bytes(n, 16)
     avg_ms = prof64[dom][0]
     achieved = bytes64[dom_kind] / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(dom_kind + "_c128", n)
+    traffic = read_traffic(dom_kind + "_c128", n, layout["fp64"])
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": bytes64[dom_kind], "avg_launch_ms": round(avg_ms, 5),
@@ -300,7 +321,8 @@ def main():
         "config": {"workload": f"ori_red_n{n}_k{k:g}", "n": n, "unknowns": P, "padded_grid": 2 * n,
                    "k": k, "h": "(-1+0.5i)(1+0.1 xi), xi~U[-1,1]", "N": 1, "u0": "plane wave, random alpha",
                    "seed": {256: 5, 128: 1, 512: 4}.get(n, 5), "tol": a.tol,
-                   "step": "ori_load (coefficients + kernel spectrum) + ori_solve complex128 COCG"},
+                   "step": "ori_load (coefficients + kernel spectrum) + ori_solve complex128 COCG",
+                   "layout": layout},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64": {"time_to_tol_s": t_solve64, "iterations": solve64["iterations"], "matvecs": solve64["matvecs"],

@@ -253,7 +253,15 @@ __global__ void __launch_bounds__(NP * TPP) k_zpass(ZArgs a) {
   const int64_t k3 = (w % CT) * NP + t;
   const bool act = k3 < L;
   const cx<T>* __restrict__ kh = static_cast<const cx<T>*>(a.khat);
-  const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(a.tw);
+  // The twiddle table is staged in LDS: read from global memory inside a
+  // stage, a twiddle would wait behind every tile load still in flight
+  // (vector-memory completions are counted in order).
+  __shared__ cx<T> twl[L];
+  {
+    const cx<T>* __restrict__ src = static_cast<const cx<T>*>(a.tw);
+    for (int i = tid; i < L; i += NP * TPP) twl[i] = src[i];
+  }
+  const cx<T>* tw = twl;
   cx<T>* buf = static_cast<cx<T>*>(a.buf);
   ZRegs<T> kv;
 #pragma unroll

@@ -357,3 +357,31 @@ def test_large_solve_sampled_true_residual():
     assert np.linalg.norm(rmx) / scale <= 1e-7
     assert i64["rel_res_true"] < 1e-7 and imx["rel_res_true"] < 1e-7
     assert rel(um, u) <= 1e-6
+
+
+def test_c4_n512_solve_sampled_true_residual():
+    # n = 512 (134 M unknowns, padded 1024^3 grid), k = 10, complex128 and
+    # mixed to 1e-8: sampled rows of eq. 2.19 computed one by one by the oracle
+    case = workloads.named_case("n512_k10")
+    n, k = case["n"], case["k"]
+    P = n ** 3
+    say("[C4] n=512 k=10")
+    with context(n, k, case["h"], case["N"], case["u0"]) as ctx:
+        ug = torch.empty(P, dtype=torch.complex128, device="cuda")
+        _, i64 = ori.ori_solve(ctx, ug, tol=1e-8)
+        u = cpu(ug)
+        _, imx = ori.ori_solve(ctx, ug, tol=1e-8, precision=ori.ORI_MIXED)
+        um = cpu(ug)
+    say(f"   fp64 iters={i64['iterations']} {i64['seconds']:.3f}s true={i64['rel_res_true']:.2e}; "
+        f"mixed inner={imx['iterations']} ref={imx['refinements']} {imx['seconds']:.3f}s true={imx['rel_res_true']:.2e}")
+    rows = np.array([0, P // 2 + n // 2 + 3])
+    pts = O.cell_points(n)
+    D = O.coupling(case["h"], case["N"], n)
+    r64 = O.sample_residual_rows(pts, k, D, u, case["u0"], rows)
+    rmx = O.sample_residual_rows(pts, k, D, um, case["u0"], rows[:1])
+    scale = np.linalg.norm(case["u0"][rows])
+    say(f"   sampled residual fp64={np.linalg.norm(r64) / scale:.2e} mixed={abs(rmx[0]):.2e}")
+    assert np.linalg.norm(r64) / scale <= 1e-7
+    assert abs(rmx[0]) / abs(case["u0"][rows[0]]) <= 1e-7
+    assert i64["rel_res_true"] < 1e-7 and imx["rel_res_true"] < 1e-7
+    assert rel(um, u) <= 1e-6
