@@ -11,7 +11,8 @@ Everything is complex128 / float64 NumPy, with LAPACK (``numpy.linalg.solve``)
 as the only library primitive beyond ``numpy.fft`` in the Section 3 route.
 
 Parity pins: every function is pinned by a CPU test in
-``tests/test_oracle_pins.py`` (no function is "parity unpinned").
+``tests/test_oracle_pins.py`` or ``tests/test_physics_pins.py`` (no function
+is "parity unpinned").
 """
 
 from .ori_oracle import (  # noqa: F401
@@ -41,4 +42,13 @@ from .section3 import (  # noqa: F401
     green_table,
     convolve_section3,
     scatter_section3,
+)
+from .physics import (  # noqa: F401
+    sqrt_branch_0_2pi,
+    refraction_from_h,
+    h_for_refraction,
+    cell_charges,
+    particle_charge,
+    scattered_field,
+    far_field,
 )
