@@ -189,6 +189,44 @@ ori_status ori_gradient(ori_ctx ctx, const ori_solve_opts* opts, const void* u_t
  * stay complex128).  Used by tests and the benchmark. */
 ori_status ori_matvec(ori_ctx ctx, int32_t op, int32_t precision, const void* x, void* y);
 
+/* ---- what the solution is used for (Section 2, Section 4) ---------------- */
+
+/* Charges of the cells: q_p = -D_p u_p = -c_S h_p N_p |Delta_p| u_p, the sum
+ * of the particle charges Q_m = -c_S a^{2-kappa} h(x_m) u_e(x_m) (eq. 2.13)
+ * over the a^{-(2-kappa)} N_p |Delta_p| particles of cell p (eq. 2.18).
+ * u, q: device complex128[nrhs][P] (u a solution of eq. 2.19 for the loaded
+ * data).  Synchronises the context stream. */
+ori_status ori_charges(ori_ctx ctx, const void* u, void* q);
+
+/* Scattered field v(x) = sum_p G(x, x_p) q_p at M points (eq. 2.10 with the
+ * particles of each cell at x_p, G of eq. 2.6a); u0(x) + v(x) is the total
+ * field.  A cell point at distance exactly 0 is left out, as in the sum of
+ * eq. 2.19, so at the cell points u0 + v reproduces u.  x: device
+ * double[M][3]; v: device complex128[nrhs][M].  Direct sum in FP64, O(M P)
+ * work, deterministic.  Synchronises the context stream. */
+ori_status ori_scattered_field(ori_ctx ctx, const void* u, const double* x, int64_t M, void* v);
+
+/* Far-field amplitude A(beta) = (1 / 4 pi) sum_p exp(-i k beta . x_p) q_p,
+ * so that v(r beta) = A(beta) e^{ikr} / r + O(1/r^2) as r -> infinity.
+ * beta: device double[M][3] unit directions; A: device complex128[nrhs][M].
+ * Synchronises the context stream. */
+ori_status ori_far_field(ori_ctx ctx, const void* u, const double* beta, int64_t M, void* A);
+
+/* Refraction recipe on the grid (P entries each; ctx supplies P, the stream
+ * and scratch and need not be loaded).  ori_refraction_index:
+ * n = [n0^2 - c_S h N / k^2]^{1/2} (eq. 4.1, from eqs. 2.20a and 2.24) with
+ * the branch z^{1/2} = |z|^{1/2} e^{i phi/2}, phi = arg z in [0, 2 pi)
+ * (eq. 4.2).  ori_design_impedance: the h that gives n,
+ * h = k^2 (n0^2 - n^2) / (c_S N) (eqs. 2.25, 2.26).  c_S: shape constant
+ * (4 pi for spheres).  n0, h, n: device complex128[P]; N: device double[P]
+ * or NULL for N = 1.  Entries with NaN/Inf, or with N < 0 (N <= 0 for the
+ * design), get 0 and make the call return ORI_ERR_INVALID_ARG.
+ * Synchronises the context stream. */
+ori_status ori_refraction_index(ori_ctx ctx, double k, double c_S, const void* n0, const void* h,
+                                const double* N, void* n);
+ori_status ori_design_impedance(ori_ctx ctx, double k, double c_S, const void* n0, const void* n,
+                                const double* N, void* h);
+
 /* Layout of the FFT passes of one precision.  Performance only: blk_lg and
  * prefetch leave every result bitwise unchanged; narrow tiles may change
  * results at the level of rounding. */

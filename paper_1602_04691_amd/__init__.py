@@ -101,6 +101,11 @@ def lib():
             "ori_profile_enable": (ctypes.c_int, [P, I32]),
             "ori_profile_read": (ctypes.c_int, [P, I32, ctypes.POINTER(ctypes.c_char_p),
                                                 ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(I32)]),
+            "ori_charges": (ctypes.c_int, [P, P, P]),
+            "ori_scattered_field": (ctypes.c_int, [P, P, P, I64, P]),
+            "ori_far_field": (ctypes.c_int, [P, P, P, I64, P]),
+            "ori_refraction_index": (ctypes.c_int, [P, D, D, P, P, P, P]),
+            "ori_design_impedance": (ctypes.c_int, [P, D, D, P, P, P, P]),
             "ori_get_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout)]),
             "ori_set_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout)]),
             "ori_tune": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout), ctypes.POINTER(D)]),
@@ -296,6 +301,72 @@ def ori_batch_info(ctx, i):
 
 def ori_destroy(ctx):
     ctx.close()
+
+
+def ori_charges(ctx, u, q=None):
+    """q = -D u (cell charges) for a solution u of the loaded problem."""
+    import torch
+    if q is None:
+        q = torch.empty(ctx.nrhs * ctx.P, dtype=torch.complex128, device=u.device)
+    _check(lib().ori_charges(ctx.handle, _dev(u, torch.complex128, ctx.nrhs * ctx.P, "u"),
+                             _dev(q, torch.complex128, ctx.nrhs * ctx.P, "q")), ctx)
+    return q
+
+
+def _points(x, what):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_cuda and x.is_contiguous()
+            and x.dim() == 2 and x.shape[1] == 3):
+        raise TypeError(f"{what} must be a contiguous CUDA float64 tensor of shape (M, 3)")
+    return x
+
+
+def ori_scattered_field(ctx, u, x, v=None):
+    """v(x) = sum_p G(x, x_p) q_p at the rows of x (M, 3); returns v (nrhs * M)."""
+    import torch
+    x = _points(x, "x")
+    M = x.shape[0]
+    if v is None:
+        v = torch.empty(ctx.nrhs * M, dtype=torch.complex128, device=x.device)
+    _check(lib().ori_scattered_field(ctx.handle, _dev(u, torch.complex128, ctx.nrhs * ctx.P, "u"),
+                                     ctypes.c_void_p(x.data_ptr()), M,
+                                     _dev(v, torch.complex128, ctx.nrhs * M, "v")), ctx)
+    return v
+
+
+def ori_far_field(ctx, u, beta, A=None):
+    """A(beta) = (1/4 pi) sum_p exp(-i k beta.x_p) q_p for unit rows of beta (M, 3)."""
+    import torch
+    beta = _points(beta, "beta")
+    M = beta.shape[0]
+    if A is None:
+        A = torch.empty(ctx.nrhs * M, dtype=torch.complex128, device=beta.device)
+    _check(lib().ori_far_field(ctx.handle, _dev(u, torch.complex128, ctx.nrhs * ctx.P, "u"),
+                               ctypes.c_void_p(beta.data_ptr()), M,
+                               _dev(A, torch.complex128, ctx.nrhs * M, "A")), ctx)
+    return A
+
+
+def ori_refraction_index(ctx, k, n0, h, N=None, c_S=4 * 3.141592653589793, n=None):
+    """n = [n0^2 - c_S h N / k^2]^{1/2}, arg in [0, 2 pi) (P entries)."""
+    import torch
+    if n is None:
+        n = torch.empty(ctx.P, dtype=torch.complex128, device=h.device)
+    _check(lib().ori_refraction_index(ctx.handle, float(k), float(c_S), _dev(n0, torch.complex128, ctx.P, "n0"),
+                                      _dev(h, torch.complex128, ctx.P, "h"), _dev(N, torch.float64, ctx.P, "N"),
+                                      _dev(n, torch.complex128, ctx.P, "n")), ctx)
+    return n
+
+
+def ori_design_impedance(ctx, k, n0, n, N=None, c_S=4 * 3.141592653589793, h=None):
+    """h = k^2 (n0^2 - n^2) / (c_S N): the impedance that creates n (P entries)."""
+    import torch
+    if h is None:
+        h = torch.empty(ctx.P, dtype=torch.complex128, device=n.device)
+    _check(lib().ori_design_impedance(ctx.handle, float(k), float(c_S), _dev(n0, torch.complex128, ctx.P, "n0"),
+                                      _dev(n, torch.complex128, ctx.P, "n"), _dev(N, torch.float64, ctx.P, "N"),
+                                      _dev(h, torch.complex128, ctx.P, "h")), ctx)
+    return h
 
 
 def ori_get_layout(ctx, precision=ORI_FP64):

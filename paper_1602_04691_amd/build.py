@@ -41,6 +41,7 @@ def _sources():
     units = [(os.path.join(CSRC, "passes.hip"), f"passes_L{L}.o", [f"-DORI_L={L}"])
              for L in supported_lengths()]
     units.append((os.path.join(CSRC, "aux.hip"), "aux.o", []))
+    units.append((os.path.join(CSRC, "physics.hip"), "physics.o", []))
     units.append((os.path.join(CSRC, "ori_api.cpp"), "ori_api.o", ["-x", "hip"]))
     return units
 

@@ -158,6 +158,40 @@ const LengthKernels* kernels_for_length(int L);
 // (red_blocks(P), nrhs) workgroups; right-hand side rhs writes partials
 // [rhs * red_blocks(P), (rhs + 1) * red_blocks(P)).
 // ---------------------------------------------------------------------------
+// Field sums over the cells (eq. 2.10): points a.pts[m0 .. m0 + mb) of M,
+// cells in chunks of `chunk`, partials [nrhs][mb][nchunk], results
+// out[nrhs][M].
+struct FieldArgs {
+  const cxd* u;      // [nrhs][P] solution of eq. 2.19
+  const cxd* D;      // [P]
+  const double* pts; // [M][3] points (field) or unit directions (far field)
+  cxd* part;
+  cxd* out;
+  int64_t n, P, M, m0, mb, nchunk, chunk, nrhs;
+  double dn, side, offset, k;
+  double origin[3];
+};
+hipError_t launch_field(const FieldArgs& a, bool far, hipStream_t st);
+// q = -D u over the batch
+hipError_t launch_charges(const void* D, const void* u, int64_t P, int64_t nrhs, void* q, hipStream_t st);
+
+// Refraction recipe, elementwise over P entries: design = 1 gives
+// h = k^2 (n0^2 - n^2) / (c_S N) from in = n; design = 0 gives
+// n = [n0^2 - c_S h N / k^2]^{1/2} (arg in [0, 2 pi)) from in = h.
+// bad[refraction_blocks(P)] counts rejected entries per workgroup.
+struct RefractionArgs {
+  const cxd* n0;
+  const cxd* in;
+  const double* N;  // NULL: N = 1
+  cxd* out;
+  double* bad;
+  int64_t P;
+  double k, c_s;
+  int32_t design, pad;
+};
+int64_t refraction_blocks(int64_t P);
+hipError_t launch_refraction(const RefractionArgs& a, hipStream_t st);
+
 constexpr int kRedThreads = 256;
 constexpr int64_t kRedBlocksMax = 1024;
 inline int64_t red_blocks(int64_t P) {

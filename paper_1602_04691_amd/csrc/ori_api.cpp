@@ -809,6 +809,77 @@ double elapsed(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+ori_status field_sum(ori_ctx c, const void* u, const double* pts, int64_t M, void* out, bool far) {
+  ORI_TRY(guard(c));
+  if (!c->loaded) return set_err(c, ORI_ERR_INVALID_ARG, "ori_load has not succeeded on this context");
+  if (M < 0) return set_err(c, ORI_ERR_INVALID_ARG, "M = %lld must be >= 0", (long long)M);
+  if (M == 0) return ORI_OK;
+  ORI_TRY(check_dev_ptr(c, u, c->nrhs * c->P * 16, "u"));
+  ORI_TRY(check_dev_ptr(c, pts, M * 3 * 8, far ? "beta" : "x"));
+  ORI_TRY(check_dev_ptr(c, out, c->nrhs * M * 16, far ? "A" : "v"));
+  FieldArgs a{};
+  a.u = static_cast<const cxd*>(u);
+  a.D = c->D;
+  a.pts = pts;
+  a.part = c->t1;  // P complex values of scratch
+  a.out = static_cast<cxd*>(out);
+  a.n = c->n;
+  a.P = c->P;
+  a.M = M;
+  a.nrhs = c->nrhs;
+  a.chunk = int64_t{1} << 16;
+  a.nchunk = (c->P + a.chunk - 1) / a.chunk;
+  a.dn = static_cast<double>(c->n);
+  a.side = c->grid.side;
+  a.offset = c->grid.cell_offset;
+  a.k = c->k;
+  for (int d = 0; d < 3; ++d) a.origin[d] = c->grid.origin[d];
+  // points per launch: the partials [nrhs][mb][nchunk] fit the P-value scratch
+  int64_t mb = c->P / (c->nrhs * a.nchunk);
+  if (mb < 1) mb = 1;
+  if (mb > 65535) mb = 65535;
+  for (int64_t m0 = 0; m0 < M; m0 += mb) {
+    a.m0 = m0;
+    a.mb = std::min(mb, M - m0);
+    if (c->nrhs * a.mb * a.nchunk > c->P) return set_err(c, ORI_ERR_UNSUPPORTED, "field scratch too small");
+    ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_field(a, far, c->stream); }));
+  }
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  return ORI_OK;
+}
+
+ori_status refraction(ori_ctx c, double k, double c_s, const void* n0, const void* in, const double* N, void* out,
+                      bool design) {
+  ORI_TRY(guard(c));
+  if (!(k > 0.0) || !std::isfinite(k)) return set_err(c, ORI_ERR_INVALID_ARG, "k must be finite and > 0");
+  if (!(c_s > 0.0) || !std::isfinite(c_s)) return set_err(c, ORI_ERR_INVALID_ARG, "c_S must be finite and > 0");
+  const int64_t bytes = c->P * 16;
+  ORI_TRY(check_dev_ptr(c, n0, bytes, "n0"));
+  ORI_TRY(check_dev_ptr(c, in, bytes, design ? "n" : "h"));
+  if (N) ORI_TRY(check_dev_ptr(c, N, c->P * 8, "N"));
+  ORI_TRY(check_dev_ptr(c, out, bytes, design ? "h" : "n"));
+  RefractionArgs a{};
+  a.n0 = static_cast<const cxd*>(n0);
+  a.in = static_cast<const cxd*>(in);
+  a.N = N;
+  a.out = static_cast<cxd*>(out);
+  a.bad = c->partials;
+  a.P = c->P;
+  a.k = k;
+  a.c_s = c_s;
+  a.design = design ? 1 : 0;
+  ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_refraction(a, c->stream); }));
+  const int64_t nb = refraction_blocks(c->P);
+  std::vector<double> bad(nb);
+  ORI_HIP(c, hipMemcpyAsync(bad.data(), c->partials, nb * 8, hipMemcpyDeviceToHost, c->stream));
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  double nbad = 0.0;
+  for (double b : bad) nbad += b;
+  if (nbad > 0.0)
+    return set_err(c, ORI_ERR_INVALID_ARG, "%.0f entries hold NaN/Inf or N %s 0 (their output is 0)", nbad,
+                   design ? "<=" : "<");
+  return ORI_OK;
+}
 }  // namespace
 
 // ===========================================================================
@@ -1029,6 +1100,38 @@ ori_status ori_matvec(ori_ctx c, int32_t op, int32_t precision, const void* x, v
   ORI_TRY(matvec(c, PREC_F64, fp, f1, i1, nullptr));
   ORI_HIP(c, hipStreamSynchronize(c->stream));
   return ORI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// physics of the solution: charges, field, far field, refraction recipe
+// ---------------------------------------------------------------------------
+ori_status ori_charges(ori_ctx c, const void* u, void* q) {
+  ORI_TRY(guard(c));
+  if (!c->loaded) return set_err(c, ORI_ERR_INVALID_ARG, "ori_load has not succeeded on this context");
+  const int64_t bytes = c->nrhs * c->P * 16;
+  ORI_TRY(check_dev_ptr(c, u, bytes, "u"));
+  ORI_TRY(check_dev_ptr(c, q, bytes, "q"));
+  ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_charges(c->D, u, c->P, c->nrhs, q, c->stream); }));
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  return ORI_OK;
+}
+
+ori_status ori_scattered_field(ori_ctx c, const void* u, const double* x, int64_t M, void* v) {
+  return field_sum(c, u, x, M, v, false);
+}
+
+ori_status ori_far_field(ori_ctx c, const void* u, const double* beta, int64_t M, void* A) {
+  return field_sum(c, u, beta, M, A, true);
+}
+
+ori_status ori_refraction_index(ori_ctx c, double k, double c_s, const void* n0, const void* h, const double* N,
+                                void* n) {
+  return refraction(c, k, c_s, n0, h, N, n, false);
+}
+
+ori_status ori_design_impedance(ori_ctx c, double k, double c_s, const void* n0, const void* n, const double* N,
+                                void* h) {
+  return refraction(c, k, c_s, n0, n, N, h, true);
 }
 
 ori_status ori_get_layout(ori_ctx c, int32_t precision, ori_layout* out) {

@@ -1,0 +1,187 @@
+// What the solution of eq. 2.19 is used for.
+//
+//  * Charges (eq. 2.13 summed over the particles of a cell with eq. 2.18):
+//    Q_p = -c_S h_p N_p |Delta_p| u_p = -D_p u_p.
+//  * The scattered field anywhere (eq. 2.10, the particles of each cell at
+//    x_p): v(x) = sum_p G(x, x_p) Q_p, G of eq. 2.6a; a cell point at distance
+//    exactly 0 is left out, as the sum of eq. 2.19 leaves out p = q.
+//  * Its far-field amplitude: v(r beta) = A(beta) e^{ikr} / r + O(1/r^2) with
+//    A(beta) = (1 / 4 pi) sum_p e^{-ik beta.x_p} Q_p.
+//  * The refraction recipe (eqs. 2.24-2.26, 4.1-4.2): n = [n0^2 - c_S h N /
+//    k^2]^{1/2} with the branch arg in [0, 2 pi), and the h that creates a
+//    desired n.
+//
+// The sums over cells are direct (M points x P cells, FP64): workgroup
+// (chunk of cells, point, right-hand side) writes one partial; a second
+// kernel adds the partials of each point in a fixed order, so results are
+// deterministic.
+#include "cx.h"
+#include "kernels.h"
+
+namespace ori {
+namespace {
+
+constexpr int kFieldThreads = 256;
+constexpr double kFourPi = 12.566370614359172954;
+
+__device__ __forceinline__ cxd block_sum_cx(cxd v) {
+  __shared__ double sh[2 * (kFieldThreads / 64)];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.re += __shfl_xor(v.re, off, 64);
+    v.im += __shfl_xor(v.im, off, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[2 * w] = v.re;
+    sh[2 * w + 1] = v.im;
+  }
+  __syncthreads();
+  cxd s{0.0, 0.0};
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kFieldThreads / 64; ++i) s = s + cxd{sh[2 * i], sh[2 * i + 1]};
+  return s;
+}
+
+// cell point of p = (i1 n + i2) n + i3: origin + side (i + offset) / n
+__device__ __forceinline__ void cell_point(const FieldArgs& a, int64_t p, double (&x)[3]) {
+  const int64_t i3 = p % a.n, r = p / a.n, i2 = r % a.n, i1 = r / a.n;
+  const int64_t i[3] = {i1, i2, i3};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) x[d] = a.origin[d] + a.side * (static_cast<double>(i[d]) + a.offset) / a.dn;
+}
+
+// grid (chunks, points, right-hand sides): partial sum over one chunk of cells
+template <bool FAR>
+__global__ void __launch_bounds__(kFieldThreads) k_field_partial(FieldArgs a) {
+  const int64_t chunk = blockIdx.x, m = blockIdx.y, rhs = blockIdx.z;
+  const double* y = a.pts + 3 * (a.m0 + m);
+  const double y0 = y[0], y1 = y[1], y2 = y[2];
+  const cxd* __restrict__ u = a.u + rhs * a.P;
+  const int64_t p0 = chunk * a.chunk, p1 = p0 + a.chunk < a.P ? p0 + a.chunk : a.P;
+  cxd acc{0.0, 0.0};
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += kFieldThreads) {
+    double x[3];
+    cell_point(a, p, x);
+    const cxd q = scale(a.D[p] * u[p], -1.0);  // Q_p
+    double s, c;
+    if (FAR) {
+      // e^{-ik beta.x_p} Q_p
+      sincos(-a.k * (y0 * x[0] + y1 * x[1] + y2 * x[2]), &s, &c);
+      acc = acc + cxd{c, s} * q;
+    } else {
+      const double d0 = y0 - x[0], d1 = y1 - x[1], d2 = y2 - x[2];
+      const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      if (r > 0.0) {
+        sincos(a.k * r, &s, &c);
+        const double g = 1.0 / (kFourPi * r);  // G = e^{ikr} / (4 pi r)
+        acc = acc + cxd{c * g, s * g} * q;
+      }
+    }
+  }
+  const cxd t = block_sum_cx(acc);
+  if (threadIdx.x == 0) a.part[(rhs * a.mb + m) * a.nchunk + chunk] = t;
+}
+
+// one thread per (point, right-hand side): chunks in order
+__global__ void __launch_bounds__(64) k_field_finalize(FieldArgs a, int32_t far) {
+  const int64_t m = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x, rhs = blockIdx.y;
+  if (m >= a.mb) return;
+  const cxd* part = a.part + (rhs * a.mb + m) * a.nchunk;
+  cxd s{0.0, 0.0};
+  for (int64_t c = 0; c < a.nchunk; ++c) s = s + part[c];
+  if (far) s = scale(s, 1.0 / kFourPi);
+  a.out[rhs * a.M + a.m0 + m] = s;
+}
+
+__global__ void __launch_bounds__(256) k_charges(const cxd* __restrict__ D, const cxd* __restrict__ u, int64_t P,
+                                                 cxd* __restrict__ q) {
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    q[off + i] = scale(D[i] * u[off + i], -1.0);
+}
+
+// z^{1/2} with arg z in [0, 2 pi) (eq. 4.2): the root with Im >= 0, and the
+// positive root on the cut [0, +inf).  The larger component comes from a
+// square root, the smaller one from |Im z| / (2 * larger), so neither loses
+// digits to cancellation.
+__device__ __forceinline__ cxd sqrt_upper(cxd z) {
+  if (z.re == 0.0 && z.im == 0.0) return cxd{0.0, 0.0};
+  const double r = hypot(z.re, z.im), ay = fabs(z.im);
+  double re, im;
+  if (z.re >= 0.0) {
+    re = sqrt(0.5 * (r + z.re));
+    im = ay / (2.0 * re);
+  } else {
+    im = sqrt(0.5 * (r - z.re));
+    re = ay / (2.0 * im);
+  }
+  if (z.im < 0.0) re = -re;  // arg in (pi, 2 pi): Re < 0
+  return cxd{re, im};
+}
+
+// partials[block] = number of bad entries (N <= 0 or a non-finite input)
+__global__ void __launch_bounds__(256) k_refraction(RefractionArgs a) {
+  __shared__ double sh[4];
+  double bad = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.P;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const cxd n0 = a.n0[i], x = a.in[i];
+    const double N = a.N ? a.N[i] : 1.0;
+    const bool ok = isfinite(n0.re) && isfinite(n0.im) && isfinite(x.re) && isfinite(x.im) && isfinite(N) &&
+                    (a.design ? N > 0.0 : N >= 0.0);
+    cxd out{0.0, 0.0};
+    if (ok) {
+      if (a.design) {
+        // h = k^2 (n0^2 - n^2) / (c_S N)  (eqs. 2.25, 2.26)
+        out = scale(n0 * n0 - x * x, a.k * a.k / (a.c_s * N));
+      } else {
+        // n = [n0^2 - c_S h N / k^2]^{1/2}  (eq. 4.1)
+        out = sqrt_upper(n0 * n0 - scale(x, a.c_s * N / (a.k * a.k)));
+      }
+    }
+    a.out[i] = out;
+    bad += ok ? 0.0 : 1.0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) a.bad[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+}  // namespace
+
+hipError_t launch_field(const FieldArgs& a, bool far, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(a.nchunk), static_cast<unsigned>(a.mb), static_cast<unsigned>(a.nrhs));
+  if (far)
+    hipLaunchKernelGGL((k_field_partial<true>), grid, dim3(kFieldThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_field_partial<false>), grid, dim3(kFieldThreads), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_field_finalize, dim3(static_cast<unsigned>((a.mb + 63) / 64), static_cast<unsigned>(a.nrhs)),
+                     dim3(64), 0, st, a, far ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_charges(const void* D, const void* u, int64_t P, int64_t nrhs, void* q, hipStream_t st) {
+  int64_t g = (P + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_charges, dim3(static_cast<unsigned>(g), static_cast<unsigned>(nrhs)), dim3(256), 0, st,
+                     static_cast<const cxd*>(D), static_cast<const cxd*>(u), P, static_cast<cxd*>(q));
+  return hipGetLastError();
+}
+
+int64_t refraction_blocks(int64_t P) {
+  const int64_t g = (P + 255) / 256;
+  return g < 1 ? 1 : (g > 1024 ? 1024 : g);
+}
+
+hipError_t launch_refraction(const RefractionArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_refraction, dim3(static_cast<unsigned>(refraction_blocks(a.P))), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace ori
