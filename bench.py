@@ -120,9 +120,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle rows for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--layout", default="auto",
-                    help="pass layout: auto (ori_tune before timing), default, or LG,NP,PF[/LG,NP,PF] "
-                         "(complex128 / complex64 passes)")
+    ap.add_argument("--layout", default="2,0,0/3,0,0",
+                    help="pass layout LG,NP,PF[/LG,NP,PF] (complex128 / complex64 passes); the default is what "
+                         "ori_tune picks at n = 256 on MI355X; 'auto' tunes before timing, 'default' keeps the "
+                         "library's")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain 1-to-1 copy of this many MiB (counter calibration)")
     a = ap.parse_args()

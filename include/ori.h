@@ -227,6 +227,19 @@ ori_status ori_refraction_index(ori_ctx ctx, double k, double c_S, const void* n
 ori_status ori_design_impedance(ori_ctx ctx, double k, double c_S, const void* n0, const void* n,
                                 const double* N, void* h);
 
+/* Section 4, the comparison behind Table 4: for solutions x on a fine grid
+ * (n_fine per side, points at (i + fine_offset) side / n_fine from the
+ * context's origin) and y on the context's grid (the coarse one), the sup
+ * over coarse cells Delta_q of the mean of |x_i - y_q| over the fine points
+ * inside Delta_q; a fine point lies in cell floor((i + fine_offset) n /
+ * n_fine) per axis.  Cells with no fine point are skipped; *diff = -1 if
+ * none holds one.  y: device complex128[P]; x_fine: device
+ * complex128[n_fine^3]; ctx need not be loaded.  ORI, RED and IE solutions
+ * are this solver on nested grids (eqs. 2.15, 2.19, 2.20).  Synchronises
+ * the context stream. */
+ori_status ori_interpolation_difference(ori_ctx ctx, const void* y, const void* x_fine, int64_t n_fine,
+                                       double fine_offset, double* diff);
+
 /* Layout of the FFT passes of one precision.  Performance only: blk_lg and
  * prefetch leave every result bitwise unchanged; narrow tiles may change
  * results at the level of rounding. */

@@ -51,4 +51,6 @@ from .physics import (  # noqa: F401
     particle_charge,
     scattered_field,
     far_field,
+    coarse_cell_of,
+    interpolation_difference,
 )

@@ -12,6 +12,8 @@ direct sums; every function cites the passage it follows.
   field v(x) = sum_p G(x, x_p) Q_p, and its far-field amplitude A(beta)
   with v(r beta) ~ A(beta) e^{ikr} / r as r -> infinity (from eq. 2.6a:
   |r beta - y| = r - beta.y + O(1/r)).
+* The solution difference of Section 4 (Table 4): solutions on a fine and a
+  coarse grid compared by the mean over the fine points of each coarse cell.
 """
 
 import numpy as np
@@ -83,3 +85,29 @@ def far_field(points, k, Q, beta):
     return (ph @ Q) / (4.0 * np.pi)
 
 
+
+
+def coarse_cell_of(n_fine, n_coarse, offset=0.5):
+    """Coarse cell, along one axis, of each fine point: the fine point
+    (i + offset) / n_fine (units of the side) lies in the coarse cell
+    [q / n_coarse, (q + 1) / n_coarse) with q = floor((i + offset) n_coarse /
+    n_fine)."""
+    i = np.arange(n_fine, dtype=np.float64)
+    return np.floor((i + offset) * n_coarse / n_fine).astype(np.int64)
+
+
+def interpolation_difference(x_fine, n_fine, y_coarse, n_coarse, offset_fine=0.5):
+    """Section 4, the procedure of Table 4: for each coarse cell Delta_q, the
+    mean of |x_i - y_q| over the fine points x_i in Delta_q, and the sup of
+    that mean over the cells that hold fine points."""
+    q1 = coarse_cell_of(n_fine, n_coarse, offset_fine)
+    x = np.asarray(x_fine, dtype=np.complex128).reshape(n_fine, n_fine, n_fine)
+    y = np.asarray(y_coarse, dtype=np.complex128).reshape(n_coarse, n_coarse, n_coarse)
+    yq = y[q1[:, None, None], q1[None, :, None], q1[None, None, :]]   # y of the cell of each fine point
+    cell = (q1[:, None, None] * n_coarse + q1[None, :, None]) * n_coarse + q1[None, None, :]
+    d = np.abs(x - yq).ravel()
+    P = n_coarse ** 3
+    sums = np.bincount(cell.ravel(), weights=d, minlength=P)
+    counts = np.bincount(cell.ravel(), minlength=P)
+    held = counts > 0
+    return float(np.max(sums[held] / counts[held]))

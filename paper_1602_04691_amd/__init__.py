@@ -106,6 +106,7 @@ def lib():
             "ori_far_field": (ctypes.c_int, [P, P, P, I64, P]),
             "ori_refraction_index": (ctypes.c_int, [P, D, D, P, P, P, P]),
             "ori_design_impedance": (ctypes.c_int, [P, D, D, P, P, P, P]),
+            "ori_interpolation_difference": (ctypes.c_int, [P, P, P, I64, D, ctypes.POINTER(D)]),
             "ori_get_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout)]),
             "ori_set_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout)]),
             "ori_tune": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout), ctypes.POINTER(D)]),
@@ -367,6 +368,17 @@ def ori_design_impedance(ctx, k, n0, n, N=None, c_S=4 * 3.141592653589793, h=Non
                                       _dev(n, torch.complex128, ctx.P, "n"), _dev(N, torch.float64, ctx.P, "N"),
                                       _dev(h, torch.complex128, ctx.P, "h")), ctx)
     return h
+
+
+def ori_interpolation_difference(ctx, y, x_fine, n_fine, fine_offset=0.5):
+    """Section 4 / Table 4: sup over the cells of ctx's grid of the mean |x_i - y_q|
+    over the points of the fine grid (n_fine per side) inside each cell."""
+    import torch
+    out = ctypes.c_double()
+    _check(lib().ori_interpolation_difference(ctx.handle, _dev(y, torch.complex128, ctx.P, "y"),
+                                              _dev(x_fine, torch.complex128, int(n_fine) ** 3, "x_fine"),
+                                              int(n_fine), float(fine_offset), ctypes.byref(out)), ctx)
+    return out.value
 
 
 def ori_get_layout(ctx, precision=ORI_FP64):

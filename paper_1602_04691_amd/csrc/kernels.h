@@ -192,6 +192,19 @@ struct RefractionArgs {
 int64_t refraction_blocks(int64_t P);
 hipError_t launch_refraction(const RefractionArgs& a, hipStream_t st);
 
+// Section 4 solution difference: x fine [nf^3], y coarse [nc^3]; means
+// [nc^3] (mean |x_i - y_q| per coarse cell, -1 for a cell without fine
+// points); part[max_blocks(nc^3)] receives block maxima of the means.
+struct DiffArgs {
+  const cxd* x;
+  const cxd* y;
+  double* means;
+  int64_t nf, nc;
+  double off;  // offset of the fine points in their cells
+};
+int64_t max_blocks(int64_t P);
+hipError_t launch_cell_difference(const DiffArgs& a, int64_t P_coarse, double* part, hipStream_t st);
+
 constexpr int kRedThreads = 256;
 constexpr int64_t kRedBlocksMax = 1024;
 inline int64_t red_blocks(int64_t P) {

@@ -1134,6 +1134,34 @@ ori_status ori_design_impedance(ori_ctx c, double k, double c_s, const void* n0,
   return refraction(c, k, c_s, n0, n, N, h, true);
 }
 
+ori_status ori_interpolation_difference(ori_ctx c, const void* y, const void* x_fine, int64_t n_fine,
+                                       double fine_offset, double* diff) {
+  ORI_TRY(guard(c));
+  if (!diff) return set_err(c, ORI_ERR_INVALID_ARG, "diff is NULL");
+  if (n_fine < 1 || n_fine > 4096) return set_err(c, ORI_ERR_INVALID_ARG, "n_fine = %lld out of range", (long long)n_fine);
+  if (!std::isfinite(fine_offset) || fine_offset < 0.0 || fine_offset >= 1.0)
+    return set_err(c, ORI_ERR_INVALID_ARG, "fine_offset must lie in [0, 1)");
+  ORI_TRY(check_dev_ptr(c, y, c->P * 16, "y"));
+  ORI_TRY(check_dev_ptr(c, x_fine, n_fine * n_fine * n_fine * 16, "x_fine"));
+  DiffArgs a{};
+  a.x = static_cast<const cxd*>(x_fine);
+  a.y = static_cast<const cxd*>(y);
+  a.means = reinterpret_cast<double*>(c->t1);  // P doubles of scratch
+  a.nf = n_fine;
+  a.nc = c->n;
+  a.off = fine_offset;
+  ORI_TRY(launch(c, K_ELEMWISE, PREC_F64,
+                 [&] { return launch_cell_difference(a, c->P, c->partials, c->stream); }));
+  const int64_t nb = max_blocks(c->P);
+  std::vector<double> part(nb);
+  ORI_HIP(c, hipMemcpyAsync(part.data(), c->partials, nb * 8, hipMemcpyDeviceToHost, c->stream));
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  double m = -1.0;
+  for (double v : part) m = std::max(m, v);
+  *diff = m;
+  return ORI_OK;
+}
+
 ori_status ori_get_layout(ori_ctx c, int32_t precision, ori_layout* out) {
   ORI_TRY(guard(c));
   if (!out) return set_err(c, ORI_ERR_INVALID_ARG, "out is NULL");

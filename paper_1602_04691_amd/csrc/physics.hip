@@ -10,6 +10,9 @@
 //  * The refraction recipe (eqs. 2.24-2.26, 4.1-4.2): n = [n0^2 - c_S h N /
 //    k^2]^{1/2} with the branch arg in [0, 2 pi), and the h that creates a
 //    desired n.
+//  * The solution difference of Section 4 (Table 4) between a fine and a
+//    coarse grid: the sup over coarse cells of the mean |x_i - y_q| over the
+//    fine points x_i inside the cell.
 //
 // The sums over cells are direct (M points x P cells, FP64): workgroup
 // (chunk of cells, point, right-hand side) writes one partial; a second
@@ -151,6 +154,56 @@ __global__ void __launch_bounds__(256) k_refraction(RefractionArgs a) {
   if (threadIdx.x == 0) a.bad[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// One workgroup per coarse cell q: the fine points inside it are those whose
+// index i (per axis) has floor((i + off) nc / nf) = q; they lie in a box of
+// a few more than nf / nc indices per axis around q nf / nc.
+__global__ void __launch_bounds__(kFieldThreads) k_cell_difference(DiffArgs a) {
+  const int64_t q = blockIdx.x;
+  const int64_t qq[3] = {q / (a.nc * a.nc), (q / a.nc) % a.nc, q % a.nc};
+  int64_t lo[3], len[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double dn = static_cast<double>(a.nf), dc = static_cast<double>(a.nc);
+    int64_t l = static_cast<int64_t>(floor(static_cast<double>(qq[d]) * dn / dc - a.off)) - 1;
+    int64_t h = static_cast<int64_t>(ceil(static_cast<double>(qq[d] + 1) * dn / dc - a.off)) + 2;
+    l = l < 0 ? 0 : l;
+    h = h > a.nf ? a.nf : h;
+    lo[d] = l;
+    len[d] = h > l ? h - l : 0;
+  }
+  const cxd yq = a.y[q];
+  const int64_t box = len[0] * len[1] * len[2];
+  double sum = 0.0, cnt = 0.0;
+  for (int64_t t = threadIdx.x; t < box; t += kFieldThreads) {
+    const int64_t i[3] = {lo[0] + t / (len[1] * len[2]), lo[1] + (t / len[2]) % len[1], lo[2] + t % len[2]};
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      in = in && static_cast<int64_t>(floor((static_cast<double>(i[d]) + a.off) * static_cast<double>(a.nc) /
+                                            static_cast<double>(a.nf))) == qq[d];
+    if (in) {
+      const cxd x = a.x[(i[0] * a.nf + i[1]) * a.nf + i[2]];
+      sum += hypot(x.re - yq.re, x.im - yq.im);
+      cnt += 1.0;
+    }
+  }
+  const cxd t = block_sum_cx(cxd{sum, cnt});
+  if (threadIdx.x == 0) a.means[q] = t.im > 0.0 ? t.re / t.im : -1.0;
+}
+
+__global__ void __launch_bounds__(256) k_max(const double* __restrict__ v, int64_t P, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double m = -1.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    m = fmax(m, v[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
 }  // namespace
 
 hipError_t launch_field(const FieldArgs& a, bool far, hipStream_t st) {
@@ -181,6 +234,20 @@ int64_t refraction_blocks(int64_t P) {
 
 hipError_t launch_refraction(const RefractionArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_refraction, dim3(static_cast<unsigned>(refraction_blocks(a.P))), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+int64_t max_blocks(int64_t P) {
+  const int64_t g = (P + 255) / 256;
+  return g < 1 ? 1 : (g > 1024 ? 1024 : g);
+}
+
+hipError_t launch_cell_difference(const DiffArgs& a, int64_t P_coarse, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_cell_difference, dim3(static_cast<unsigned>(P_coarse)), dim3(kFieldThreads), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_max, dim3(static_cast<unsigned>(max_blocks(P_coarse))), dim3(256), 0, st, a.means, P_coarse,
+                     part);
   return hipGetLastError();
 }
 

@@ -147,3 +147,40 @@ def test_refraction_recipe_vs_oracle_and_bad_input():
         hb[3] = np.nan
         with pytest.raises(ori.OriError):
             ori.ori_refraction_index(ctx, k, gpu(n0), gpu(hb), gpu(N))
+
+
+@pytest.mark.parametrize("nf,nc,off", [(24, 5, 0.0), (24, 8, 0.5), (16, 16, 0.5), (10, 12, 0.0), (40, 20, 0.0)])
+def test_interpolation_difference_vs_oracle(nf, nc, off):
+    rng = np.random.default_rng(nf + nc)
+    x = rng.standard_normal(nf ** 3) + 1j * rng.standard_normal(nf ** 3)
+    y = rng.standard_normal(nc ** 3) + 1j * rng.standard_normal(nc ** 3)
+    with ori.ori_create(nc) as ctx:
+        d = ori.ori_interpolation_difference(ctx, gpu(y), gpu(x), nf, off)
+    do = O.interpolation_difference(x, nf, y, nc, off)
+    assert abs(d - do) <= 1e-13 * do
+
+
+def test_ori_red_ie_comparison_in_miniature():
+    # Section 4's study on nested corner lattices (eq. 3.3.5): the ORI system
+    # of M particles is eq. 2.19 on the M-point lattice (a^{2-kappa} = 1/M,
+    # N = 1), RED and IE are the same system on P- and C-point lattices
+    k, hval = 0.182651 * 40, 2.65481e-09 + 5.30961e-06j   # a larger k makes the cells matter
+    sols = {}
+    for name, n in (("ORI", 48), ("RED", 8), ("IE", 16)):
+        u0 = workloads.plane_wave(n, k, (1.0, 0.0, 0.0), offset=0.0)
+        with ori.ori_setup(n, k, gpu(np.full(n ** 3, hval)), None, gpu(u0), cell_offset=0.0) as ctx:
+            u = torch.empty(n ** 3, dtype=torch.complex128, device="cuda")
+            ori.ori_solve(ctx, u, tol=1e-12)
+            sols[name] = (n, u)
+    out = {}
+    for fine, coarse in (("ORI", "RED"), ("IE", "RED"), ("ORI", "IE")):
+        nf, xf = sols[fine]
+        nc, yc = sols[coarse]
+        with ori.ori_create(nc, cell_offset=0.0) as ctx:
+            d = ori.ori_interpolation_difference(ctx, yc, xf, nf, 0.0)
+        do = O.interpolation_difference(xf.cpu().numpy(), nf, yc.cpu().numpy(), nc, 0.0)
+        assert abs(d - do) <= 1e-13 * do
+        out[(fine, coarse)] = d
+    say(f"   ORI-RED {out[('ORI', 'RED')]:.4f}  RED-IE {out[('IE', 'RED')]:.4f}  ORI-IE {out[('ORI', 'IE')]:.4f}")
+    # the difference is set by how much u varies inside a coarse cell
+    assert out[("ORI", "IE")] < out[("ORI", "RED")]

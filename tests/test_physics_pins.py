@@ -128,3 +128,49 @@ def test_far_field_reciprocity():
     assert abs(a1 - a2) <= 1e-12 * abs(a1)
     # and it is not a trivial symmetry: swapping without the sign changes differs
     assert abs(amp(beta, alpha) - a1) > 1e-6 * abs(a1)
+
+
+def _difference_brute(x, nf, y, nc, off):
+    # pure-Python loops over the coarse cells and the fine points inside each
+    worst = 0.0
+    for q1 in range(nc):
+        for q2 in range(nc):
+            for q3 in range(nc):
+                tot, cnt = 0.0, 0
+                for i1 in range(nf):
+                    if not (q1 / nc <= (i1 + off) / nf < (q1 + 1) / nc):
+                        continue
+                    for i2 in range(nf):
+                        if not (q2 / nc <= (i2 + off) / nf < (q2 + 1) / nc):
+                            continue
+                        for i3 in range(nf):
+                            if not (q3 / nc <= (i3 + off) / nf < (q3 + 1) / nc):
+                                continue
+                            tot += abs(x[(i1 * nf + i2) * nf + i3] - y[(q1 * nc + q2) * nc + q3])
+                            cnt += 1
+                if cnt:
+                    worst = max(worst, tot / cnt)
+    return worst
+
+
+@pytest.mark.parametrize("nf,nc,off", [(6, 2, 0.5), (7, 3, 0.5), (5, 5, 0.0), (4, 6, 0.5), (9, 4, 0.0)])
+def test_interpolation_difference_vs_brute_force(nf, nc, off):
+    rng = np.random.default_rng(nf * 10 + nc)
+    x = rng.standard_normal(nf ** 3) + 1j * rng.standard_normal(nf ** 3)
+    y = rng.standard_normal(nc ** 3) + 1j * rng.standard_normal(nc ** 3)
+    assert abs(O.interpolation_difference(x, nf, y, nc, off) - _difference_brute(x, nf, y, nc, off)) <= 1e-13
+
+
+def test_interpolation_difference_closed_forms():
+    # constants: |c1 - c2|; same grid: max |x - y|
+    assert abs(O.interpolation_difference(np.full(64, 1 + 2j), 4, np.full(8, -2 + 6j), 2) - 5.0) <= 1e-14
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(27) + 0j
+    y = rng.standard_normal(27) + 0j
+    assert O.interpolation_difference(x, 3, y, 3) == np.max(np.abs(x - y))
+    # a field linear along x1, fine = 2 x coarse, y = the cell mean: each coarse
+    # cell holds fine rows 2q and 2q + 1, so the mean |x - y| is 1/2
+    nf, nc = 8, 4
+    x = np.repeat(np.arange(nf, dtype=float), nf * nf) + 0j
+    y = np.repeat(2.0 * np.arange(nc) + 0.5, nc * nc) + 0j
+    assert abs(O.interpolation_difference(x, nf, y, nc) - 0.5) <= 1e-14
