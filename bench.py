@@ -45,8 +45,9 @@ def pass_bytes(n, elem):
     kp3 = (n + 1) ** 3
     vec = 16 if elem == 16 else 8  # inner mixed solve keeps vectors in complex64
     return {
-        # read r, p, S; write p, A (2 n^3)
-        "f1": 4 * n3 * vec + 2 * n3 * elem,
+        # COCG launch: read r, p, S, x; write p, x (the previous step folded
+        # in), A (2 n^3)
+        "f1": 6 * n3 * vec + 2 * n3 * elem,
         # read A (2 n^3), write B (4 n^3)
         "f2": 6 * n3 * elem,
         # read B (4 n^3) and the spectrum octant, write B (4 n^3)
@@ -55,8 +56,8 @@ def pass_bytes(n, elem):
         "i2": 6 * n3 * elem,
         # read A (2 n^3), p, S; write q
         "i1": 2 * n3 * elem + 3 * n3 * vec,
-        # read x, p, r, q; write x, r
-        "update": 6 * n3 * vec,
+        # read r, q; write r
+        "update": 3 * n3 * vec,
     }
 
 

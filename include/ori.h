@@ -88,7 +88,9 @@ typedef struct {
   int32_t check_every;   /* read the residual norm on the host every this many
                             iterations (>= 1; 0 means 1)                             */
   int32_t use_x0;        /* 1: u holds an initial guess of u on entry                */
-  double inner_tol;      /* mixed: relative tolerance of each inner solve (0: 1e-5)  */
+  double inner_tol;      /* mixed: relative tolerance of each inner solve (0: 1e-5);
+                            an inner solve stops earlier when half of the residual
+                            reduction still needed for tol is reached            */
   int32_t max_outer;     /* mixed: refinement cycles (0: 10)                         */
   int32_t true_residual; /* 1: also compute ||u0 - A u|| / ||u0|| (one extra matvec) */
   int32_t graph;         /* 1: after the first check_every iterations, run each block

@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(kRedThreads)
 // fixed order and update its scalars.
 __global__ void __launch_bounds__(kRedThreads)
     k_finalize(const double* __restrict__ partials, int64_t nblk, ScalarBlock* scb, int32_t mode, double eps,
-               double tol2, int32_t tol2_of_bb) {
+               double tol2, int32_t tol2_of_bb, const double* __restrict__ tol2_rhs) {
   const double* part = partials + 4 * nblk * blockIdx.x;
   ScalarBlock* sc = scb + blockIdx.x;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kRedThreads)
       sc->alpha_re = 0.0;
       sc->alpha_im = 0.0;
       sc->iters = 0;
-      sc->rr_target = tol2 * (tol2_of_bb ? sc->bb : s2);
+      sc->rr_target = (tol2_rhs ? tol2_rhs[blockIdx.x] : tol2) * (tol2_of_bb ? sc->bb : s2);
       int f = 0;
       if (s2 == 0.0) f |= FLAG_ZERO_RESIDUAL;
       else if (s2 <= sc->rr_target) f |= FLAG_CONVERGED;
@@ -260,8 +260,7 @@ __global__ void __launch_bounds__(kRedThreads)
   ORI_RHS_LOOP(i) {
     cxd rd;
     if (moving) {
-      const cxd pv = cvt<double>(p[off + i]);
-      x[off + i] = cvt<V>(cvt<double>(x[off + i]) + al * pv);
+      if (x) x[off + i] = cvt<V>(cvt<double>(x[off + i]) + al * cvt<double>(p[off + i]));
       const cx<V> rs = cvt<V>(cvt<double>(r[off + i]) - al * cvt<double>(q[off + i]));
       r[off + i] = rs;
       rd = cvt<double>(rs);  // reduce what was stored
@@ -274,6 +273,16 @@ __global__ void __launch_bounds__(kRedThreads)
     acc[2] += norm2(rd);
   }
   block_sum4(acc, partials + 4 * (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x));
+}
+
+template <typename V>
+__global__ void __launch_bounds__(256)
+    k_x_flush(cx<V>* __restrict__ x, const cx<V>* __restrict__ p, int64_t P, const ScalarBlock* __restrict__ scb) {
+  const ScalarBlock* sc = scb + blockIdx.y;
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+  const cxd al = {sc->alpha_re, sc->alpha_im};
+  if (al.re == 0.0 && al.im == 0.0) return;
+  ORI_RHS_LOOP(i) x[off + i] = cvt<V>(cvt<double>(x[off + i]) + al * cvt<double>(p[off + i]));
 }
 
 template <typename V>
@@ -374,9 +383,9 @@ hipError_t launch_rhs(const void* u0, const void* S, int64_t P, int64_t nrhs, vo
 }
 
 hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, ScalarBlock* sc, int32_t mode,
-                           double eps, double tol2, int32_t tol2_of_bb, hipStream_t st) {
+                           double eps, double tol2, int32_t tol2_of_bb, const double* tol2_rhs, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>(nrhs)), dim3(kRedThreads), 0, st, partials, nblk, sc,
-                     mode, eps, tol2, tol2_of_bb);
+                     mode, eps, tol2, tol2_of_bb, tol2_rhs);
   return hipGetLastError();
 }
 
@@ -388,6 +397,18 @@ hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* 
   else
     hipLaunchKernelGGL(k_update<float>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<cxf*>(x),
                        static_cast<const cxf*>(p), static_cast<cxf*>(r), static_cast<const cxf*>(q), P, sc, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_x_flush(int prec, void* x, const void* p, int64_t P, int64_t nrhs, const ScalarBlock* sc,
+                          hipStream_t st) {
+  const dim3 g(static_cast<unsigned>(grid_for(P, 256, 8192)), static_cast<unsigned>(nrhs));
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(k_x_flush<double>, g, dim3(256), 0, st, static_cast<cxd*>(x), static_cast<const cxd*>(p), P,
+                       sc);
+  else
+    hipLaunchKernelGGL(k_x_flush<float>, g, dim3(256), 0, st, static_cast<cxf*>(x), static_cast<const cxf*>(p), P,
+                       sc);
   return hipGetLastError();
 }
 

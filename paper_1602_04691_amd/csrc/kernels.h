@@ -52,6 +52,8 @@ enum Prec : int { PREC_F64 = 0, PREC_F32 = 1 };
 struct ContigFwdArgs {
   const void* x;        // PLAIN input / COCG residual r        (vector type V)
   void* pvec;           // COCG search direction, updated in place (V)
+  void* xvec;           // COCG iterate (V): x += alpha p with the alpha and p of the
+                        // previous iteration, before p is replaced (NULL: no update)
   const void* s_in;     // diagonal scale (V) or NULL
   const ScalarBlock* sc;  // [nrhs]
   int32_t mode;         // 0 PLAIN, 1 COCG
@@ -233,13 +235,18 @@ enum FinalizeMode : int32_t {
   FIN_RHO = 3,     // sums = {rho'.re, rho'.im, rr, -}: beta = rho'/rho, rho = rho', rr, flags
   FIN_NORM = 4,    // sums = {-, -, ||y||^2, -}: aux
 };
-// FIN_INIT: rr_target = tol2 * (tol2_of_bb ? bb : rr)
+// FIN_INIT: rr_target = t2 * (tol2_of_bb ? bb : rr), t2 = tol2_rhs[rhs] when
+// tol2_rhs is not NULL, else tol2
 hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, ScalarBlock* sc, int32_t mode,
-                           double eps, double tol2, int32_t tol2_of_bb, hipStream_t st);
-// x += alpha p; r -= alpha q; partials {r^T r, ||r||^2}; converged
-// right-hand sides (alpha = 0) stay as they are
+                           double eps, double tol2, int32_t tol2_of_bb, const double* tol2_rhs, hipStream_t st);
+// r -= alpha q (and x += alpha p when x is not NULL); partials
+// {r^T r, ||r||^2}; converged right-hand sides (alpha = 0) stay as they are
 hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* q, int64_t P, int64_t nrhs,
                          const ScalarBlock* sc, double* partials, hipStream_t st);
+// x += alpha p per right-hand side (the update left pending by the last
+// COCG iteration, whose F1 would have applied it)
+hipError_t launch_x_flush(int prec, void* x, const void* p, int64_t P, int64_t nrhs, const ScalarBlock* sc,
+                          hipStream_t st);
 // r = m_inv[rhs] * b (converted to prec; m NULL: 1), x = 0; partials {r^T r, ||r||^2}
 hipError_t launch_init(int prec, const void* b, const double* m, void* x, void* r, int64_t P, int64_t nrhs,
                        double* partials, hipStream_t st);

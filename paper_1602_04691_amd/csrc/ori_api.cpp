@@ -129,7 +129,7 @@ struct ori_ctx_s {
   double* partials = nullptr;
   ScalarBlock* sc = nullptr;       // [nrhs]
   ScalarBlock* sc_host = nullptr;  // pinned mirror
-  double* outer_m = nullptr;       // [nrhs] refinement multipliers
+  double* outer_m = nullptr;       // [2 nrhs]: refinement multipliers, then inner tolerances^2
   double* outer_m_host = nullptr;  // pinned
   std::vector<void*> allocs;
 
@@ -219,7 +219,7 @@ Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
   const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
   l.total = l.arena + shared + batch + l.kh + l.khf + align_up(2 * n * 16) + align_up(2 * n * 8) +
-            align_up(l.npart * 4 * 8) + align_up(nrhs * (int64_t)sizeof(ScalarBlock)) + align_up(nrhs * 8);
+            align_up(l.npart * 4 * 8) + align_up(nrhs * (int64_t)sizeof(ScalarBlock)) + align_up(2 * nrhs * 8);
   return l;
 }
 
@@ -297,9 +297,11 @@ ori_status sync_scalars(ori_ctx c) {
   return ORI_OK;
 }
 
-ori_status finalize(ori_ctx c, int64_t nblk, int mode, double tol2 = 0.0, int tol2_of_bb = 0) {
+ori_status finalize(ori_ctx c, int64_t nblk, int mode, double tol2 = 0.0, int tol2_of_bb = 0,
+                    const double* tol2_rhs = nullptr) {
   return launch(c, K_FINALIZE, PREC_F64, [&] {
-    return launch_finalize(c->partials, nblk, c->nrhs, c->sc, mode, kBreakdownEps, tol2, tol2_of_bb, c->stream);
+    return launch_finalize(c->partials, nblk, c->nrhs, c->sc, mode, kBreakdownEps, tol2, tol2_of_bb, tol2_rhs,
+                           c->stream);
   });
 }
 
@@ -427,13 +429,16 @@ bool all_done(ori_ctx c) {
   return true;
 }
 
-// One COCG iteration on every right-hand side: p = r + beta p (p = r when
-// first), q = (I + S G0 S) p with <p,q>, then alpha, x, r and rho.  No
-// memset and no host work, so it can be captured.
+// One COCG iteration on every right-hand side: x += alpha p (the previous
+// iteration's step) and p = r + beta p (p = r when first) in F1, q = (I +
+// S G0 S) p with <p,q>, then alpha, r and rho.  The step x += alpha p of
+// the last iteration is left pending for flush_x.  No memset and no host
+// work, so it can be captured.
 ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, bool first) {
   ContigFwdArgs f1{};
   f1.x = r;
   f1.pvec = p;
+  f1.xvec = x;  // applies the previous iteration's x += alpha p
   f1.s_in = S;
   f1.sc = c->sc;
   f1.mode = 1;
@@ -443,7 +448,7 @@ ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* 
   ORI_TRY(matvec(c, prec, prec, f1, i1, &nblk));
   ORI_TRY(finalize(c, nblk, FIN_MU));
   ORI_TRY(launch(c, K_UPDATE, prec, [&] {
-    return launch_update(prec, x, p, r, q, c->P, c->nrhs, c->sc, c->partials, c->stream);
+    return launch_update(prec, nullptr, p, r, q, c->P, c->nrhs, c->sc, c->partials, c->stream);
   }));
   return finalize(c, rblocks(c), FIN_RHO);
 }
@@ -491,8 +496,23 @@ ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void*
   return ORI_OK;
 }
 
+// x += alpha p left pending by the last iteration
+ori_status flush_x(ori_ctx c, int prec, void* x, const void* p) {
+  return launch(c, K_UPDATE, prec, [&] { return launch_x_flush(prec, x, p, c->P, c->nrhs, c->sc, c->stream); });
+}
+
+ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
+                          int check_every, bool use_graph, CocgOut* out);
+
 ori_status run_cocg(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
                     int check_every, bool use_graph, CocgOut* out) {
+  ORI_TRY(run_cocg_steps(c, prec, x, r, p, q, S, max_iter, check_every, use_graph, out));
+  if (out->iters > 0) ORI_TRY(flush_x(c, prec, x, p));
+  return ORI_OK;
+}
+
+ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
+                          int check_every, bool use_graph, CocgOut* out) {
   ORI_TRY(sync_scalars(c));
   if (all_done(c)) {
     out->all_done = true;
@@ -698,14 +718,21 @@ ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const s
       if (done[i] == 0 && (s.rr <= target[i] || s.rr == 0.0)) done[i] = 1;
       if (done[i] == 0 && outer == 0 && (s.flags & FLAG_BREAKDOWN_RHO)) done[i] = 2;
       c->outer_m_host[i] = done[i] ? 0.0 : std::sqrt(s.rr);
+      // inner tolerance: inner_tol, or looser when the outer tolerance needs
+      // less (the correction reduces the residual by about the inner
+      // tolerance; half of what is left is asked for)
+      double t = o.inner_tol;
+      if (!done[i] && s.rr > 0.0) t = std::max(t, 0.5 * std::sqrt(target[i] / s.rr));
+      c->outer_m_host[R + i] = std::min(t, 0.5) * std::min(t, 0.5);
       all = all && done[i];
     }
     if (all || outer >= o.max_outer || inner_left <= 0) break;
-    ORI_HIP(c, hipMemcpyAsync(c->outer_m, c->outer_m_host, R * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    ORI_HIP(c, hipMemcpyAsync(c->outer_m, c->outer_m_host, 2 * R * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
     ORI_TRY(launch(c, K_INIT, PREC_F32, [&] {
       return launch_init(PREC_F32, c->r, c->outer_m, c->xf, c->rf, P, R, c->partials, c->stream);
     }));
-    ORI_TRY(finalize(c, rblocks(c), FIN_INIT, o.inner_tol * o.inner_tol, 0));
+    ORI_TRY(finalize(c, rblocks(c), FIN_INIT, 0.0, 0, c->outer_m + R));
     CocgOut co;
     ORI_TRY(run_cocg(c, PREC_F32, c->xf, c->rf, c->pf, c->qf, c->Sf, inner_left, o.check_every, o.graph != 0, &co));
     inner_left -= co.iters;
@@ -998,11 +1025,11 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
   ORI_ALLOC(align_up(2 * g->n * 8), c->twf, cxf*);
   ORI_ALLOC(align_up(lay.npart * 4 * 8), c->partials, double*);
   ORI_ALLOC(align_up(R * (int64_t)sizeof(ScalarBlock)), c->sc, ScalarBlock*);
-  ORI_ALLOC(align_up(R * 8), c->outer_m, double*);
+  ORI_ALLOC(align_up(2 * R * 8), c->outer_m, double*);
 #undef ORI_ALLOC
   if (hipHostMalloc(reinterpret_cast<void**>(&c->sc_host), R * sizeof(ScalarBlock), hipHostMallocDefault) !=
           hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->outer_m_host), R * sizeof(double), hipHostMallocDefault) !=
+      hipHostMalloc(reinterpret_cast<void**>(&c->outer_m_host), 2 * R * sizeof(double), hipHostMallocDefault) !=
           hipSuccess) {
     set_err(c, ORI_ERR_OUT_OF_MEMORY, "hipHostMalloc of the scalar mirrors failed");
     return fail(ORI_ERR_OUT_OF_MEMORY);

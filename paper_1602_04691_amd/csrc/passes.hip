@@ -96,8 +96,13 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
   const int64_t ib = pid * a.in_pitch;
   const int64_t db = lp_id * a.in_pitch;  // shared diagonal
   const int64_t ob = pid * a.out_pitch;
-  cx<double> beta = {0.0, 0.0};
-  if (a.mode == 1 && !a.first) beta = cx<double>{a.sc[rhs].beta_re, a.sc[rhs].beta_im};
+  cx<V>* xv = static_cast<cx<V>*>(a.xvec);
+  cx<double> beta = {0.0, 0.0}, alpha = {0.0, 0.0};
+  if (a.mode == 1 && !a.first) {
+    beta = cx<double>{a.sc[rhs].beta_re, a.sc[rhs].beta_im};
+    alpha = cx<double>{a.sc[rhs].alpha_re, a.sc[rhs].alpha_im};
+  }
+  const bool x_moves = xv && (alpha.re != 0.0 || alpha.im != 0.0);
 
   auto load = [&](int e) -> cx<T> {
     if (!act) return cx<T>{};
@@ -105,7 +110,12 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
     cx<double> v;
     if (a.mode == 1) {
       v = cvt<double>(x[i]);
-      if (!a.first) v = v + beta * cvt<double>(pv[i]);
+      if (!a.first) {
+        const cx<double> po = cvt<double>(pv[i]);
+        // the previous iteration's x += alpha p, folded into this pass
+        if (x_moves) xv[i] = cvt<V>(cvt<double>(xv[i]) + alpha * po);
+        v = v + beta * po;
+      }
       pv[i] = cvt<V>(v);
     } else {
       v = cvt<double>(x[i]);
@@ -202,7 +212,15 @@ __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
   const int64_t o = w / CT;
   const int64_t c = (w % CT) * NP + t;
   const bool act = c < a.C;
-  const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(a.tw);
+  // complex64: the twiddles are staged in LDS (measured faster; for
+  // complex128 the extra LDS traffic costs more than the loads it saves)
+  constexpr bool TW_LDS = sizeof(T) == 4;
+  __shared__ cx<T> twl[TW_LDS ? L : 1];
+  const cx<T>* tw = static_cast<const cx<T>*>(a.tw);
+  if constexpr (TW_LDS) {
+    for (int i = tid; i < L; i += NP * TPP) twl[i] = tw[i];
+    tw = twl;  // first read after the first exchange barrier
+  }
   const cx<T>* in = static_cast<const cx<T>*>(a.in);
   cx<T>* out = static_cast<cx<T>*>(a.out);
   const int64_t ib = two_level(o, a.in_lg, a.in_hi, a.in_lo) + c;
