@@ -182,11 +182,11 @@ struct Dft<INV, 5, T> {
 // ---------------------------------------------------------------------------
 // Stage bookkeeping
 // ---------------------------------------------------------------------------
-template <int L, bool INV>
+template <int L, bool INV, int TP = threads_per_pencil(L)>
 struct Stages {
   static constexpr RadixPlan plan = radix_plan(L);
   static constexpr int NS = plan.n;
-  static constexpr int TPP = threads_per_pencil(L);
+  static constexpr int TPP = TP;  // threads per pencil
   static constexpr int radix(int s) { return INV ? plan.r[NS - 1 - s] : plan.r[s]; }
   static constexpr int ns(int s) {  // product of the radices before stage s
     int p = 1;
@@ -221,9 +221,9 @@ struct Regs {
   cx<T> v[C][R];
 };
 
-template <typename T, int L, bool INV>
+template <typename T, int L, bool INV, int TP = threads_per_pencil(L)>
 struct Engine {
-  using St = Stages<L, INV>;
+  using St = Stages<L, INV, TP>;
   static constexpr int NS = St::NS;
   static constexpr int TPP = St::TPP;
 

@@ -249,15 +249,25 @@ __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
 // one after the other, loading the inputs of the next tile before it
 // transforms the current one.  Every spectrum value is read from HBM once
 // per pass.
+//
+// Threads per pencil of the Z pass: the length's default, except complex128
+// at L >= 1024, which keeps one wavefront per pencil (two butterflies per
+// thread): with two wavefronts its registers spill (measured slower).
 template <typename T>
-using ZRegs = typename Engine<T, L, false>::template RegsOf<Stages<L, false>::NS - 1>;
+constexpr int z_tpp() {
+  return (sizeof(T) == 8 && L >= 1024 && TPP > 64) ? 64 : TPP;
+}
+
+template <typename T>
+using ZRegs = typename Engine<T, L, false, z_tpp<T>()>::template RegsOf<Stages<L, false, z_tpp<T>()>::NS - 1>;
 
 template <typename T, int NP, bool PF>
-__global__ void __launch_bounds__(NP * TPP) k_zpass(ZArgs a) {
+__global__ void __launch_bounds__(NP * z_tpp<T>()) k_zpass(ZArgs a) {
   constexpr int n = L / 2;
-  using EF = Engine<T, L, false>;
-  using EI = Engine<T, L, true>;
-  using St = Stages<L, false>;
+  constexpr int ZT = z_tpp<T>();
+  using EF = Engine<T, L, false, ZT>;
+  using EI = Engine<T, L, true, ZT>;
+  using St = Stages<L, false, ZT>;
   using G0 = typename EF::template RegsOf<0>;
   constexpr int SL = St::NS - 1;
   constexpr int RL = St::radix(SL);
@@ -277,19 +287,19 @@ __global__ void __launch_bounds__(NP * TPP) k_zpass(ZArgs a) {
   __shared__ cx<T> twl[L];
   {
     const cx<T>* __restrict__ src = static_cast<const cx<T>*>(a.tw);
-    for (int i = tid; i < L; i += NP * TPP) twl[i] = src[i];
+    for (int i = tid; i < L; i += NP * ZT) twl[i] = src[i];
   }
   const cx<T>* tw = twl;
   cx<T>* buf = static_cast<cx<T>*>(a.buf);
   ZRegs<T> kv;
 #pragma unroll
   for (int i = 0; i < St::cnt(SL); ++i) {
-    const int b = bt + i * TPP;
+    const int b = bt + i * ZT;
 #pragma unroll
     for (int j = 0; j < RL; ++j) {
       const int e = b + j * STRIDE;
       const int m1 = e <= L - e ? e : L - e;
-      const bool ok = act && (St::nbf(SL) % TPP == 0 || b < St::nbf(SL));
+      const bool ok = act && (St::nbf(SL) % ZT == 0 || b < St::nbf(SL));
       kv.v[i][j] = ok ? kh[(m1 * a.kp + m2) * L + k3] : cx<T>{};
     }
   }
@@ -509,7 +519,7 @@ int64_t zpass_blocks(int fprec, int np_sel, int64_t n) {
 
 template <typename T, int NP>
 hipError_t zpass_t(const ZArgs& a, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>((a.n + 1) * ((2 * a.n + NP - 1) / NP))), block(NP * TPP);
+  const dim3 grid(static_cast<unsigned>((a.n + 1) * ((2 * a.n + NP - 1) / NP))), block(NP * z_tpp<T>());
   if (a.prefetch)
     hipLaunchKernelGGL((k_zpass<T, NP, true>), grid, block, 0, st, a);
   else

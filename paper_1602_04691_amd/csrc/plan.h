@@ -53,8 +53,9 @@ constexpr RadixPlan radix_plan(int L) {
 constexpr bool supported_length(int L) { return radix_plan(L).n > 0; }
 
 // Threads per pencil: the smallest butterfly count over the stages, so that
-// no stage leaves threads idle in its widest configuration, capped at one
-// wavefront (longer pencils give each thread several butterflies).
+// no stage leaves threads idle in its widest configuration, capped at two
+// wavefronts (L = 1024: one radix-8 butterfly per thread keeps a complex128
+// thread within 128 registers).
 constexpr int threads_per_pencil(int L) {
   RadixPlan p = radix_plan(L);
   int t = L;
@@ -62,7 +63,7 @@ constexpr int threads_per_pencil(int L) {
     int b = L / p.r[s];
     if (b < t) t = b;
   }
-  return t > 64 ? 64 : t;
+  return t > 128 ? 128 : t;
 }
 
 constexpr int pow2_floor(int x) {
@@ -88,6 +89,7 @@ constexpr int pencils_strided(int L, int elem_bytes) {
   int lo = elem_bytes == 16 ? 8 : 16;
   if (np < lo) np = lo;
   if (np > 64) np = 64;
+  while (np > 1 && np * tpp > 1024) np /= 2;  // at most 1024 threads per workgroup
   return whole_waves(np, tpp);
 }
 

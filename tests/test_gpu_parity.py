@@ -306,7 +306,7 @@ def test_initial_guess_restart():
 # ---------------------------------------------------------------------------
 # full sizes: sampled rows computed one by one by the oracle
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name,nrows", [("n128_k5", 3), ("n256_k5", 2)])
+@pytest.mark.parametrize("name,nrows", [("n128_k5", 3), ("n256_k5", 2), ("n512_k10", 1)])
 def test_large_matvec_sampled_rows(name, nrows):
     case = workloads.named_case(name)
     n, k = case["n"], case["k"]
