@@ -81,7 +81,23 @@ def build(jobs=None, incremental=False, verbose=False):
     if p.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{p.stdout}{p.stderr}")
     os.replace(tmp, LIB)
+    _build_c_smoke()
     return LIB
+
+
+# a C program that uses the C ABI without Python (tests/c/ori_abi_smoke.c)
+C_SMOKE_SRC = os.path.join(ROOT, "tests", "c", "ori_abi_smoke.c")
+C_SMOKE_BIN = os.path.join(ROOT, "tests", "c", "ori_abi_smoke")
+
+
+def _build_c_smoke():
+    if not os.path.exists(C_SMOKE_SRC):
+        return
+    cmd = [HIPCC, "-x", "hip", f"--offload-arch={ARCH}", "-O2", "-I", INCLUDE, C_SMOKE_SRC, "-o", C_SMOKE_BIN,
+           "-L", PKG, "-lori", "-Wl,-rpath,$ORIGIN/../../paper_1602_04691_amd"]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{p.stdout}{p.stderr}")
 
 
 def main(argv=None):

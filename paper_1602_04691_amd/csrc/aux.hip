@@ -108,18 +108,40 @@ __global__ void __launch_bounds__(kRedThreads)
   }
 }
 
-// {bad count, min |S|^2, max |S|^2} over nblk partials -> sc[0]
-__global__ void __launch_bounds__(64) k_finalize_coeff(const double* __restrict__ part, int64_t nblk, ScalarBlock* sc) {
-  if (threadIdx.x != 0) return;
+// {bad count, min |S|^2, max |S|^2} over nblk partials -> sc[0]; one
+// workgroup, strided over the partials, then a fixed-order combine (the
+// count is a sum of small integers, so the order does not matter anyway)
+__global__ void __launch_bounds__(kRedThreads) k_finalize_coeff(const double* __restrict__ part, int64_t nblk,
+                                                                ScalarBlock* sc) {
   double bad = 0.0, mn = INFINITY, mx = 0.0;
-  for (int64_t i = 0; i < nblk; ++i) {
+  for (int64_t i = threadIdx.x; i < nblk; i += kRedThreads) {
     bad += part[4 * i];
     mn = fmin(mn, part[4 * i + 1]);
     mx = fmax(mx, part[4 * i + 2]);
   }
-  sc->flags = bad > 0.0 ? FLAG_BAD_INPUT : 0;
-  sc->s2_min = mn;
-  sc->s2_max = mx;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    bad += __shfl_xor(bad, off, 64);
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+  }
+  __shared__ double sh[(kRedThreads / 64) * 3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[3 * w] = bad;
+    sh[3 * w + 1] = mn;
+    sh[3 * w + 2] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int i = 1; i < kRedThreads / 64; ++i) {
+    sh[0] += sh[3 * i];
+    sh[1] = fmin(sh[1], sh[3 * i + 1]);
+    sh[2] = fmax(sh[2], sh[3 * i + 2]);
+  }
+  sc->flags = sh[0] > 0.0 ? FLAG_BAD_INPUT : 0;
+  sc->s2_min = sh[1];
+  sc->s2_max = sh[2];
 }
 
 // u = w / S, per right-hand side (S shared)
@@ -365,7 +387,7 @@ hipError_t launch_coefficients(const void* h, const double* N, double vol, int64
 }
 
 hipError_t launch_finalize_coeff(const double* partials, int64_t nblk, ScalarBlock* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_coeff, dim3(1), dim3(64), 0, st, partials, nblk, sc);
+  hipLaunchKernelGGL(k_finalize_coeff, dim3(1), dim3(kRedThreads), 0, st, partials, nblk, sc);
   return hipGetLastError();
 }
 
