@@ -62,11 +62,17 @@ def pass_bytes(n, elem):
 
 
 def kernel_sources_sha():
+    """Hash of the library sources with comments and blank space removed (a
+    counter summary stays valid across edits that change no code)."""
+    import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1602_04691_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(d, f), "rb").read())
+            text = open(os.path.join(d, f), encoding="utf-8").read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            h.update(f.encode() + b"\0" + " ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,7 +1,9 @@
 // Host runtime and C ABI (include/ori.h): context, workspaces, the FFT
 // product with the Green's matrix (Section 3), COCG (van der Vorst &
-// Melissen, cited by the paper), mixed-precision refinement, batches of
-// right-hand sides and the adjoint.
+// Melissen, cited by the paper) with HIP-graph replay of its iterations,
+// mixed-precision refinement, batches of right-hand sides, the adjoint, the
+// layout autotuner, and the physics of the solution (charges, field, far
+// field, refraction recipe, and the Table 4 comparison of Section 4).
 #include "ori.h"
 
 #include <hip/hip_runtime.h>
@@ -763,7 +765,7 @@ ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const s
 }
 
 // Forward problem for every right-hand side: w = S u (guess) or 0, solve,
-// u = u0 - G0 S w, true residual.
+// recover u (recover: w / S, or u0 - G0 S w), true residual.
 ori_status forward_solve(ori_ctx c, const ori_solve_opts& o, cxd* u, Outcome* oc) {
   const int64_t P = c->P, R = c->nrhs;
   oc->info.assign(R, ori_solve_info{});

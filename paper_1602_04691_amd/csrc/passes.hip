@@ -246,9 +246,9 @@ __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
 // loads its K values once into registers (the shape of the last forward
 // stage, so element e = b + j L/R of the transform meets K(min(e, L-e), m2,
 // k3) in place) and runs the tiles (k2 = m2 | L - m2) x (right-hand sides)
-// one after the other, loading the inputs of the next tile before it
-// transforms the current one.  Every spectrum value is read from HBM once
-// per pass.
+// one after the other (with PF, the loads of the next tile are issued before
+// the current one is transformed).  Every spectrum value is read from HBM
+// once per pass.
 //
 // Threads per pencil of the Z pass: the length's default, except complex128
 // at L >= 1024, which keeps one wavefront per pencil (two butterflies per
