@@ -253,23 +253,35 @@ def main():
         log(f"[bench] mixed: time-to-{a.tol:g} {t_solvemx * 1e3:.2f} ms vs fp64 {t_solve64 * 1e3:.2f} ms")
 
     # ---- plain operator loop (per-matvec rate) ------------------------------
+    # each product is bracketed by HIP events on the library stream; median
+    # and interquartile range of the device time, and the bytes of the pass
+    # model (480 n^3 B complex128, 280 n^3 B complex64) per median time
     x = u0.clone()
     y = torch.empty_like(x)
-    mv_rates = {}
-    mv_prof = {}
+    mv_rates, mv_prof, mv_stats = {}, {}, {}
+    model_bytes = {"c128": 480 * n ** 3, "c64": 280 * n ** 3}
     for prec, tag in ((ori.ORI_FP64, "c128"), (ori.ORI_MIXED, "c64")):
-        for _ in range(3):
+        for _ in range(5):
             ori.ori_matvec(ctx, x, y, ori.ORI_OP_SYMMETRIC, prec)
-        ori.ori_profile_enable(ctx, True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.matvecs)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(a.matvecs):
+        for e0, e1 in evs:
+            e0.record(stream)
             ori.ori_matvec(ctx, x, y, ori.ORI_OP_SYMMETRIC, prec)
+            e1.record(stream)
         torch.cuda.synchronize()
         mv_rates[tag] = a.matvecs / (time.perf_counter() - t0)
+        dt = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+        q = lambda f: dt[min(len(dt) - 1, int(f * (len(dt) - 1) + 0.5))]
+        mv_stats[tag] = {"median_ms": round(q(0.5), 5), "iqr_ms": round(q(0.75) - q(0.25), 5),
+                         "model_gbs": round(model_bytes[tag] / (q(0.5) * 1e-3) / 1e9, 1)}
+        ori.ori_profile_enable(ctx, True)
+        for _ in range(10):
+            ori.ori_matvec(ctx, x, y, ori.ORI_OP_SYMMETRIC, prec)
         mv_prof[tag] = ori.ori_profile_read(ctx)
         ori.ori_profile_enable(ctx, False)
-    log(f"[bench] operator loop: {mv_rates}")
+    log(f"[bench] operator loop: {mv_rates} {mv_stats}")
 
     # ---- roofline of the dominant kernel of the FP64 step --------------------
     passes = ["f1.c128", "f2.c128", "zpass.c128", "i2.c128", "i1.c128", "update.c128"]
@@ -340,7 +352,7 @@ def main():
                  "iteration_model_gbs": round(it_bytes / (it_ms * 1e-3) / 1e9, 1),
                  "kernel_ms": {kk: round(v[0], 5) for kk, v in prof64.items()}},
         "mixed": mixed,
-        "matvec_only": {"per_s": {kk: round(v, 2) for kk, v in mv_rates.items()},
+        "matvec_only": {"per_s": {kk: round(v, 2) for kk, v in mv_rates.items()}, "device_time": mv_stats,
                         "kernel_ms": {t: {kk: round(v[0], 5) for kk, v in p.items()} for t, p in mv_prof.items()}},
         "kernel_sources_sha": kernel_sources_sha(),
     }

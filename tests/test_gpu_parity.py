@@ -306,16 +306,25 @@ def test_initial_guess_restart():
 # ---------------------------------------------------------------------------
 # full sizes: sampled rows computed one by one by the oracle
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name,nrows", [("n128_k5", 3), ("n256_k5", 2), ("n512_k10", 1)])
-def test_large_matvec_sampled_rows(name, nrows):
+# the pass layout the benchmark times at n = 256 (blk_lg 2 complex128, 3 complex64)
+BENCH_LAYOUT = ((ori.ORI_FP64, dict(blk_lg=2, narrow=0, prefetch=0)),
+                (ori.ORI_MIXED, dict(blk_lg=3, narrow=0, prefetch=0)))
+
+
+@pytest.mark.parametrize("name,nrows,bench_layout", [("n128_k5", 3, False), ("n256_k5", 2, False),
+                                                     ("n256_k5", 2, True), ("n512_k10", 1, False)])
+def test_large_matvec_sampled_rows(name, nrows, bench_layout):
     case = workloads.named_case(name)
     n, k = case["n"], case["k"]
-    say(f"[large matvec] {name}")
+    say(f"[large matvec] {name} bench_layout={bench_layout}")
     rng = np.random.default_rng(9)
     P = n ** 3
     rows = np.concatenate([[0, P - 1], rng.integers(0, P, nrows)])
     x = case["u0"] * (1.0 + 0.25 * np.cos(np.arange(P) * 0.001))
     with context(n, k, case["h"], case["N"], case["u0"]) as ctx:
+        if bench_layout:
+            for prec, lay in BENCH_LAYOUT:
+                ori.ori_set_layout(ctx, prec, **lay)
         xg = gpu(x)
         yg = torch.empty_like(xg)
         ori.ori_matvec(ctx, xg, yg, ori.ORI_OP_SYSTEM, ori.ORI_FP64)
@@ -383,5 +392,34 @@ def test_c4_n512_solve_sampled_true_residual():
     say(f"   sampled residual fp64={np.linalg.norm(r64) / scale:.2e} mixed={abs(rmx[0]):.2e}")
     assert np.linalg.norm(r64) / scale <= 1e-7
     assert abs(rmx[0]) / abs(case["u0"][rows[0]]) <= 1e-7
+    assert i64["rel_res_true"] < 1e-7 and imx["rel_res_true"] < 1e-7
+    assert rel(um, u) <= 1e-6
+
+
+def test_bench_configuration_n256_solve_sampled_true_residual():
+    # the benchmark's step at n = 256 (k = 5, seed 5): load, complex128 and
+    # mixed solves to 1e-8 in the layout it times; sampled rows of eq. 2.19
+    case = workloads.named_case("n256_k5")
+    n, k = case["n"], case["k"]
+    P = n ** 3
+    say("[bench config] n=256")
+    with context(n, k, case["h"], case["N"], case["u0"]) as ctx:
+        for prec, lay in BENCH_LAYOUT:
+            ori.ori_set_layout(ctx, prec, **lay)
+        ug = torch.empty(P, dtype=torch.complex128, device="cuda")
+        _, i64 = ori.ori_solve(ctx, ug, tol=1e-8)
+        u = cpu(ug)
+        _, imx = ori.ori_solve(ctx, ug, tol=1e-8, precision=ori.ORI_MIXED)
+        um = cpu(ug)
+    say(f"   fp64 iters={i64['iterations']} true={i64['rel_res_true']:.2e}; mixed inner={imx['iterations']} "
+        f"true={imx['rel_res_true']:.2e}")
+    rows = np.array([0, 4097, P // 3, P - 1])
+    pts = O.cell_points(n)
+    D = O.coupling(case["h"], case["N"], n)
+    r64 = O.sample_residual_rows(pts, k, D, u, case["u0"], rows)
+    rmx = O.sample_residual_rows(pts, k, D, um, case["u0"], rows)
+    scale = np.linalg.norm(case["u0"][rows])
+    say(f"   sampled residual fp64={np.linalg.norm(r64) / scale:.2e} mixed={np.linalg.norm(rmx) / scale:.2e}")
+    assert np.linalg.norm(r64) / scale <= 1e-7 and np.linalg.norm(rmx) / scale <= 1e-7
     assert i64["rel_res_true"] < 1e-7 and imx["rel_res_true"] < 1e-7
     assert rel(um, u) <= 1e-6
