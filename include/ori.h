@@ -275,6 +275,13 @@ ori_status ori_tune(ori_ctx ctx, int32_t reps, ori_layout* best, double* ms_per_
  * clears the counters and starts recording every launch; 0 stops. */
 ori_status ori_profile_enable(ori_ctx ctx, int32_t enable);
 
+/* Time only the kernel kinds in a comma-separated list of the names that
+ * ori_profile_read reports, without their precision suffix ("zpass",
+ * "f1,f2", ...); NULL or "" times every kind (the default).  Fewer events
+ * cost less inside a timed region.  Unknown names give ORI_ERR_INVALID_ARG
+ * and leave the selection as it was. */
+ori_status ori_profile_kinds(ori_ctx ctx, const char* kinds);
+
 /* Average device duration (ms) and launch count of each kernel kind since
  * ori_profile_enable(ctx, 1).  names[i] (static strings) identify the kinds;
  * up to max entries are written; *count receives the number of kinds. */

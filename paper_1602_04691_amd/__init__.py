@@ -99,6 +99,7 @@ def lib():
             "ori_gradient": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), P, P, ctypes.POINTER(D), P,
                                             ctypes.POINTER(SolveInfo)]),
             "ori_profile_enable": (ctypes.c_int, [P, I32]),
+            "ori_profile_kinds": (ctypes.c_int, [P, ctypes.c_char_p]),
             "ori_profile_read": (ctypes.c_int, [P, I32, ctypes.POINTER(ctypes.c_char_p),
                                                 ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(I32)]),
             "ori_charges": (ctypes.c_int, [P, P, P]),
@@ -404,6 +405,13 @@ def ori_tune(ctx, reps=0):
 
 def ori_profile_enable(ctx, enable=True):
     _check(lib().ori_profile_enable(ctx.handle, int(bool(enable))), ctx)
+
+
+def ori_profile_kinds(ctx, kinds=None):
+    """Time only these kernel kinds (list or comma-separated names, e.g. "zpass"); None: all."""
+    if kinds is not None and not isinstance(kinds, str):
+        kinds = ",".join(kinds)
+    _check(lib().ori_profile_kinds(ctx.handle, None if kinds is None else kinds.encode()), ctx)
 
 
 def ori_profile_read(ctx, max_kinds=64):

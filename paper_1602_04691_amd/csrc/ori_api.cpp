@@ -145,6 +145,7 @@ struct ori_ctx_s {
 
   // profiling
   bool prof = false;
+  uint32_t prof_mask = ~0u;  // bit per kernel kind that is timed
   std::vector<hipEvent_t> ev;  // pairs
   std::vector<ProfPending> pend;
   double prof_ms[2 * K_NKIND] = {};
@@ -272,7 +273,8 @@ ori_status prof_fold(ori_ctx c) {
 template <class F>
 ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
   int evi = -1;
-  if (c->prof) {
+  const bool timed = c->prof && ((c->prof_mask >> kind) & 1u);
+  if (timed) {
     const int cap = 4096;
     if (static_cast<int>(c->pend.size()) >= cap) ORI_TRY(prof_fold(c));
     evi = static_cast<int>(c->pend.size());
@@ -286,7 +288,7 @@ ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
   hipError_t e = f();
   if (e != hipSuccess)
     return set_err(c, ORI_ERR_DEVICE, "kernel %s launch failed: %s", kKindNames[kind], hipGetErrorString(e));
-  if (c->prof) {
+  if (timed) {
     ORI_HIP(c, hipEventRecord(c->ev[2 * evi + 1], c->stream));
     c->pend.push_back(ProfPending{kind * 2 + (fprec == PREC_F32 ? 1 : 0), evi});
   }
@@ -1396,6 +1398,29 @@ ori_status ori_profile_enable(ori_ctx c, int32_t enable) {
     std::fill(std::begin(c->prof_n), std::end(c->prof_n), 0);
   }
   c->prof = enable != 0;
+  return ORI_OK;
+}
+
+ori_status ori_profile_kinds(ori_ctx c, const char* kinds) {
+  ORI_TRY(guard(c));
+  if (!kinds || !*kinds) {
+    c->prof_mask = ~0u;
+    return ORI_OK;
+  }
+  uint32_t mask = 0;
+  std::string list(kinds);
+  size_t pos = 0;
+  while (pos <= list.size()) {
+    const size_t end = std::min(list.find(',', pos), list.size());
+    const std::string name = list.substr(pos, end - pos);
+    int found = -1;
+    for (int k = 0; k < K_NKIND; ++k)
+      if (name == kKindNames[k]) found = k;
+    if (found < 0) return set_err(c, ORI_ERR_INVALID_ARG, "unknown kernel kind '%s'", name.c_str());
+    mask |= 1u << found;
+    pos = end + 1;
+  }
+  c->prof_mask = mask;
   return ORI_OK;
 }
 

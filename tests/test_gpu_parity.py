@@ -423,3 +423,25 @@ def test_bench_configuration_n256_solve_sampled_true_residual():
     assert np.linalg.norm(r64) / scale <= 1e-7 and np.linalg.norm(rmx) / scale <= 1e-7
     assert i64["rel_res_true"] < 1e-7 and imx["rel_res_true"] < 1e-7
     assert rel(um, u) <= 1e-6
+
+
+def test_profile_kinds_selects_timed_kernels():
+    n = 8
+    case = workloads.make_case(n, 3.0, seed=71)
+    with context(n, 3.0, case["h"], case["N"], case["u0"]) as ctx:
+        ug = torch.empty(n ** 3, dtype=torch.complex128, device="cuda")
+        ori.ori_profile_kinds(ctx, ["zpass", "f2"])
+        ori.ori_profile_enable(ctx, True)
+        ori.ori_solve(ctx, ug, tol=1e-10)
+        prof = ori.ori_profile_read(ctx)
+        ori.ori_profile_enable(ctx, False)
+        assert set(prof) == {"zpass.c128", "f2.c128"}
+        assert prof["zpass.c128"][1] == prof["f2.c128"][1] > 0
+        with pytest.raises(ori.OriError) as e:
+            ori.ori_profile_kinds(ctx, "nonsense")
+        assert e.value.status == ori.ORI_ERR_INVALID_ARG
+        ori.ori_profile_kinds(ctx, None)
+        ori.ori_profile_enable(ctx, True)
+        ori.ori_solve(ctx, ug, tol=1e-10)
+        assert {"f1.c128", "i1.c128", "update.c128", "finalize"} <= set(ori.ori_profile_read(ctx))
+        ori.ori_profile_enable(ctx, False)
