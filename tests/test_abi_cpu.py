@@ -119,3 +119,14 @@ def test_no_oracle_in_product_path():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+@pytest.mark.parametrize("nrhs", [0, -1, 1 << 20])
+def test_bad_batch_size_rejected_on_host(nrhs):
+    lib = ori.lib()
+    g = ori._grid(8)
+    out = ctypes.c_int64()
+    assert lib.ori_workspace_bytes(ctypes.byref(g), nrhs, 3, ctypes.byref(out)) == ori.ORI_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    assert lib.ori_create(ctypes.byref(g), nrhs, 3, 0, None, ctypes.byref(h)) == ori.ORI_ERR_INVALID_ARG
+    assert h.value is None

@@ -445,3 +445,31 @@ def test_profile_kinds_selects_timed_kernels():
         ori.ori_solve(ctx, ug, tol=1e-10)
         assert {"f1.c128", "i1.c128", "update.c128", "finalize"} <= set(ori.ori_profile_read(ctx))
         ori.ori_profile_enable(ctx, False)
+
+
+def test_degenerate_inputs():
+    # no particles (h = 0 or N = 0): u = u0 exactly, no iteration; zero
+    # incident field: u = 0; k -> 0 (the static kernel 1/(4 pi r)): finite and
+    # equal to the dense solution
+    n = 6
+    P = n ** 3
+    case = workloads.make_case(n, 2.0, seed=81)
+    for h, N in ((np.zeros(P, complex), None), (case["h"], np.zeros(P))):
+        with context(n, 2.0, h, N, case["u0"]) as ctx:
+            ug = torch.empty(P, dtype=torch.complex128, device="cuda")
+            st, info = ori.ori_solve(ctx, ug, raise_on_error=False)
+            assert st == ori.ORI_OK and info["iterations"] == 0
+            assert np.array_equal(cpu(ug), case["u0"])
+    with context(n, 2.0, case["h"], None, np.zeros(P, complex)) as ctx:
+        ug = torch.empty(P, dtype=torch.complex128, device="cuda")
+        st, info = ori.ori_solve(ctx, ug, raise_on_error=False)
+        assert st == ori.ORI_OK and np.all(cpu(ug) == 0)
+    k = 1e-9
+    pts = O.cell_points(n)
+    D = O.coupling(case["h"], case["N"], n)
+    u_ref = O.solve_direct(O.system_matrix(pts, k, D), case["u0"])
+    with context(n, k, case["h"], case["N"], case["u0"]) as ctx:
+        ug = torch.empty(P, dtype=torch.complex128, device="cuda")
+        ori.ori_solve(ctx, ug, tol=1e-12)
+        u = cpu(ug)
+    assert np.all(np.isfinite(u)) and rel(u, u_ref) <= 1e-10
