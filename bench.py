@@ -127,10 +127,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle rows for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--layout", default="2,0,0/3,0,0",
-                    help="pass layout LG,NP,PF[/LG,NP,PF] (complex128 / complex64 passes); the default is what "
-                         "ori_tune picks at n = 256 on MI355X; 'auto' tunes before timing, 'default' keeps the "
-                         "library's")
+    ap.add_argument("--layout", default="2,0,0,0/3,0,0,1",
+                    help="pass layout LG,NP,PF,ZNP[/LG,NP,PF,ZNP] (complex128 / complex64 passes: i1 row block, "
+                         "narrow strided tiles, Z prefetch, narrow Z tiles); the default is what ori_tune picks "
+                         "at n = 256 on MI355X; 'auto' tunes before timing, 'default' keeps the library's")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain 1-to-1 copy of this many MiB (counter calibration)")
     a = ap.parse_args()
@@ -172,14 +172,16 @@ def main():
     elif a.layout != "default":
         parts = a.layout.split("/")
         for prec, spec in zip((ori.ORI_FP64, ori.ORI_MIXED), parts if len(parts) == 2 else parts * 2):
-            lg, nar, pf = (int(v) for v in spec.split(","))
-            ori.ori_set_layout(ctx, prec, blk_lg=lg, narrow=nar, prefetch=pf)
+            vals = [int(v) for v in spec.split(",")]
+            if len(vals) not in (3, 4):
+                sys.exit(f"--layout: expected LG,NP,PF[,ZNP], got {spec!r}")
+            ori.ori_set_layout(ctx, prec, *vals)
 
     def lay_str(prec):
         d = ori.ori_get_layout(ctx, prec)
-        return f"{d['blk_lg']},{d['narrow']},{d['prefetch']}"
+        return f"{d['blk_lg']},{d['narrow']},{d['prefetch']},{d['znarrow']}"
     layout = {"fp64": lay_str(ori.ORI_FP64), "c64": lay_str(ori.ORI_MIXED)}
-    log(f"[bench] layout (blk_lg,narrow,prefetch): {layout}")
+    log(f"[bench] layout (blk_lg,narrow,prefetch,znarrow): {layout}")
 
     def step(precision):
         ori.ori_load(ctx, k, h, N, u0)

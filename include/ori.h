@@ -248,8 +248,10 @@ ori_status ori_interpolation_difference(ori_ctx ctx, const void* y, const void* 
 typedef struct {
   int32_t blk_lg;   /* log2 of the row block (along i1) of the work array between
                        the strided and Z passes, 0..6, n divisible by 2^blk_lg  */
-  int32_t narrow;   /* 1: narrow pencil tiles in the strided and Z passes      */
+  int32_t narrow;   /* 1: narrow pencil tiles (half as many pencils per
+                       workgroup) in the two strided passes                     */
   int32_t prefetch; /* 1: the Z pass loads its next tile while it transforms one */
+  int32_t znarrow;  /* 1: narrow pencil tiles in the Z pass                      */
 } ori_layout;
 
 /* Layout in use for precision ORI_FP64 (complex128 FFTs) or ORI_MIXED

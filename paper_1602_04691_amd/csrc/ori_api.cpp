@@ -71,9 +71,12 @@ thread_local std::string g_last_error = "no error";
 // Layout knobs of the FFT passes (performance only)
 struct Knobs {
   int blk_lg = 4;  // log2 of the i1 block of the B layout (n divisible by 2^blk_lg)
-  int np_sel = 0;  // strided / Z tile width: 0 wide, 1 narrow
+  int np_sel = 0;  // strided tile width: 0 wide, 1 narrow
   int zpf = 0;     // Z pass: prefetch the next tile
-  bool operator==(const Knobs& o) const { return blk_lg == o.blk_lg && np_sel == o.np_sel && zpf == o.zpf; }
+  int z_np = 0;    // Z tile width: 0 wide, 1 narrow
+  bool operator==(const Knobs& o) const {
+    return blk_lg == o.blk_lg && np_sel == o.np_sel && zpf == o.zpf && z_np == o.z_np;
+  }
 };
 
 // Tuned layouts, process-wide, by (device, n, nrhs): a context created on a
@@ -142,6 +145,8 @@ struct ori_ctx_s {
     const void* key[5] = {};
   } graphs[2];
   hipStream_t cap_stream = nullptr;  // capture stream (the context stream may be the null stream)
+  hipError_t launch_err = hipSuccess;  // HIP error of the last failed kernel launch
+  int64_t eager_fallbacks = 0;       // iteration blocks run eagerly after an invalidated capture
 
   // profiling
   bool prof = false;
@@ -286,8 +291,10 @@ ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
     ORI_HIP(c, hipEventRecord(c->ev[2 * evi], c->stream));
   }
   hipError_t e = f();
-  if (e != hipSuccess)
+  if (e != hipSuccess) {
+    c->launch_err = e;
     return set_err(c, ORI_ERR_DEVICE, "kernel %s launch failed: %s", kKindNames[kind], hipGetErrorString(e));
+  }
   if (timed) {
     ORI_HIP(c, hipEventRecord(c->ev[2 * evi + 1], c->stream));
     c->pend.push_back(ProfPending{kind * 2 + (fprec == PREC_F32 ? 1 : 0), evi});
@@ -342,7 +349,7 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   StridedArgs f2{A, B, R * n, L, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, ns, tw};
   ORI_TRY(launch(c, K_F2, fprec, [&] { return c->K->strided(fprec, f2, c->stream); }));
 
-  ZArgs z{B, n, lg, ns, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, 0, kh, n + 1, tw};
+  ZArgs z{B, n, lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, 0, kh, n + 1, tw};
   ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, z, c->stream); }));
 
   StridedArgs i2{B, A, R * n, L, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};
@@ -457,10 +464,21 @@ ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* 
   return finalize(c, rblocks(c), FIN_RHO);
 }
 
+bool capture_error(hipError_t e) {
+  return e == hipErrorStreamCaptureInvalidated || e == hipErrorStreamCaptureUnsupported ||
+         e == hipErrorStreamCaptureImplicit;
+}
+
 // The graph of `iters` non-first iterations on (x, r, p, q, S), captured on
-// the context's capture stream and cached per precision.
+// the context's capture stream and cached per precision.  The capture makes
+// no call that is unsafe during capture, so it uses the relaxed mode:
+// another thread's allocations or frees (other contexts, the caller's
+// allocator) must not end it.  If the runtime still invalidates it, nothing
+// captured has run, so *out is left NULL, the context stays usable and the
+// caller runs the block eagerly (same kernels, same results).
 ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int iters,
                            hipGraphExec_t* out) {
+  *out = nullptr;
   auto& g = c->graphs[prec == PREC_F32 ? 1 : 0];
   const void* key[5] = {x, r, p, q, S};
   if (g.exec && g.iters == iters && std::equal(key, key + 5, g.key)) {
@@ -475,16 +493,27 @@ ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void*
   hipStream_t own = c->stream;
   c->stream = c->cap_stream;
   hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
   ori_status st = e == hipSuccess ? ORI_OK : set_err(c, ORI_ERR_DEVICE, "hipStreamBeginCapture: %s",
                                                      hipGetErrorString(e));
+  bool invalidated = false;
   if (st == ORI_OK) {
+    c->launch_err = hipSuccess;
     for (int it = 0; it < iters && st == ORI_OK; ++it) st = cocg_iteration(c, prec, x, r, p, q, S, false);
     e = hipStreamEndCapture(c->cap_stream, &graph);
-    if (st == ORI_OK && e != hipSuccess)
+    invalidated = (st != ORI_OK && capture_error(c->launch_err)) || (st == ORI_OK && capture_error(e));
+    if (st == ORI_OK && e != hipSuccess && !invalidated)
       st = set_err(c, ORI_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
   }
   c->stream = own;
+  if (invalidated) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();  // the capture error is handled here
+    c->poisoned = false;
+    c->err = "no error";
+    ++c->eager_fallbacks;
+    return ORI_OK;
+  }
   if (st == ORI_OK) {
     e = hipGraphInstantiateWithFlags(&g.exec, graph, 0);
     if (e != hipSuccess) {
@@ -528,9 +557,9 @@ ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* 
     // the first block runs eagerly (it holds the first iteration); later
     // full blocks replay the captured graph
     const int blk = std::min(check_every, max_iter - it);
-    if (use_graph && it > 0 && blk == check_every) {
-      hipGraphExec_t exec = nullptr;
-      ORI_TRY(iteration_graph(c, prec, x, r, p, q, S, blk, &exec));
+    hipGraphExec_t exec = nullptr;
+    if (use_graph && it > 0 && blk == check_every) ORI_TRY(iteration_graph(c, prec, x, r, p, q, S, blk, &exec));
+    if (exec) {
       ORI_HIP(c, hipGraphLaunch(exec, c->stream));
     } else {
       for (int j = 0; j < blk; ++j) ORI_TRY(cocg_iteration(c, prec, x, r, p, q, S, it + j == 0));
@@ -583,18 +612,22 @@ ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel)
   return ORI_OK;
 }
 
-// Layout knobs: the i1 blocking of the B work array (ZArgs), the tile width
-// of the strided and Z passes and the Z-pass prefetch.  Start from the
-// measured defaults, or from the tuned layout of this (device, n, nrhs);
-// ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF override both for tuning runs.
+// Layout knobs: the i1 blocking of the B work array (ZArgs), the tile widths
+// of the strided and of the Z passes and the Z-pass prefetch.  Start from the
+// measured defaults (the complex64 Z pass runs faster on narrow tiles: twice
+// as many workgroups per CU, where the wide one fits a single workgroup of
+// 16 wavefronts), or from the tuned layout of this (device, n, nrhs);
+// ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF / ORI_TUNE_ZNP override both
+// for tuning runs.
 bool valid_knobs(int64_t n, const Knobs& k) {
   return k.blk_lg >= 0 && k.blk_lg <= 6 && n % (int64_t{1} << k.blk_lg) == 0 && (k.np_sel == 0 || k.np_sel == 1) &&
-         (k.zpf == 0 || k.zpf == 1);
+         (k.zpf == 0 || k.zpf == 1) && (k.z_np == 0 || k.z_np == 1);
 }
 
 void choose_layout(ori_ctx c) {
   for (int f = 0; f < 2; ++f) {
     Knobs k;
+    k.z_np = f == 1 ? 1 : 0;
     while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
     c->knob[f] = k;
   }
@@ -610,6 +643,7 @@ void choose_layout(ori_ctx c) {
     if (const char* e = std::getenv("ORI_TUNE_BLK_LG")) k.blk_lg = std::atoi(e);
     if (const char* e = std::getenv("ORI_TUNE_NP")) k.np_sel = std::atoi(e) ? 1 : 0;
     if (const char* e = std::getenv("ORI_TUNE_ZPF")) k.zpf = std::atoi(e) ? 1 : 0;
+    if (const char* e = std::getenv("ORI_TUNE_ZNP")) k.z_np = std::atoi(e) ? 1 : 0;
     if (k.blk_lg < 0) k.blk_lg = 0;
     if (k.blk_lg > 6) k.blk_lg = 6;
     while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
@@ -1198,9 +1232,7 @@ ori_status ori_get_layout(ori_ctx c, int32_t precision, ori_layout* out) {
   if (!out) return set_err(c, ORI_ERR_INVALID_ARG, "out is NULL");
   if (precision != ORI_FP64 && precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
   const Knobs& k = c->knob[precision == ORI_MIXED ? 1 : 0];
-  out->blk_lg = k.blk_lg;
-  out->narrow = k.np_sel;
-  out->prefetch = k.zpf;
+  *out = ori_layout{k.blk_lg, k.np_sel, k.zpf, k.z_np};
   return ORI_OK;
 }
 
@@ -1208,10 +1240,11 @@ ori_status ori_set_layout(ori_ctx c, int32_t precision, const ori_layout* in) {
   ORI_TRY(guard(c));
   if (!in) return set_err(c, ORI_ERR_INVALID_ARG, "layout is NULL");
   if (precision != ORI_FP64 && precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
-  const Knobs k{in->blk_lg, in->narrow, in->prefetch};
+  const Knobs k{in->blk_lg, in->narrow, in->prefetch, in->znarrow};
   if (!valid_knobs(c->n, k))
-    return set_err(c, ORI_ERR_INVALID_ARG, "layout {blk_lg %d, narrow %d, prefetch %d} is not valid for n = %lld",
-                   in->blk_lg, in->narrow, in->prefetch, (long long)c->n);
+    return set_err(c, ORI_ERR_INVALID_ARG,
+                   "layout {blk_lg %d, narrow %d, prefetch %d, znarrow %d} is not valid for n = %lld", in->blk_lg,
+                   in->narrow, in->prefetch, in->znarrow, (long long)c->n);
   ORI_HIP(c, hipStreamSynchronize(c->stream));
   ORI_TRY(drop_graphs(c));
   c->knob[precision == ORI_MIXED ? 1 : 0] = k;
@@ -1250,39 +1283,36 @@ ori_status ori_tune(ori_ctx c, int32_t reps, ori_layout* best, double* ms_per_pr
     double win_ms = INFINITY;
     for (int lg = 0; lg <= 6 && st == ORI_OK; ++lg)
       for (int np = 0; np <= 1 && st == ORI_OK; ++np)
-        for (int pf = 0; pf <= 1 && st == ORI_OK; ++pf) {
-          const Knobs k{lg, np, pf};
-          if (!valid_knobs(c->n, k)) continue;
-          c->knob[f] = k;
-          auto product = [&] {
-            return matvec(c, fp, fp, plain_f1(x, S), epi(y, x, 1.0, nullptr, 0.0, S, 1.0, nullptr, 0), nullptr);
-          };
-          st = product();  // warm-up
-          if (st == ORI_OK && hipEventRecord(e0, c->stream) != hipSuccess)
-            st = set_err(c, ORI_ERR_DEVICE, "hipEventRecord failed");
-          for (int i = 0; i < reps && st == ORI_OK; ++i) st = product();
-          if (st == ORI_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-            st = set_err(c, ORI_ERR_DEVICE, "timing events failed");
-          float ms = 0.f;
-          if (st == ORI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-            st = set_err(c, ORI_ERR_DEVICE, "hipEventElapsedTime failed");
-          if (st == ORI_OK && ms / reps < win_ms) {
-            win_ms = ms / reps;
-            win = k;
+        for (int pf = 0; pf <= 1 && st == ORI_OK; ++pf)
+          for (int znp = 0; znp <= 1 && st == ORI_OK; ++znp) {
+            const Knobs k{lg, np, pf, znp};
+            if (!valid_knobs(c->n, k)) continue;
+            c->knob[f] = k;
+            auto product = [&] {
+              return matvec(c, fp, fp, plain_f1(x, S), epi(y, x, 1.0, nullptr, 0.0, S, 1.0, nullptr, 0), nullptr);
+            };
+            st = product();  // warm-up
+            if (st == ORI_OK && hipEventRecord(e0, c->stream) != hipSuccess)
+              st = set_err(c, ORI_ERR_DEVICE, "hipEventRecord failed");
+            for (int i = 0; i < reps && st == ORI_OK; ++i) st = product();
+            if (st == ORI_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+              st = set_err(c, ORI_ERR_DEVICE, "timing events failed");
+            float ms = 0.f;
+            if (st == ORI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+              st = set_err(c, ORI_ERR_DEVICE, "hipEventElapsedTime failed");
+            if (st == ORI_OK && ms / reps < win_ms) {
+              win_ms = ms / reps;
+              win = k;
+            }
           }
-        }
     c->knob[f] = st == ORI_OK ? win : start;
     found.k[f] = win;
     found.have[f] = st == ORI_OK;
-    if (best) {
-      best[f].blk_lg = win.blk_lg;
-      best[f].narrow = win.np_sel;
-      best[f].prefetch = win.zpf;
-    }
+    if (best) best[f] = ori_layout{win.blk_lg, win.np_sel, win.zpf, win.z_np};
     if (ms_per_product) ms_per_product[f] = st == ORI_OK ? win_ms : -1.0;
   }
   if (!mixed) {
-    if (best) best[1] = ori_layout{c->knob[1].blk_lg, c->knob[1].np_sel, c->knob[1].zpf};
+    if (best) best[1] = ori_layout{c->knob[1].blk_lg, c->knob[1].np_sel, c->knob[1].zpf, c->knob[1].z_np};
     if (ms_per_product) ms_per_product[1] = -1.0;
   }
   (void)hipEventDestroy(e0);

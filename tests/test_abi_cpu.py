@@ -130,3 +130,40 @@ def test_bad_batch_size_rejected_on_host(nrhs):
     h = ctypes.c_void_p()
     assert lib.ori_create(ctypes.byref(g), nrhs, 3, 0, None, ctypes.byref(h)) == ori.ORI_ERR_INVALID_ARG
     assert h.value is None
+
+
+_CTYPES = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
+
+
+def _header_structs():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(ori_[a-z_]+)\s*;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            m = re.fullmatch(r"(\w+)\s+(\w+)(?:\[(\d+)\])?", decl)
+            assert m, (name, decl)
+            ty = _CTYPES[m.group(1)]
+            fields.append((m.group(2), ty * int(m.group(3)) if m.group(3) else ty))
+        out[name] = fields
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("ori_grid", "Grid"), ("ori_solve_opts", "SolveOpts"),
+                                          ("ori_solve_info", "SolveInfo"), ("ori_layout", "Layout")])
+def test_binding_structs_match_header(cname, pyname):
+    # the ctypes mirrors have the header's fields, in order, at the same offsets
+    fields = _header_structs()[cname]
+
+    class FromHeader(ctypes.Structure):
+        _fields_ = fields
+
+    mirror = getattr(ori, pyname)
+    assert [f for f, _ in mirror._fields_] == [f for f, _ in fields]
+    assert ctypes.sizeof(mirror) == ctypes.sizeof(FromHeader)
+    for f, _ in fields:
+        assert getattr(mirror, f).offset == getattr(FromHeader, f).offset, f
+        assert getattr(mirror, f).size == getattr(FromHeader, f).size, f

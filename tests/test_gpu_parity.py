@@ -306,9 +306,10 @@ def test_initial_guess_restart():
 # ---------------------------------------------------------------------------
 # full sizes: sampled rows computed one by one by the oracle
 # ---------------------------------------------------------------------------
-# the pass layout the benchmark times at n = 256 (blk_lg 2 complex128, 3 complex64)
-BENCH_LAYOUT = ((ori.ORI_FP64, dict(blk_lg=2, narrow=0, prefetch=0)),
-                (ori.ORI_MIXED, dict(blk_lg=3, narrow=0, prefetch=0)))
+# the pass layout the benchmark times at n = 256 (blk_lg 2 complex128, 3 complex64
+# with narrow Z tiles)
+BENCH_LAYOUT = ((ori.ORI_FP64, dict(blk_lg=2, narrow=0, prefetch=0, znarrow=0)),
+                (ori.ORI_MIXED, dict(blk_lg=3, narrow=0, prefetch=0, znarrow=1)))
 
 
 @pytest.mark.parametrize("name,nrows,bench_layout", [("n128_k5", 3, False), ("n256_k5", 2, False),

@@ -30,9 +30,9 @@ def gpu(a):
 
 
 def layouts(n):
-    for lg, nar, pf in itertools.product(range(7), (0, 1), (0, 1)):
+    for lg, nar, pf, znar in itertools.product(range(7), (0, 1), (0, 1), (0, 1)):
         if n % (1 << lg) == 0:
-            yield dict(blk_lg=lg, narrow=nar, prefetch=pf)
+            yield dict(blk_lg=lg, narrow=nar, prefetch=pf, znarrow=znar)
 
 
 @pytest.mark.parametrize("n,R", [(24, 1), (16, 3)])
@@ -52,13 +52,14 @@ def test_every_layout_same_product(n, R):
                 y = torch.empty_like(x)
                 ori.ori_matvec(ctx, x, y, op=ori.ORI_OP_SYMMETRIC, precision=prec)
                 y = y.cpu().numpy()
+                tiles = (lay["narrow"], lay["znarrow"])
                 if ref is None:
-                    ref = {0: y}
-                if lay["narrow"] not in ref:
-                    ref[lay["narrow"]] = y
+                    ref = {(0, 0): y}
+                if tiles not in ref:
+                    ref[tiles] = y
                 # blocking and prefetch: bitwise; narrow vs wide tiles: rounding
-                assert np.array_equal(y, ref[lay["narrow"]]), lay
-                d = np.linalg.norm(y - ref[0]) / np.linalg.norm(ref[0])
+                assert np.array_equal(y, ref[tiles]), lay
+                d = np.linalg.norm(y - ref[(0, 0)]) / np.linalg.norm(ref[(0, 0)])
                 assert d <= (1e-14 if prec == ori.ORI_FP64 else 1e-6), (lay, d)
 
 
@@ -67,12 +68,13 @@ def test_invalid_layout_rejected():
     case = workloads.make_case(n, 2.0, seed=1)
     with ori.ori_setup(n, 2.0, gpu(case["h"]), gpu(case["N"]), gpu(case["u0"])) as ctx:
         before = ori.ori_get_layout(ctx)
-        for bad in (dict(blk_lg=3), dict(blk_lg=-1), dict(blk_lg=7), dict(narrow=2), dict(prefetch=-1)):
-            lay = ori.Layout(bad.get("blk_lg", 0), bad.get("narrow", 0), bad.get("prefetch", 0))
+        for bad in (dict(blk_lg=3), dict(blk_lg=-1), dict(blk_lg=7), dict(narrow=2), dict(prefetch=-1),
+                    dict(znarrow=2)):
+            lay = ori.Layout(bad.get("blk_lg", 0), bad.get("narrow", 0), bad.get("prefetch", 0), bad.get("znarrow", 0))
             st = ori.lib().ori_set_layout(ctx.handle, ori.ORI_FP64, ctypes.byref(lay))
             assert st == ori.ORI_ERR_INVALID_ARG, bad
             assert ori.ori_get_layout(ctx) == before
-        assert ori.lib().ori_set_layout(ctx.handle, 7, ctypes.byref(ori.Layout(0, 0, 0))) == ori.ORI_ERR_INVALID_ARG
+        assert ori.lib().ori_set_layout(ctx.handle, 7, ctypes.byref(ori.Layout(0, 0, 0, 0))) == ori.ORI_ERR_INVALID_ARG
 
 
 def test_tune_picks_layout_and_records_it():
