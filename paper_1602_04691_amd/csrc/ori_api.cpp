@@ -614,11 +614,11 @@ ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel)
 
 // Layout knobs: the i1 blocking of the B work array (ZArgs), the tile widths
 // of the strided and of the Z passes and the Z-pass prefetch.  Start from the
-// measured defaults (the complex64 Z pass runs faster on narrow tiles: twice
-// as many workgroups per CU, where the wide one fits a single workgroup of
-// 16 wavefronts), or from the tuned layout of this (device, n, nrhs);
+// measured defaults, or from the tuned layout of this (device, n, nrhs);
 // ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF / ORI_TUNE_ZNP override both
-// for tuning runs.
+// for tuning runs.  Narrow Z tiles by default where they measured faster:
+// complex64 up to L = 512 (its wide workgroup of 16 wavefronts fits once per
+// CU, the narrow one twice) and complex128 from L = 1024 on.
 bool valid_knobs(int64_t n, const Knobs& k) {
   return k.blk_lg >= 0 && k.blk_lg <= 6 && n % (int64_t{1} << k.blk_lg) == 0 && (k.np_sel == 0 || k.np_sel == 1) &&
          (k.zpf == 0 || k.zpf == 1) && (k.z_np == 0 || k.z_np == 1);
@@ -627,7 +627,7 @@ bool valid_knobs(int64_t n, const Knobs& k) {
 void choose_layout(ori_ctx c) {
   for (int f = 0; f < 2; ++f) {
     Knobs k;
-    k.z_np = f == 1 ? 1 : 0;
+    k.z_np = (f == 1 && c->L <= 512) || (f == 0 && c->L >= 1024) ? 1 : 0;
     while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
     c->knob[f] = k;
   }
