@@ -258,11 +258,21 @@ constexpr int z_tpp() {
   return (sizeof(T) == 8 && L >= 1024 && TPP > 64) ? 64 : TPP;
 }
 
+// Waves per SIMD that the register allocation must allow.  At L = 512 the
+// complex64 pass on 512-thread workgroups (36 KB of LDS) fits three
+// workgroups per CU once it stays within 80 VGPRs (it needs 81
+// unconstrained, which allows two): 0.366 vs 0.441 ms at n = 256.  At other
+// lengths the same bound spills.
+template <typename T, int NP, bool PF>
+constexpr int z_min_waves() {
+  return (L == 512 && sizeof(T) == 4 && !PF && NP * z_tpp<T>() == 512) ? 6 : 1;
+}
+
 template <typename T>
 using ZRegs = typename Engine<T, L, false, z_tpp<T>()>::template RegsOf<Stages<L, false, z_tpp<T>()>::NS - 1>;
 
 template <typename T, int NP, bool PF>
-__global__ void __launch_bounds__(NP * z_tpp<T>()) k_zpass(ZArgs a) {
+__global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k_zpass(ZArgs a) {
   constexpr int n = L / 2;
   constexpr int ZT = z_tpp<T>();
   using EF = Engine<T, L, false, ZT>;
