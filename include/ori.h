@@ -20,7 +20,8 @@
  * Conventions (all entry points):
  *  - Flat index p = (i1 * n + i2) * n + i3, i3 fastest.  P = n^3.
  *  - Complex arrays are interleaved {re, im} doubles (C99 double complex,
- *    torch.complex128), 16-byte aligned.
+ *    torch.complex128), 16-byte aligned; real arrays (N, points,
+ *    directions) are doubles, 8-byte aligned.
  *  - Every array argument is DEVICE memory of the current HIP device
  *    (hipMalloc / torch CUDA tensors).  Host pointers are rejected with
  *    ORI_ERR_INVALID_ARG before any kernel runs.  Structs (ori_grid,

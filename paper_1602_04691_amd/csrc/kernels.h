@@ -107,9 +107,10 @@ struct StridedArgs {
 //   rhs * batch_stride + (i1 >> e_lg) * e_hi + (i1 & (2^e_lg - 1)) * e_lo + k2 * o_stride + k3
 // i.e. i1 is split into blocks of 2^e_lg rows stored next to each other, so
 // that one pencil of the Z pass spans n / 2^e_lg far-apart regions instead
-// of n.  The spectrum is even along every axis; it is stored for
-// m1, m2 in [0..n] and all k3: khat[(m1 * kp + m2) * L + k3], kp = n + 1, so
-// a tile of consecutive k3 is one aligned run.
+// of n.  The spectrum is even along every axis and stored as its octant:
+// khat[(m1 * kp + m2) * kp + m3], kp = n + 1, m = min(k, L - k) per axis, so
+// a tile of consecutive k3 reads one run, ascending below n and descending
+// above.
 struct ZArgs {
   void* buf;
   int64_t n;
@@ -117,7 +118,7 @@ struct ZArgs {
   int64_t e_hi, e_lo, o_stride;
   int64_t nrhs, batch_stride;
   int32_t prefetch, pad2;  // 1: load the next tile while transforming the current one
-  const void* khat;     // spectrum (T), [n+1][n+1][L]
+  const void* khat;     // spectrum (T), octant [n+1][n+1][n+1]
   int64_t kp;
   const void* tw;
 };
@@ -125,12 +126,12 @@ struct ZArgs {
 // Kernel spectrum: passes 1 and 2 in place on an octant scratch
 // kh[(m1 kp + m2) kp + m3], kp = n + 1 (the Green's table of the padded grid
 // is even along every axis, so are its transforms, and [0..n] per axis
-// determines everything); pass 3 writes the Z-pass layout kout (ZArgs):
+// determines everything); pass 3 writes the scaled octant kout (ZArgs):
 //   pass 1: generate the table along m3 for (m1, m2) in [0..n]^2, forward DFT,
 //           keep k3 in [0..n]
 //   pass 2: along m2 for (m1, k3): read [0..n], mirror, DFT, keep [0..n]
-//   pass 3: along m1 for (k2, k3): same, times `scale`, stored at k3 and
-//           L - k3 of kout (complex128) and koutf (complex64, or NULL).
+//   pass 3: along m1 for (k2, k3): same, times `scale`, stored in kout
+//           (complex128) and koutf (complex64, or NULL).
 struct SpectrumArgs {
   void* kh;
   void* kout;

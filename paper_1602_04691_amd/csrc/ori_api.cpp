@@ -146,7 +146,6 @@ struct ori_ctx_s {
   } graphs[2];
   hipStream_t cap_stream = nullptr;  // capture stream (the context stream may be the null stream)
   hipError_t launch_err = hipSuccess;  // HIP error of the last failed kernel launch
-  int64_t eager_fallbacks = 0;       // iteration blocks run eagerly after an invalidated capture
 
   // profiling
   bool prof = false;
@@ -221,8 +220,8 @@ Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   l.arena = align_up(std::max<int64_t>(nrhs * 6 * P, kp * kp * kp) * 16);
   l.vec_d = align_up(P * 16);
   l.vec_f = align_up(P * 8);
-  l.kh = align_up(kp * kp * 2 * n * 16);  // [n+1][n+1][L]
-  l.khf = mixed ? align_up(kp * kp * 2 * n * 8) : 0;
+  l.kh = align_up(kp * kp * kp * 16);  // octant [n+1][n+1][n+1]
+  l.khf = mixed ? align_up(kp * kp * kp * 8) : 0;
   l.npart = nrhs * std::max<int64_t>(red_blocks(P), n * n);
   const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
   const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
@@ -231,7 +230,9 @@ Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   return l;
 }
 
-ori_status check_dev_ptr(ori_ctx c, const void* ptr, int64_t bytes, const char* what) {
+// align: the element alignment the kernels need (16 for complex128 arrays,
+// 8 for real ones)
+ori_status check_dev_ptr(ori_ctx c, const void* ptr, int64_t bytes, const char* what, int align = 16) {
   if (!ptr) return set_err(c, ORI_ERR_INVALID_ARG, "%s is NULL", what);
   hipPointerAttribute_t at{};
   if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
@@ -254,8 +255,8 @@ ori_status check_dev_ptr(ori_ctx c, const void* ptr, int64_t bytes, const char* 
   } else {
     (void)hipGetLastError();
   }
-  if (reinterpret_cast<uintptr_t>(ptr) % 16 != 0 && bytes > 8)
-    return set_err(c, ORI_ERR_INVALID_ARG, "%s is not 16-byte aligned", what);
+  if (reinterpret_cast<uintptr_t>(ptr) % align != 0)
+    return set_err(c, ORI_ERR_INVALID_ARG, "%s is not %d-byte aligned", what, align);
   return ORI_OK;
 }
 
@@ -511,7 +512,6 @@ ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void*
     (void)hipGetLastError();  // the capture error is handled here
     c->poisoned = false;
     c->err = "no error";
-    ++c->eager_fallbacks;
     return ORI_OK;
   }
   if (st == ORI_OK) {
@@ -880,7 +880,7 @@ ori_status field_sum(ori_ctx c, const void* u, const double* pts, int64_t M, voi
   if (M < 0) return set_err(c, ORI_ERR_INVALID_ARG, "M = %lld must be >= 0", (long long)M);
   if (M == 0) return ORI_OK;
   ORI_TRY(check_dev_ptr(c, u, c->nrhs * c->P * 16, "u"));
-  ORI_TRY(check_dev_ptr(c, pts, M * 3 * 8, far ? "beta" : "x"));
+  ORI_TRY(check_dev_ptr(c, pts, M * 3 * 8, far ? "beta" : "x", 8));
   ORI_TRY(check_dev_ptr(c, out, c->nrhs * M * 16, far ? "A" : "v"));
   FieldArgs a{};
   a.u = static_cast<const cxd*>(u);
@@ -921,7 +921,7 @@ ori_status refraction(ori_ctx c, double k, double c_s, const void* n0, const voi
   const int64_t bytes = c->P * 16;
   ORI_TRY(check_dev_ptr(c, n0, bytes, "n0"));
   ORI_TRY(check_dev_ptr(c, in, bytes, design ? "n" : "h"));
-  if (N) ORI_TRY(check_dev_ptr(c, N, c->P * 8, "N"));
+  if (N) ORI_TRY(check_dev_ptr(c, N, c->P * 8, "N", 8));
   ORI_TRY(check_dev_ptr(c, out, bytes, design ? "h" : "n"));
   RefractionArgs a{};
   a.n0 = static_cast<const cxd*>(n0);
@@ -1091,7 +1091,7 @@ ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const v
   if (!(k > 0.0) || !std::isfinite(k)) return set_err(c, ORI_ERR_INVALID_ARG, "k must be finite and > 0");
   const int64_t P = c->P, R = c->nrhs;
   ORI_TRY(check_dev_ptr(c, h, P * 16, "h"));
-  if (N) ORI_TRY(check_dev_ptr(c, N, P * 8, "N"));
+  if (N) ORI_TRY(check_dev_ptr(c, N, P * 8, "N", 8));
   ORI_TRY(check_dev_ptr(c, u0, R * P * 16, "u0"));
   c->loaded = false;
   c->k = k;
@@ -1480,10 +1480,7 @@ ori_status ori_profile_read(ori_ctx c, int32_t max, const char** names, double* 
 void ori_destroy(ori_ctx c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  if (c->stream)
-    (void)hipStreamSynchronize(c->stream);
-  else
-    (void)hipDeviceSynchronize();
+  (void)hipStreamSynchronize(c->stream);  // all of the context's work is on its stream
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   for (auto& g : c->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);

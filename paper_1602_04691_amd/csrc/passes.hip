@@ -247,8 +247,10 @@ __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
 // stage, so element e = b + j L/R of the transform meets K(min(e, L-e), m2,
 // k3) in place) and runs the tiles (k2 = m2 | L - m2) x (right-hand sides)
 // one after the other (with PF, the loads of the next tile are issued before
-// the current one is transformed).  Every spectrum value is read from HBM
-// once per pass.
+// the current one is transformed).  The spectrum is read from its octant: the
+// tiles k3 and L - k3 of a row m2 need the same values; the workgroups of a
+// row take the tiles in the order 0, last, 1, last - 1, ... so that the two
+// run back to back on one XCD and the second read is served by its L2.
 //
 // Threads per pencil of the Z pass: the length's default, except complex128
 // at L >= 1024, which keeps one wavefront per pencil (two butterflies per
@@ -288,8 +290,13 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
   const int t = tid % NP, bt = tid / NP;
   const int64_t w = xcd_order(blockIdx.x, gridDim.x);
   const int64_t m2 = w / CT;
-  const int64_t k3 = (w % CT) * NP + t;
+  // tiles of a row in the order 0, CT-1, 1, CT-2, ...: a tile and its mirror
+  // (which reads the same spectrum values) run back to back
+  const int64_t j = w % CT;
+  const int64_t tile = (j & 1) ? CT - 1 - (j >> 1) : (j >> 1);
+  const int64_t k3 = tile * NP + t;
   const bool act = k3 < L;
+  const int64_t m3 = k3 <= L - k3 ? k3 : L - k3;  // the octant holds k3 and its mirror
   const cx<T>* __restrict__ kh = static_cast<const cx<T>*>(a.khat);
   // The twiddle table is staged in LDS: read from global memory inside a
   // stage, a twiddle would wait behind every tile load still in flight
@@ -310,7 +317,7 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
       const int e = b + j * STRIDE;
       const int m1 = e <= L - e ? e : L - e;
       const bool ok = act && (St::nbf(SL) % ZT == 0 || b < St::nbf(SL));
-      kv.v[i][j] = ok ? kh[(m1 * a.kp + m2) * L + k3] : cx<T>{};
+      kv.v[i][j] = ok ? kh[(m1 * a.kp + m2) * a.kp + m3] : cx<T>{};
     }
   }
   const int64_t nvar = (m2 != 0 && m2 != n) ? 2 : 1;  // uniform over the workgroup
@@ -443,15 +450,11 @@ __global__ void __launch_bounds__(block_s<double>()) k_spectrum_strided(Spectrum
         kh[base + e * axis] = v;
         return;
       }
-      // pass 3: K(k1 = e, k2 = o, k3 = c) and its mirror k3 -> L - k3
+      // pass 3: K(k1 = e, k2 = o, k3 = c), scaled, into the octant the Z pass reads
       v = scale(v, a.scale);
-      const int64_t row = (static_cast<int64_t>(e) * kp + o) * L;
-      kout[row + c] = v;
-      if (koutf) koutf[row + c] = cvt<float>(v);
-      if (c != 0 && c != n) {
-        kout[row + L - c] = v;
-        if (koutf) koutf[row + L - c] = cvt<float>(v);
-      }
+      const int64_t at = (static_cast<int64_t>(e) * kp + o) * kp + c;
+      kout[at] = v;
+      if (koutf) koutf[at] = cvt<float>(v);
     });
   });
 }

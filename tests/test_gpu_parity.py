@@ -276,6 +276,34 @@ def test_bad_inputs_rejected():
         assert st == ori.ORI_ERR_INVALID_ARG
 
 
+def test_alignment_rules():
+    # real arrays need 8-byte alignment, complex ones 16 (include/ori.h)
+    say("[alignment]")
+    import ctypes
+    n, k = 4, 2.0
+    case = workloads.make_case(n, k, seed=3)
+    P = n ** 3
+    lib = ori.lib()
+    hg, ug = gpu(case["h"]), gpu(case["u0"])
+    Nbuf = torch.zeros(P + 1, dtype=torch.float64, device="cuda")
+    Nbuf[1:] = torch.from_numpy(case["N"]).cuda()
+    Nview = Nbuf[1:]  # 8-byte aligned, not 16
+    assert Nview.data_ptr() % 16 == 8
+    out = []
+    for N in (gpu(case["N"]), Nview):
+        with ori.ori_setup(n, k, hg, N, ug) as ctx:
+            u = torch.empty(P, dtype=torch.complex128, device="cuda")
+            ori.ori_solve(ctx, u, tol=1e-12)
+            out.append(cpu(u))
+    assert np.array_equal(out[0], out[1])
+    # a complex128 array 8 bytes off its alignment is refused
+    hbuf = torch.zeros(2 * P + 1, dtype=torch.float64, device="cuda")
+    with ori.ori_create(n) as ctx:
+        st = lib.ori_load(ctx.handle, k, ctypes.c_void_p(hbuf.data_ptr() + 8), None, ctypes.c_void_p(ug.data_ptr()))
+        assert st == ori.ORI_ERR_INVALID_ARG
+        assert "aligned" in ori.ori_last_error(ctx)
+
+
 def test_deterministic_bitwise():
     say("[determinism]")
     n = 16
