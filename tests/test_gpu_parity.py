@@ -333,6 +333,32 @@ def test_initial_guess_restart():
 
 # ---------------------------------------------------------------------------
 # full sizes: sampled rows computed one by one by the oracle
+@pytest.mark.parametrize("n", [32, 40, 48, 64, 96, 192])
+def test_matvec_sampled_rows_every_length(n):
+    # the padded lengths the dense comparison does not reach: L = 64, 80, 96,
+    # 128, 192, 384 (radix 2, 3 and 5 stages; at L = 80 the Z pass has three
+    # tiles of 32 pencils over 80 columns: odd and ragged)
+    k, side, origin = 4.3, 1.1, (0.3, -0.2, 0.1)
+    say(f"[matvec rows] n={n}")
+    h, N, x = varied(n, seed=300 + n)
+    P = n ** 3
+    rng = np.random.default_rng(301 + n)
+    rows = np.concatenate([[0, P - 1, n * n - 1, P - n * n], rng.integers(0, P, 4)])
+    with context(n, k, h, N, x, side, origin) as ctx:
+        xg = gpu(x)
+        yg = torch.empty_like(xg)
+        ori.ori_matvec(ctx, xg, yg, ori.ORI_OP_SYSTEM, ori.ORI_FP64)
+        y = cpu(yg)
+        ori.ori_matvec(ctx, xg, yg, ori.ORI_OP_SYSTEM, ori.ORI_MIXED)
+        ym = cpu(yg)
+    pts = O.cell_points(n, side, origin)
+    D = O.coupling(h, N, n, side)
+    s = O.sample_scatter_rows(pts, k, D, x, rows)
+    say(f"   err64={rel(y[rows] - x[rows], s):.2e} err_mixed={rel(ym[rows] - x[rows], s):.2e}")
+    assert rel(y[rows] - x[rows], s) <= 1e-12
+    assert rel(ym[rows] - x[rows], s) <= 2e-6
+
+
 # ---------------------------------------------------------------------------
 # the pass layout the benchmark times at n = 256 (blk_lg 2 complex128, 3 complex64
 # with narrow Z tiles)
