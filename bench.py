@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle rows for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--layout", default="2,0,0,0/3,0,0,1",
+    ap.add_argument("--layout", default="2,0,0,1/3,0,0,1",
                     help="pass layout LG,NP,PF,ZNP[/LG,NP,PF,ZNP] (complex128 / complex64 passes: i1 row block, "
                          "narrow strided tiles, Z prefetch, narrow Z tiles); the default is what ori_tune picks "
                          "at n = 256 on MI355X; 'auto' tunes before timing, 'default' keeps the library's")

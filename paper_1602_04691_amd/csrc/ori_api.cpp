@@ -618,7 +618,8 @@ ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel)
 // ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF / ORI_TUNE_ZNP override both
 // for tuning runs.  Narrow Z tiles by default where they measured faster:
 // complex64 up to L = 512 (its wide workgroup of 16 wavefronts fits once per
-// CU, the narrow one twice) and complex128 from L = 1024 on.
+// CU, the narrow one twice) and complex128 from L = 512 on (0.57 vs 0.65 ms
+// at n = 256, while wide tiles win at L = 256).
 bool valid_knobs(int64_t n, const Knobs& k) {
   return k.blk_lg >= 0 && k.blk_lg <= 6 && n % (int64_t{1} << k.blk_lg) == 0 && (k.np_sel == 0 || k.np_sel == 1) &&
          (k.zpf == 0 || k.zpf == 1) && (k.z_np == 0 || k.z_np == 1);
@@ -627,7 +628,7 @@ bool valid_knobs(int64_t n, const Knobs& k) {
 void choose_layout(ori_ctx c) {
   for (int f = 0; f < 2; ++f) {
     Knobs k;
-    k.z_np = (f == 1 && c->L <= 512) || (f == 0 && c->L >= 1024) ? 1 : 0;
+    k.z_np = (f == 1 && c->L <= 512) || (f == 0 && c->L >= 512) ? 1 : 0;
     while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
     c->knob[f] = k;
   }
