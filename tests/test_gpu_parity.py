@@ -7,6 +7,7 @@ complex128 FFT product, <= 1e-10 for complex128 solves (run at tol 1e-12),
 """
 
 import math
+import os
 import sys
 
 import numpy as np
@@ -528,3 +529,21 @@ def test_degenerate_inputs():
         ori.ori_solve(ctx, ug, tol=1e-12)
         u = cpu(ug)
     assert np.all(np.isfinite(u)) and rel(u, u_ref) <= 1e-10
+
+
+def test_solves_vs_frozen_oracle_fixtures():
+    # the stored LU solutions of tests/golden/oracle_fixtures.npz (written by
+    # the oracle) against GPU solves through the C ABI, in both precisions
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_fixtures.npz"))
+    for key in sorted(k for k in z.files if k.endswith("_params")):
+        n, k, seed = z[key]
+        n, seed = int(n), int(seed)
+        case = workloads.make_case(n, float(k), seed)
+        ref = z[f"n{n}_u"]
+        for prec, bar in ((ori.ORI_FP64, 1e-10), (ori.ORI_MIXED, 1e-6)):
+            with context(n, float(k), case["h"], case["N"], case["u0"]) as ctx:
+                ug = torch.empty(n ** 3, dtype=torch.complex128, device="cuda")
+                ori.ori_solve(ctx, ug, tol=1e-12, precision=prec)
+                err = rel(cpu(ug), ref)
+            say(f"[fixture] n={n} k={k} prec={prec} err={err:.2e}")
+            assert err <= bar, (n, prec, err)

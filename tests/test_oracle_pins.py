@@ -315,3 +315,18 @@ def test_adjoint_gradient_matches_central_differences():
     c = O.coupling(np.ones(n ** 3), N, n).real
     g_wrong = -2 * c * u * (O.green_matrix(pts, k) @ lam_wrong)
     assert np.linalg.norm(g_wrong - g) > 1e-3 * np.linalg.norm(g)
+
+
+def test_frozen_oracle_fixtures_reproduce():
+    # the oracle still gives the LU solutions and condition numbers it wrote
+    # to tests/golden/oracle_fixtures.npz (make_oracle_fixtures.py)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(GOLDEN, "make_oracle_fixtures.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    z = np.load(os.path.join(GOLDEN, "oracle_fixtures.npz"))
+    for n, k, seed in mk.FIXTURES:
+        _, u, kappa = mk.compute(n, k, seed)
+        ref = z[f"n{n}_u"]
+        assert np.linalg.norm(u - ref) <= 1e-13 * np.linalg.norm(ref), n
+        assert abs(kappa - float(z[f"n{n}_kappa"])) <= 1e-10 * kappa, n
