@@ -82,6 +82,7 @@ def build(jobs=None, incremental=False, verbose=False):
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{p.stdout}{p.stderr}")
     os.replace(tmp, LIB)
     _build_c_smoke()
+    _build_sanitized(objs)
     return LIB
 
 
@@ -98,6 +99,53 @@ def _build_c_smoke():
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{p.stdout}{p.stderr}")
+
+
+# The runtime's host code under AddressSanitizer and UBSan (device code is
+# not instrumented: every -fsanitize= applies to the host pass only), linked
+# with the same kernel objects, and two C programs against it: the host-only
+# paths of the ABI (runs without a GPU) and the C ABI smoke program.
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_LIB = os.path.join(ASAN_DIR, "libori_asan.so")
+C_HOST_PATHS_SRC = os.path.join(ROOT, "tests", "c", "ori_host_paths.c")
+C_HOST_PATHS_ASAN = os.path.join(ROOT, "tests", "c", "ori_host_paths_asan")
+C_SMOKE_ASAN = os.path.join(ROOT, "tests", "c", "ori_abi_smoke_asan")
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime_dir():
+    # the directory of the compiler's own libclang_rt.asan-x86_64.so
+    p = subprocess.run([HIPCC, "--print-resource-dir"], capture_output=True, text=True)
+    res = p.stdout.strip().splitlines()[-1] if p.returncode == 0 and p.stdout.strip() else ""
+    d = os.path.join(res, "lib", "linux")
+    return d if res and os.path.exists(os.path.join(d, "libclang_rt.asan-x86_64.so")) else None
+
+
+def _run(cmd):
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"build failed: {' '.join(cmd)}\n{p.stdout}{p.stderr}")
+
+
+def _build_sanitized(objs):
+    rt = asan_runtime_dir()
+    if rt is None:
+        return None
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    src = os.path.join(CSRC, "ori_api.cpp")
+    obj = os.path.join(ASAN_DIR, "ori_api.o")
+    _run([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", "-O1", "-g", "-std=c++17", "-fPIC",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC]
+         + SANITIZE + ["-c", src, "-o", obj])
+    kernels = [o for o in objs if os.path.basename(o) != "ori_api.o"]
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + SANITIZE + ["-shared-libasan", "-o", ASAN_LIB, obj]
+         + kernels + [f"-Wl,-rpath,{rt}"])
+    for src, out in ((C_HOST_PATHS_SRC, C_HOST_PATHS_ASAN), (C_SMOKE_SRC, C_SMOKE_ASAN)):
+        _run([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", "-O1", "-g", "-I", INCLUDE] + SANITIZE
+             + ["-shared-libasan", src, "-o", out, "-L", ASAN_DIR, "-lori_asan", f"-Wl,-rpath,{rt}",
+                "-Wl,-rpath,$ORIGIN/../../paper_1602_04691_amd/_build/asan"])
+    return ASAN_LIB
 
 
 def main(argv=None):
