@@ -274,6 +274,16 @@ ori_status ori_set_layout(ori_ctx ctx, int32_t precision, const ori_layout* layo
  * precision that is not provisioned).  Synchronises the context stream. */
 ori_status ori_tune(ori_ctx ctx, int32_t reps, ori_layout* best, double* ms_per_product);
 
+/* Memory-safety check of the library's own workspaces.  Every workspace is
+ * followed by a 4 KB guard band of a fixed byte pattern; *damaged receives
+ * the number of bands no longer intact (0 unless a kernel wrote past the end
+ * of a workspace).  With ORI_CHECK_GUARDS=1 in the environment when a context
+ * is created, every kernel launch of that context is followed by this check
+ * (graph replay is then off) and a damaged band ends the call with
+ * ORI_ERR_DEVICE naming the kernel: a slow debug mode.  Synchronises the
+ * context stream. */
+ori_status ori_check_guards(ori_ctx ctx, int64_t* damaged);
+
 /* Per-kernel timing with HIP events on the context stream.  enable = 1
  * clears the counters and starts recording every launch; 0 stops. */
 ori_status ori_profile_enable(ori_ctx ctx, int32_t enable);

@@ -112,6 +112,7 @@ def lib():
             "ori_get_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout)]),
             "ori_set_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout)]),
             "ori_tune": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout), ctypes.POINTER(D)]),
+            "ori_check_guards": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64)]),
             "ori_destroy": (None, [P]),
             "ori_last_error": (ctypes.c_char_p, [P]),
         }
@@ -402,6 +403,13 @@ def ori_tune(ctx, reps=0):
     ms = (ctypes.c_double * 2)()
     _check(lib().ori_tune(ctx.handle, int(reps), best, ms), ctx)
     return {"fp64": (best[0].as_dict(), ms[0]), "c64": (best[1].as_dict(), ms[1])}
+
+
+def ori_check_guards(ctx):
+    """Number of the context's workspaces whose trailing guard band was overwritten."""
+    out = ctypes.c_int64()
+    _check(lib().ori_check_guards(ctx.handle, ctypes.byref(out)), ctx)
+    return out.value
 
 
 def ori_profile_enable(ctx, enable=True):

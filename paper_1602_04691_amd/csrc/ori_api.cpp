@@ -68,6 +68,9 @@ const char* const kKindNames[K_NKIND] = {"f1", "f2", "zpass", "i2", "i1", "updat
 
 thread_local std::string g_last_error = "no error";
 
+constexpr int64_t kGuardBytes = 4096;
+constexpr unsigned char kGuardByte = 0xA5;
+
 // Layout knobs of the FFT passes (performance only)
 struct Knobs {
   int blk_lg = 4;  // log2 of the i1 block of the B layout (n divisible by 2^blk_lg)
@@ -137,6 +140,11 @@ struct ori_ctx_s {
   double* outer_m = nullptr;       // [2 nrhs]: refinement multipliers, then inner tolerances^2
   double* outer_m_host = nullptr;  // pinned
   std::vector<void*> allocs;
+  // guard band after every workspace: kGuardBytes of kGuardByte, checked by
+  // ori_check_guards and, with ORI_CHECK_GUARDS=1 in the environment at
+  // create, after every kernel launch
+  std::vector<unsigned char*> guards;
+  bool check_guards = false;
 
   // captured COCG iteration blocks, one per vector precision
   struct IterGraph {
@@ -226,7 +234,8 @@ Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
   const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
   l.total = l.arena + shared + batch + l.kh + l.khf + align_up(2 * n * 16) + align_up(2 * n * 8) +
-            align_up(l.npart * 4 * 8) + align_up(nrhs * (int64_t)sizeof(ScalarBlock)) + align_up(2 * nrhs * 8);
+            align_up(l.npart * 4 * 8) + align_up(nrhs * (int64_t)sizeof(ScalarBlock)) + align_up(2 * nrhs * 8) +
+            (mixed ? 24 : 18) * kGuardBytes;  // one guard band per allocation
   return l;
 }
 
@@ -276,6 +285,23 @@ ori_status prof_fold(ori_ctx c) {
   return ORI_OK;
 }
 
+// number of workspaces whose guard band no longer holds kGuardByte
+ori_status count_damaged_guards(ori_ctx c, int64_t* damaged) {
+  std::vector<unsigned char> h(kGuardBytes);
+  ORI_HIP(c, hipStreamSynchronize(c->stream));
+  int64_t bad = 0;
+  for (unsigned char* g : c->guards) {
+    ORI_HIP(c, hipMemcpy(h.data(), g, kGuardBytes, hipMemcpyDeviceToHost));
+    for (unsigned char v : h)
+      if (v != kGuardByte) {
+        ++bad;
+        break;
+      }
+  }
+  *damaged = bad;
+  return ORI_OK;
+}
+
 template <class F>
 ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
   int evi = -1;
@@ -295,6 +321,12 @@ ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
   if (e != hipSuccess) {
     c->launch_err = e;
     return set_err(c, ORI_ERR_DEVICE, "kernel %s launch failed: %s", kKindNames[kind], hipGetErrorString(e));
+  }
+  if (c->check_guards) {
+    int64_t bad = 0;
+    ORI_TRY(count_damaged_guards(c, &bad));
+    if (bad) return set_err(c, ORI_ERR_DEVICE, "kernel %s wrote past the end of %lld workspace(s)", kKindNames[kind],
+                            (long long)bad);
   }
   if (timed) {
     ORI_HIP(c, hipEventRecord(c->ev[2 * evi + 1], c->stream));
@@ -551,7 +583,7 @@ ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* 
     out->all_done = true;
     return ORI_OK;
   }
-  use_graph = use_graph && !c->prof;
+  use_graph = use_graph && !c->prof && !c->check_guards;
   int it = 0;
   while (it < max_iter) {
     // the first block runs eagerly (it holds the first iteration); later
@@ -1005,6 +1037,7 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
   c->u0norm2.assign(nrhs, 0.0);
   c->bnorm2.assign(nrhs, 0.0);
   choose_layout(c);
+  if (const char* e = std::getenv("ORI_CHECK_GUARDS")) c->check_guards = std::atoi(e) != 0;
   c->stream = static_cast<hipStream_t>(stream);
   auto fail = [&](ori_status st) {
     g_last_error = c->err;
@@ -1020,13 +1053,17 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
       *p = nullptr;
       return ORI_OK;
     }
-    hipError_t e = hipMalloc(p, static_cast<size_t>(bytes));
+    hipError_t e = hipMalloc(p, static_cast<size_t>(bytes + kGuardBytes));
     if (e != hipSuccess) {
       (void)hipGetLastError();
       *p = nullptr;
       return set_err(c, ORI_ERR_OUT_OF_MEMORY, "hipMalloc(%lld) failed: %s", (long long)bytes, hipGetErrorString(e));
     }
     c->allocs.push_back(*p);
+    unsigned char* guard = static_cast<unsigned char*>(*p) + bytes;
+    if (hipMemset(guard, kGuardByte, kGuardBytes) != hipSuccess)
+      return set_err(c, ORI_ERR_DEVICE, "hipMemset of a guard band failed");
+    c->guards.push_back(guard);
     return ORI_OK;
   };
   ori_status st = ORI_OK;
@@ -1476,6 +1513,12 @@ ori_status ori_profile_read(ori_ctx c, int32_t max, const char** names, double* 
   }
   if (count) *count = w;
   return ORI_OK;
+}
+
+ori_status ori_check_guards(ori_ctx c, int64_t* damaged) {
+  ORI_TRY(guard(c));
+  if (!damaged) return set_err(c, ORI_ERR_INVALID_ARG, "damaged is NULL");
+  return count_damaged_guards(c, damaged);
 }
 
 void ori_destroy(ori_ctx c) {
