@@ -218,7 +218,7 @@ struct Layout {
 
 // Device bytes for n and a batch of nrhs.  Partial quadruples cover the
 // largest reducing grid: I1 (at most n*n workgroups per right-hand side) and
-// the reduction kernels (red_blocks(P) per right-hand side).
+// the reduction kernels (red_blocks(P), update_blocks(P) per right-hand side).
 Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   const int64_t P = n * n * n, kp = n + 1;
   const bool mixed = provision & ORI_PROVISION_MIXED;
@@ -230,7 +230,7 @@ Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   l.vec_f = align_up(P * 8);
   l.kh = align_up(kp * kp * kp * 16);  // octant [n+1][n+1][n+1]
   l.khf = mixed ? align_up(kp * kp * kp * 8) : 0;
-  l.npart = nrhs * std::max<int64_t>(red_blocks(P), n * n);
+  l.npart = nrhs * std::max({red_blocks(P), update_blocks(P), n * n});
   const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
   const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
   l.total = l.arena + shared + batch + l.kh + l.khf + align_up(2 * n * 16) + align_up(2 * n * 8) +
@@ -494,7 +494,7 @@ ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* 
   ORI_TRY(launch(c, K_UPDATE, prec, [&] {
     return launch_update(prec, nullptr, p, r, q, c->P, c->nrhs, c->sc, c->partials, c->stream);
   }));
-  return finalize(c, rblocks(c), FIN_RHO);
+  return finalize(c, update_blocks(c->P), FIN_RHO);
 }
 
 bool capture_error(hipError_t e) {
