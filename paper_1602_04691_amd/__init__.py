@@ -493,10 +493,16 @@ def OriSolve(h, u0, n, k, N=None, side=1.0, **opts):
 def solve_many(problems, **opts):
     """Independent problems of any sizes, each on its own context and stream,
     solved concurrently from a thread pool (the library call releases the
-    GIL).  problems: dicts with n, k, h, N, u0 (CUDA tensors).  Returns a list
-    of (u, info) in order."""
+    GIL), with eager launches (no graph replay unless graph=True is passed).
+    problems: dicts with n, k, h, N, u0 (CUDA tensors).  Returns a list of
+    (u, info) in order."""
     import concurrent.futures
     import torch
+
+    # eager launches: HIP graph capture has failed intermittently while other
+    # threads worked on the device (see the capture lock in the runtime), and
+    # graph replay gains nothing at the sizes solved side by side
+    opts.setdefault("graph", False)
 
     def one(p):
         s = torch.cuda.Stream()

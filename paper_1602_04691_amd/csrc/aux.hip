@@ -414,10 +414,10 @@ hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, S
 hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* q, int64_t P, int64_t nrhs,
                          const ScalarBlock* sc, double* partials, hipStream_t st) {
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_update<double>, red_grid(P, nrhs, kUpdateBlocksMax), dim3(kRedThreads), 0, st, static_cast<cxd*>(x),
+    hipLaunchKernelGGL(k_update<double>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<cxd*>(x),
                        static_cast<const cxd*>(p), static_cast<cxd*>(r), static_cast<const cxd*>(q), P, sc, partials);
   else
-    hipLaunchKernelGGL(k_update<float>, red_grid(P, nrhs, kUpdateBlocksMax), dim3(kRedThreads), 0, st, static_cast<cxf*>(x),
+    hipLaunchKernelGGL(k_update<float>, red_grid(P, nrhs, kUpdateBlocksMaxF32), dim3(kRedThreads), 0, st, static_cast<cxf*>(x),
                        static_cast<const cxf*>(p), static_cast<cxf*>(r), static_cast<const cxf*>(q), P, sc, partials);
   return hipGetLastError();
 }

@@ -215,13 +215,15 @@ inline int64_t red_blocks(int64_t P, int64_t cap = kRedBlocksMax) {
   if (b > cap) b = cap;
   return b < 1 ? 1 : b;
 }
-// The COCG update (r -= alpha q with the partials of r^T r and |r|^2) runs on
-// up to 4096 workgroups: on complex64 vectors (8 bytes per element) 1024 of
-// them leave too few loads in flight (0.113 vs 0.079 ms at n = 256); the
-// other reductions measured faster on 1024.  Its partials are finalised with
-// the same count.
-constexpr int64_t kUpdateBlocksMax = 4096;
-inline int64_t update_blocks(int64_t P) { return red_blocks(P, kUpdateBlocksMax); }
+// The complex64 COCG update (r -= alpha q with the partials of r^T r and
+// |r|^2) runs on up to 4096 workgroups: on 8-byte elements 1024 of them leave
+// too few loads in flight (0.113 vs 0.079 ms at n = 256, 0.93 vs 0.65 ms at
+// n = 512).  The complex128 update and the other reductions measured faster
+// on 1024.  The update's partials are finalised with the same count.
+constexpr int64_t kUpdateBlocksMaxF32 = 4096;
+inline int64_t update_blocks(int64_t P, int prec) {
+  return red_blocks(P, prec == PREC_F32 ? kUpdateBlocksMaxF32 : kRedBlocksMax);
+}
 
 // a1 (operator): D = 4 pi h N vol, S = sqrt(D), complex64 S, c = 4 pi N vol;
 // partials {bad-input count, min |S|^2, max |S|^2, 0} (one range), reduced
@@ -248,7 +250,7 @@ enum FinalizeMode : int32_t {
 hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, ScalarBlock* sc, int32_t mode,
                            double eps, double tol2, int32_t tol2_of_bb, const double* tol2_rhs, hipStream_t st);
 // r -= alpha q (and x += alpha p when x is not NULL); partials
-// {r^T r, ||r||^2} on (update_blocks(P), nrhs) workgroups; converged
+// {r^T r, ||r||^2} on (update_blocks(P, prec), nrhs) workgroups; converged
 // right-hand sides (alpha = 0) stay as they are
 hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* q, int64_t P, int64_t nrhs,
                          const ScalarBlock* sc, double* partials, hipStream_t st);

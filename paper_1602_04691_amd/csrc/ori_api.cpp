@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -96,6 +97,19 @@ struct Tuned {
   bool have[2] = {false, false};
 };
 std::mutex g_tune_mu;
+
+// Graph capture and other threads' work on the device.  A capture of COCG
+// iterations on one context has failed when other threads were working on
+// theirs at the same time (the capture invalidated, another thread's kernel
+// launch or the graph instantiation refused), though contexts are
+// independent.  So kernel launches and graph replays hold this lock shared,
+// and a capture with its instantiation, and the destruction of graphs and
+// capture streams, hold it exclusively.  The capturing thread's own launches
+// are recorded into the graph and skip the lock (t_capturing).  Work that
+// other threads do outside the library is not covered: solve_many, which
+// runs contexts from several threads, solves without graph replay.
+std::shared_mutex g_capture_mu;
+thread_local bool t_capturing = false;
 std::map<TuneKey, Tuned> g_tuned;
 
 struct ProfPending {
@@ -218,7 +232,7 @@ struct Layout {
 
 // Device bytes for n and a batch of nrhs.  Partial quadruples cover the
 // largest reducing grid: I1 (at most n*n workgroups per right-hand side) and
-// the reduction kernels (red_blocks(P), update_blocks(P) per right-hand side).
+// the reduction kernels (red_blocks(P), update_blocks(P, prec) per right-hand side).
 Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   const int64_t P = n * n * n, kp = n + 1;
   const bool mixed = provision & ORI_PROVISION_MIXED;
@@ -230,7 +244,7 @@ Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   l.vec_f = align_up(P * 8);
   l.kh = align_up(kp * kp * kp * 16);  // octant [n+1][n+1][n+1]
   l.khf = mixed ? align_up(kp * kp * kp * 8) : 0;
-  l.npart = nrhs * std::max({red_blocks(P), update_blocks(P), n * n});
+  l.npart = nrhs * std::max({red_blocks(P), update_blocks(P, PREC_F32), n * n});
   const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
   const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
   l.total = l.arena + shared + batch + l.kh + l.khf + align_up(2 * n * 16) + align_up(2 * n * 8) +
@@ -317,7 +331,13 @@ ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
     }
     ORI_HIP(c, hipEventRecord(c->ev[2 * evi], c->stream));
   }
-  hipError_t e = f();
+  hipError_t e;
+  {
+    std::shared_lock<std::shared_mutex> lk(g_capture_mu, std::defer_lock);
+    if (!t_capturing) lk.lock();
+    (void)hipGetLastError();  // the launch reports its own error, not an earlier call's
+    e = f();
+  }
   if (e != hipSuccess) {
     c->launch_err = e;
     return set_err(c, ORI_ERR_DEVICE, "kernel %s launch failed: %s", kKindNames[kind], hipGetErrorString(e));
@@ -494,7 +514,7 @@ ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* 
   ORI_TRY(launch(c, K_UPDATE, prec, [&] {
     return launch_update(prec, nullptr, p, r, q, c->P, c->nrhs, c->sc, c->partials, c->stream);
   }));
-  return finalize(c, update_blocks(c->P), FIN_RHO);
+  return finalize(c, update_blocks(c->P, prec), FIN_RHO);
 }
 
 bool capture_error(hipError_t e) {
@@ -518,6 +538,7 @@ ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void*
     *out = g.exec;
     return ORI_OK;
   }
+  std::unique_lock<std::shared_mutex> capture_lock(g_capture_mu);
   if (g.exec) {
     ORI_HIP(c, hipGraphExecDestroy(g.exec));
     g.exec = nullptr;
@@ -526,6 +547,7 @@ ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void*
   hipStream_t own = c->stream;
   c->stream = c->cap_stream;
   hipGraph_t graph = nullptr;
+  t_capturing = true;
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
   ori_status st = e == hipSuccess ? ORI_OK : set_err(c, ORI_ERR_DEVICE, "hipStreamBeginCapture: %s",
                                                      hipGetErrorString(e));
@@ -539,6 +561,7 @@ ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void*
       st = set_err(c, ORI_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
   }
   c->stream = own;
+  t_capturing = false;
   if (invalidated) {
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipGetLastError();  // the capture error is handled here
@@ -592,6 +615,7 @@ ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* 
     hipGraphExec_t exec = nullptr;
     if (use_graph && it > 0 && blk == check_every) ORI_TRY(iteration_graph(c, prec, x, r, p, q, S, blk, &exec));
     if (exec) {
+      std::shared_lock<std::shared_mutex> lk(g_capture_mu);
       ORI_HIP(c, hipGraphLaunch(exec, c->stream));
     } else {
       for (int j = 0; j < blk; ++j) ORI_TRY(cocg_iteration(c, prec, x, r, p, q, S, it + j == 0));
@@ -649,9 +673,9 @@ ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel)
 // measured defaults, or from the tuned layout of this (device, n, nrhs);
 // ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF / ORI_TUNE_ZNP override both
 // for tuning runs.  Narrow Z tiles by default where they measured faster:
-// complex64 up to L = 512 (its wide workgroup of 16 wavefronts fits once per
-// CU, the narrow one twice) and complex128 from L = 512 on (0.57 vs 0.65 ms
-// at n = 256, while wide tiles win at L = 256).
+// complex64 at every length (at L = 512 its wide workgroup of 16 wavefronts
+// fits once per CU, the narrow one three times) and complex128 from L = 512
+// on (0.57 vs 0.65 ms at n = 256, while wide tiles win at L = 256).
 bool valid_knobs(int64_t n, const Knobs& k) {
   return k.blk_lg >= 0 && k.blk_lg <= 6 && n % (int64_t{1} << k.blk_lg) == 0 && (k.np_sel == 0 || k.np_sel == 1) &&
          (k.zpf == 0 || k.zpf == 1) && (k.z_np == 0 || k.z_np == 1);
@@ -660,7 +684,7 @@ bool valid_knobs(int64_t n, const Knobs& k) {
 void choose_layout(ori_ctx c) {
   for (int f = 0; f < 2; ++f) {
     Knobs k;
-    k.z_np = (f == 1 && c->L <= 512) || (f == 0 && c->L >= 512) ? 1 : 0;
+    k.z_np = (f == 1 || c->L >= 512) ? 1 : 0;
     while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
     c->knob[f] = k;
   }
@@ -686,6 +710,7 @@ void choose_layout(ori_ctx c) {
 
 // Captured graphs bake the layout into their kernel arguments.
 ori_status drop_graphs(ori_ctx c) {
+  std::unique_lock<std::shared_mutex> lk(g_capture_mu);
   for (auto& g : c->graphs) {
     if (g.exec) ORI_HIP(c, hipGraphExecDestroy(g.exec));
     g.exec = nullptr;
@@ -1526,9 +1551,12 @@ void ori_destroy(ori_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);  // all of the context's work is on its stream
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-  for (auto& g : c->graphs)
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  {
+    std::unique_lock<std::shared_mutex> lk(g_capture_mu);
+    for (auto& g : c->graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  }
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   if (c->outer_m_host) (void)hipHostFree(c->outer_m_host);

@@ -252,12 +252,13 @@ __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
 // row take the tiles in the order 0, last, 1, last - 1, ... so that the two
 // run back to back on one XCD and the second read is served by its L2.
 //
-// Threads per pencil of the Z pass: the length's default, except complex128
-// at L >= 1024, which keeps one wavefront per pencil (two butterflies per
-// thread): with two wavefronts its registers spill (measured slower).
+// Threads per pencil of the Z pass: the length's default, except at
+// L >= 1024, where one wavefront per pencil (two butterflies per thread)
+// measured faster than two: complex128 6.6 vs 6.9 ms (it spills on two),
+// complex64 on narrow tiles 3.9 vs 4.6 ms at n = 512.
 template <typename T>
 constexpr int z_tpp() {
-  return (sizeof(T) == 8 && L >= 1024 && TPP > 64) ? 64 : TPP;
+  return (L >= 1024 && TPP > 64) ? 64 : TPP;
 }
 
 // Waves per SIMD that the register allocation must allow.  At L = 512 the

@@ -123,10 +123,10 @@ def test_tune_fp64_only_provision():
         assert res["fp64"][1] > 0 and res["c64"][1] == -1.0
 
 
-@pytest.mark.parametrize("n,z128,z64", [(16, 0, 1), (128, 0, 1), (256, 1, 1), (512, 1, 0)])
+@pytest.mark.parametrize("n,z128,z64", [(16, 0, 1), (128, 0, 1), (256, 1, 1), (512, 1, 1)])
 def test_default_z_tile_width(n, z128, z64):
-    # narrow Z tiles by default where they measured faster: complex64 up to
-    # L = 512, complex128 from L = 512 on
+    # narrow Z tiles by default where they measured faster: complex64 at every
+    # length, complex128 from L = 512 on
     with ori.ori_create(n) as ctx:
         assert ori.ori_get_layout(ctx, ori.ORI_FP64)["znarrow"] == z128
         assert ori.ori_get_layout(ctx, ori.ORI_MIXED)["znarrow"] == z64
