@@ -17,8 +17,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Deterministic workgroup sum of 4 values (kRedThreads threads); thread 0
 // writes out[0..3].
+template <int NT = kRedThreads>
 __device__ __forceinline__ void block_sum4(double (&v)[4], double* out) {
-  __shared__ double sh[(kRedThreads / 64) * 4];
+  __shared__ double sh[(NT / 64) * 4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) v[j] = wave_sum(v[j]);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -31,7 +32,7 @@ __device__ __forceinline__ void block_sum4(double (&v)[4], double* out) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       double s = 0.0;
-      for (int i = 0; i < kRedThreads / 64; ++i) s += sh[i * 4 + j];
+      for (int i = 0; i < NT / 64; ++i) s += sh[i * 4 + j];
       out[j] = s;
     }
   }
@@ -175,19 +176,21 @@ __global__ void __launch_bounds__(kRedThreads)
 }
 
 // One workgroup per right-hand side: reduce its nblk partial quadruples in a
-// fixed order and update its scalars.
-__global__ void __launch_bounds__(kRedThreads)
+// fixed order and update its scalars.  1024 threads: after the I1 pass there
+// is one quadruple per I1 workgroup (16 384 at n = 256).
+constexpr int kFinThreads = 1024;
+__global__ void __launch_bounds__(kFinThreads)
     k_finalize(const double* __restrict__ partials, int64_t nblk, ScalarBlock* scb, int32_t mode, double eps,
                double tol2, int32_t tol2_of_bb, const double* __restrict__ tol2_rhs) {
   const double* part = partials + 4 * nblk * blockIdx.x;
   ScalarBlock* sc = scb + blockIdx.x;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = threadIdx.x; i < nblk; i += kRedThreads) {
+  for (int64_t i = threadIdx.x; i < nblk; i += kFinThreads) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] += part[4 * i + j];
   }
   __shared__ double tot[4];
-  block_sum4(acc, tot);
+  block_sum4<kFinThreads>(acc, tot);
   __syncthreads();
   if (threadIdx.x != 0) return;
   const double s0 = tot[0], s1 = tot[1], s2 = tot[2], s3 = tot[3];
@@ -406,7 +409,7 @@ hipError_t launch_rhs(const void* u0, const void* S, int64_t P, int64_t nrhs, vo
 
 hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, ScalarBlock* sc, int32_t mode,
                            double eps, double tol2, int32_t tol2_of_bb, const double* tol2_rhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>(nrhs)), dim3(kRedThreads), 0, st, partials, nblk, sc,
+  hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>(nrhs)), dim3(kFinThreads), 0, st, partials, nblk, sc,
                      mode, eps, tol2, tol2_of_bb, tol2_rhs);
   return hipGetLastError();
 }
