@@ -182,9 +182,9 @@ struct Dft<INV, 5, T> {
 // ---------------------------------------------------------------------------
 // Stage bookkeeping
 // ---------------------------------------------------------------------------
-template <int L, bool INV, int TP = threads_per_pencil(L)>
+template <int L, bool INV, int TP = threads_per_pencil(L), int PV = 0>
 struct Stages {
-  static constexpr RadixPlan plan = radix_plan(L);
+  static constexpr RadixPlan plan = radix_plan(L, PV);  // PV: plan variant (plan.h)
   static constexpr int NS = plan.n;
   static constexpr int TPP = TP;  // threads per pencil
   static constexpr int radix(int s) { return INV ? plan.r[NS - 1 - s] : plan.r[s]; }
@@ -195,6 +195,14 @@ struct Stages {
   }
   static constexpr int nbf(int s) { return L / radix(s); }            // butterflies per pencil
   static constexpr int cnt(int s) { return (nbf(s) + TPP - 1) / TPP; }  // per thread
+  static constexpr bool radices_ok() {
+    for (int s = 0; s < NS; ++s) {
+      int r = plan.r[s];
+      if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8 && r != 16) return false;
+    }
+    return true;
+  }
+  static_assert(NS > 0 && ns(NS) == L && radices_ok(), "plan must factor L into radices 2, 3, 4, 5, 8, 16");
 };
 
 // One thread's view of its pencil in LDS.  Strided passes interleave NP
@@ -221,9 +229,9 @@ struct Regs {
   cx<T> v[C][R];
 };
 
-template <typename T, int L, bool INV, int TP = threads_per_pencil(L)>
+template <typename T, int L, bool INV, int TP = threads_per_pencil(L), int PV = 0>
 struct Engine {
-  using St = Stages<L, INV, TP>;
+  using St = Stages<L, INV, TP, PV>;
   static constexpr int NS = St::NS;
   static constexpr int TPP = St::TPP;
 

@@ -271,16 +271,23 @@ constexpr int z_min_waves() {
   return (L == 512 && sizeof(T) == 4 && !PF && NP * z_tpp<T>() == 512) ? 6 : 1;
 }
 
+// plan variant of the Z pass (plan.h: radix_plan(L, variant))
 template <typename T>
-using ZRegs = typename Engine<T, L, false, z_tpp<T>()>::template RegsOf<Stages<L, false, z_tpp<T>()>::NS - 1>;
+constexpr int z_plan() {
+  return sizeof(T) == 8 ? 1 : 0;
+}
+
+template <typename T>
+using ZRegs = typename Engine<T, L, false, z_tpp<T>(), z_plan<T>()>::template RegsOf<
+    Stages<L, false, z_tpp<T>(), z_plan<T>()>::NS - 1>;
 
 template <typename T, int NP, bool PF>
 __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k_zpass(ZArgs a) {
   constexpr int n = L / 2;
   constexpr int ZT = z_tpp<T>();
-  using EF = Engine<T, L, false, ZT>;
-  using EI = Engine<T, L, true, ZT>;
-  using St = Stages<L, false, ZT>;
+  using EF = Engine<T, L, false, ZT, z_plan<T>()>;
+  using EI = Engine<T, L, true, ZT, z_plan<T>()>;
+  using St = Stages<L, false, ZT, z_plan<T>()>;
   using G0 = typename EF::template RegsOf<0>;
   constexpr int SL = St::NS - 1;
   constexpr int RL = St::radix(SL);

@@ -50,6 +50,15 @@ constexpr RadixPlan radix_plan(int L) {
   }
 }
 
+// Alternative plans for single kernels.  The complex128 Z pass at L = 1024
+// runs 16 x 8 x 8: two exchanges per transform instead of three with the
+// same 64 threads per pencil (6.04 vs 6.52 ms at n = 512); the other passes
+// keep 8 x 8 x 4 x 4, with which they measured faster.
+constexpr RadixPlan radix_plan(int L, int variant) {
+  if (variant == 1 && L == 1024) return {3, {16, 8, 8, 0}};
+  return radix_plan(L);
+}
+
 constexpr bool supported_length(int L) { return radix_plan(L).n > 0; }
 
 // Threads per pencil: the smallest butterfly count over the stages, so that
