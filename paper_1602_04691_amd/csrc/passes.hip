@@ -331,21 +331,26 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
   const int64_t nvar = (m2 != 0 && m2 != n) ? 2 : 1;  // uniform over the workgroup
   const int64_t ntile = nvar * a.nrhs;
   const int64_t emask = (int64_t{1} << a.e_lg) - 1;
-  auto tile_base = [&](int64_t it) -> int64_t {
-    const int64_t rhs = it % a.nrhs;
-    const int64_t k2 = (it / a.nrhs) ? L - m2 : m2;
-    return rhs * a.batch_stride + k2 * a.o_stride + k3;
+  // tiles in the order (k2 = m2, rhs 0..R-1), (k2 = L - m2, rhs 0..R-1),
+  // walked with counters (no division by R per tile)
+  int64_t nx_rhs = 0, nx_var = 0;
+  auto next_base = [&]() -> int64_t {
+    const int64_t k2 = nx_var ? L - m2 : m2;
+    const int64_t base = nx_rhs * a.batch_stride + k2 * a.o_stride + k3;
+    if (++nx_rhs == a.nrhs) {
+      nx_rhs = 0;
+      ++nx_var;
+    }
+    return base;
   };
   auto addr = [&](int64_t base, int e) -> int64_t {
     return base + (e >> a.e_lg) * a.e_hi + (e & emask) * a.e_lo;
   };
-  auto fetch = [&](G0& g, int64_t it) {
-    const int64_t base = tile_base(it);
+  auto fetch = [&](G0& g, int64_t base) {
     EF::template load_first<true>(g, bt, [&](int e) -> cx<T> { return act ? buf[addr(base, e)] : cx<T>{}; });
   };
   LdsPencil<T> lp{lds + t, NP};
-  auto transform = [&](G0& g, int64_t it) {
-    const int64_t base = tile_base(it);
+  auto transform = [&](G0& g, int64_t base) {
     EF::template run<true>(g, bt, lp, tw, [&](auto& gl) {
 #pragma unroll
       for (int i = 0; i < St::cnt(SL); ++i) {
@@ -364,22 +369,30 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
     // two register sets in turn: the loads of tile it + 1 are in flight while
     // tile it is transformed
     G0 ga, gb;
-    fetch(ga, 0);
+    int64_t ba = next_base(), bb = 0;
+    fetch(ga, ba);
 #pragma unroll 1
     for (int64_t it = 0; it < ntile; it += 2) {
-      if (it + 1 < ntile) fetch(gb, it + 1);
-      transform(ga, it);
       if (it + 1 < ntile) {
-        if (it + 2 < ntile) fetch(ga, it + 2);
-        transform(gb, it + 1);
+        bb = next_base();
+        fetch(gb, bb);
+      }
+      transform(ga, ba);
+      if (it + 1 < ntile) {
+        if (it + 2 < ntile) {
+          ba = next_base();
+          fetch(ga, ba);
+        }
+        transform(gb, bb);
       }
     }
   } else {
     G0 g;
 #pragma unroll 1
     for (int64_t it = 0; it < ntile; ++it) {
-      fetch(g, it);
-      transform(g, it);
+      const int64_t base = next_base();
+      fetch(g, base);
+      transform(g, base);
     }
   }
 }
