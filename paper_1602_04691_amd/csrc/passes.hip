@@ -448,8 +448,11 @@ __global__ void __launch_bounds__(block_s<double>()) k_spectrum_strided(Spectrum
   using E = Engine<double, L, false>;
   const int tid = threadIdx.x;
   const int t = tid % NP, bt = tid / NP;
-  const int64_t o = blockIdx.x / CT;
-  const int64_t c = (blockIdx.x % CT) * NP + t;
+  // neighbouring column tiles share cache lines (rows of kp = n + 1 values
+  // are not line aligned), so they run on one XCD
+  const int64_t w = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t o = w / CT;
+  const int64_t c = (w % CT) * NP + t;
   const bool act = c < kp;
   const int64_t ostride = a.pass == 2 ? int64_t{kp} * kp : kp;
   const int64_t axis = a.pass == 2 ? kp : int64_t{kp} * kp;
