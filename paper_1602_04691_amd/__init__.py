@@ -13,10 +13,13 @@ import ctypes
 import os
 
 __all__ = [
-    "OriError", "lib", "Grid", "SolveOpts", "SolveInfo", "Context",
+    "OriError", "lib", "Grid", "SolveOpts", "SolveInfo", "Layout", "Context",
     "ori_setup", "ori_create", "ori_load", "ori_solve", "ori_matvec", "ori_destroy",
     "ori_adjoint", "ori_gradient", "OriSolve", "ori_batch_info",
-    "ori_workspace_bytes", "ori_default_opts", "ori_profile_enable", "ori_profile_read",
+    "ori_charges", "ori_scattered_field", "ori_far_field",
+    "ori_refraction_index", "ori_design_impedance", "ori_interpolation_difference",
+    "ori_get_layout", "ori_set_layout", "ori_tune", "ori_check_guards",
+    "ori_workspace_bytes", "ori_default_opts", "ori_profile_enable", "ori_profile_kinds", "ori_profile_read",
     "ori_last_error", "ori_version",
     "ORI_OK", "ORI_ERR_INVALID_ARG", "ORI_ERR_OUT_OF_MEMORY", "ORI_ERR_DEVICE",
     "ORI_ERR_BREAKDOWN", "ORI_ERR_NOT_CONVERGED", "ORI_ERR_UNSUPPORTED",

@@ -27,9 +27,11 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 12
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    # and the binding wraps each one
+    # and the binding wraps each one, and exports it
     for n in names:
         assert hasattr(ori, n), n
+        assert n in ori.__all__, n
+    assert all(hasattr(ori, n) for n in ori.__all__)
 
 
 def test_supported_lengths_match_header():
