@@ -459,7 +459,11 @@ def _autograd_function():
             ctx = ori_setup(n, k, h.detach().contiguous(), None if N is None else N.detach().contiguous(),
                             u0.detach().contiguous(), side=side)
             u = torch.empty(int(n) ** 3, dtype=torch.complex128, device=h.device)
-            ori_solve(ctx, u, **opts)
+            try:
+                ori_solve(ctx, u, **opts)
+            except BaseException:
+                ctx.close()  # the workspaces are released at once, not at garbage collection
+                raise
             fctx.ori = ctx
             fctx.opts = opts
             fctx.save_for_backward(u)
@@ -472,10 +476,12 @@ def _autograd_function():
             f = torch.conj(grad_u).resolve_conj().contiguous()
             g = torch.empty_like(u) if fctx.needs_input_grad[0] else None
             lam = torch.empty_like(u) if fctx.needs_input_grad[1] else None
-            if g is not None or lam is not None:
-                o = {k: v for k, v in fctx.opts.items() if k != "use_x0"}
-                ori_adjoint(ctx, u, f, g=g, lam=lam, **o)
-            ctx.close()
+            try:
+                if g is not None or lam is not None:
+                    o = {k: v for k, v in fctx.opts.items() if k != "use_x0"}
+                    ori_adjoint(ctx, u, f, g=g, lam=lam, **o)
+            finally:
+                ctx.close()
             return (None if g is None else torch.conj(g), None if lam is None else torch.conj(lam),
                     None, None, None, None, None)
 
@@ -493,12 +499,13 @@ def OriSolve(h, u0, n, k, N=None, side=1.0, **opts):
     return _ORI_SOLVE_FN.apply(h, u0, N, int(n), float(k), float(side), dict(opts))
 
 
-def solve_many(problems, **opts):
+def solve_many(problems, max_workers=4, **opts):
     """Independent problems of any sizes, each on its own context and stream,
     solved concurrently from a thread pool (the library call releases the
     GIL), with eager launches (no graph replay unless graph=True is passed).
-    problems: dicts with n, k, h, N, u0 (CUDA tensors).  Returns a list of
-    (u, info) in order."""
+    problems: dicts with n, k, h, N, u0 (CUDA tensors).  At most max_workers
+    contexts (each holding its own workspaces) exist at a time.  Returns a
+    list of (u, info) in order."""
     import concurrent.futures
     import torch
 
@@ -517,5 +524,5 @@ def solve_many(problems, **opts):
         return u, info
 
     torch.cuda.synchronize()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, len(problems))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(int(max_workers), len(problems)))) as ex:
         return list(ex.map(one, problems))
