@@ -136,8 +136,8 @@ def main():
     a = ap.parse_args()
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
-              "slab/RHS sharding is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); sharding the "
+              "right-hand sides or slabs of i1 over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -17,7 +17,7 @@ What is computed (plain definitions, Section 2 of the paper):
   i.e. A u = u0 with A = I + G0 diag(D), where G0 is G with a zero diagonal
   (the sum excludes p = q).
 
-Readings taken where the paper is silent (each listed in the design doc):
+Readings taken where the paper is silent:
 
 * The self term p = q is excluded and nothing replaces it.
 * The system is solved exactly as printed (minus sign in eq. 2.19).
