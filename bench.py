@@ -116,6 +116,137 @@ def cpu_baseline(case, budget_s, x):
     return rows, np.array(vals), dt, rate
 
 
+def next_workload(a):
+    """The extension workloads, one JSON line each:
+    batch   n = 64, k = 5, 32 incident directions on a Fibonacci sphere in
+            one context (one launch per pass over the whole block), mixed
+            precision to tol; value = right-hand-side products per second
+    uneven  four independent problems, n = 32, 48, 64, 96, solved side by
+            side (solve_many); value = problems per second
+    gradient  n = 128, k = 5: J = sum |u - t|^2 with t the solution at 1.2 h,
+            and dJ/dh by one adjoint solve (ori_gradient, complex128);
+            value = gradients per second
+    A step loads the problem and solves it (the gradient: forward + adjoint).
+    The roofline entry is the dominant pass of an untimed profiled step, its
+    algorithmic bytes scaled by the batch (the spectrum is read once per
+    launch).  No CPU baseline: the oracle's rate is that of the default
+    workload's operator."""
+    import numpy as np
+    import torch
+
+    import paper_1602_04691_amd as ori
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    gpu = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+    ctx = None
+    R = 1
+    if a.workload == "batch":
+        n, k, R = 64, 5.0, 32
+        case = workloads.make_case(n, k, seed=2)
+        u0s = np.stack([workloads.plane_wave(n, k, d) for d in workloads.fibonacci_directions(R)]).reshape(-1)
+        h, N, u0 = gpu(case["h"]), gpu(case["N"]), gpu(u0s)
+        ctx = ori.ori_create(n, nrhs=R)
+        u = torch.empty(R * n ** 3, dtype=torch.complex128, device=dev)
+        prec = ori.ORI_MIXED
+
+        def step():
+            ori.ori_load(ctx, k, h, N, u0)
+            return ori.ori_solve(ctx, u, tol=a.tol, precision=prec)[1]
+
+        unit, count = "rhs_matvecs/s", lambda info: R * info["matvecs"]
+        metric = "batched COCG: right-hand-side products/sec, n=64, 32 directions, mixed precision"
+        desc = {"workload": f"ori_red_batch_n{n}_k{k:g}_r{R}", "n": n, "k": k, "nrhs": R,
+                "u0": "plane waves, Fibonacci-sphere directions", "precision": "mixed", "tol": a.tol, "seed": 2}
+    elif a.workload == "uneven":
+        k = 5.0
+        probs = []
+        for j, nn in enumerate((32, 48, 64, 96)):
+            c = workloads.make_case(nn, k, seed=20 + j)
+            probs.append(dict(n=nn, k=k, h=gpu(c["h"]), N=gpu(c["N"]), u0=gpu(c["u0"])))
+        n = 96
+
+        def step():
+            res = ori.solve_many(probs, tol=a.tol, precision=ori.ORI_MIXED)
+            return {"matvecs": sum(i["matvecs"] for _, i in res), "solves": len(res)}
+
+        unit, count = "solves/s", lambda info: info["solves"]
+        metric = "uneven batch: problems solved/sec, n in {32,48,64,96}, mixed precision"
+        desc = {"workload": "ori_red_uneven_n32_48_64_96_k5", "n": [32, 48, 64, 96], "k": k,
+                "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23]}
+    elif a.workload == "gradient":
+        n, k = 128, 5.0
+        case = workloads.make_case(n, k, seed=3)
+        h, N, u0 = gpu(case["h"]), gpu(case["N"]), gpu(case["u0"])
+        ctx = ori.ori_create(n)
+        t = torch.empty(n ** 3, dtype=torch.complex128, device=dev)
+        ori.ori_load(ctx, k, 1.2 * h, N, u0)
+        ori.ori_solve(ctx, t, tol=1e-12)
+        u = torch.empty_like(t)
+        g = torch.empty_like(t)
+        prec = ori.ORI_FP64
+
+        def step():
+            ori.ori_load(ctx, k, h, N, u0)
+            _, _, info = ori.ori_gradient(ctx, t, u, g, tol=a.tol)
+            return info
+
+        unit, count = "gradients/s", lambda info: 1
+        metric = "adjoint gradient dJ/dh: gradients/sec, n=128, complex128"
+        desc = {"workload": f"ori_red_gradient_n{n}_k{k:g}", "n": n, "k": k,
+                "objective": "sum |u - t|^2, t = solution at 1.2 h", "precision": "fp64", "tol": a.tol, "seed": 3}
+    else:
+        sys.exit(f"unknown --workload {a.workload!r}")
+    log(f"[bench] workload {desc['workload']} steps={a.steps} warmup={a.warmup}")
+
+    for _ in range(a.warmup):
+        step()
+    roofline, kernel_ms = None, None
+    if ctx is not None:
+        ori.ori_profile_kinds(ctx, None)
+        ori.ori_profile_enable(ctx, True)
+        step()
+        prof = ori.ori_profile_read(ctx)
+        ori.ori_profile_enable(ctx, False)
+        kernel_ms = {kk: round(v[0], 5) for kk, v in prof.items()}
+        passes = [kk for kk in prof if kk.split(".")[0] in ("f1", "f2", "zpass", "i2", "i1", "update")]
+        dom = max(passes, key=lambda kk: prof[kk][0] * prof[kk][1])
+        kind, tag = dom.split(".")
+        elem = 16 if tag == "c128" else 8
+        pb = pass_bytes(n, elem)
+        kp3 = (n + 1) ** 3
+        byts = R * (pb[kind] - kp3 * elem) + kp3 * elem if kind == "zpass" else R * pb[kind]
+        achieved = byts / (prof[dom][0] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(prof[dom][0], 5),
+                    "launches": prof[dom][1], "measured": "untimed profiled step"}
+        log(f"[bench] dominant {dom}: {prof[dom][0]:.4f} ms, {achieved:.0f} GB/s")
+
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = sum(count(i) for i in infos) / wall
+    log(f"[bench] {value:.3f} {unit}, {wall / a.steps * 1e3:.2f} ms/step, last {infos[-1]}")
+    if ctx is not None:
+        ctx.close()
+    out = {
+        "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(wall / a.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128" if a.workload == "gradient" else "c64+f64",
+        "data": "synthetic", "config": desc, "roofline": roofline, "cpu_baseline": None,
+        "last_step": infos[-1], "kernel_ms_untimed_step": kernel_ms,
+        "kernel_sources_sha": kernel_sources_sha(),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +262,9 @@ def main():
                     help="pass layout LG,NP,PF,ZNP[/LG,NP,PF,ZNP] (complex128 / complex64 passes: i1 row block, "
                          "narrow strided tiles, Z prefetch, narrow Z tiles); the default is what ori_tune picks "
                          "at n = 256 on MI355X; 'auto' tunes before timing, 'default' keeps the library's")
+    ap.add_argument("--workload", default="solve", choices=("solve", "batch", "uneven", "gradient"),
+                    help="solve: the n = 256 (or --n) load + solve (the default line); batch, uneven, gradient: "
+                         "the extension workloads (see next_workload)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain 1-to-1 copy of this many MiB (counter calibration)")
     a = ap.parse_args()
@@ -139,6 +273,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); sharding the "
               "right-hand sides or slabs of i1 over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
+    if a.workload != "solve":
+        next_workload(a)
+        return
 
     import numpy as np
     import torch

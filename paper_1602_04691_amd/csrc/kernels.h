@@ -117,7 +117,8 @@ struct ZArgs {
   int32_t e_lg, np_sel;  // np_sel: 0 wide tiles, 1 narrow tiles
   int64_t e_hi, e_lo, o_stride;
   int64_t nrhs, batch_stride;
-  int32_t prefetch, pad2;  // 1: load the next tile while transforming the current one
+  int32_t prefetch;    // 1: load the next tile while transforming the current one
+  int32_t rhs_slices;  // workgroups per (m2, k3 tile), each taking a contiguous share of the right-hand sides
   const void* khat;     // spectrum (T), octant [n+1][n+1][n+1]
   int64_t kp;
   const void* tw;

@@ -49,6 +49,8 @@ namespace {
 
 constexpr double kBreakdownEps = 1e-13;
 constexpr int64_t kMaxRhs = 1024;
+// Z-pass workgroups below which a batch is split over its right-hand sides
+constexpr int64_t kZMinWorkgroups = 4096;
 
 enum ProfKind : int {
   K_F1,
@@ -402,7 +404,13 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   StridedArgs f2{A, B, R * n, L, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, ns, tw};
   ORI_TRY(launch(c, K_F2, fprec, [&] { return c->K->strided(fprec, f2, c->stream); }));
 
-  ZArgs z{B, n, lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, 0, kh, n + 1, tw};
+  // Small grids (a batch at small n) are split over the right-hand sides,
+  // so that the pass has enough workgroups to fill the chip; no slice is
+  // left empty.
+  const int64_t zbase = c->K->zpass_blocks(fprec, kn.z_np, n);
+  int64_t rs = std::min<int64_t>(R, (kZMinWorkgroups + zbase - 1) / zbase);
+  if (rs > 1) rs = (R + (R + rs - 1) / rs - 1) / ((R + rs - 1) / rs);
+  ZArgs z{B, n, lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, static_cast<int32_t>(rs), kh, n + 1, tw};
   ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, z, c->stream); }));
 
   StridedArgs i2{B, A, R * n, L, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};

@@ -296,15 +296,24 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
   __shared__ cx<T> lds[NP * L];
   const int tid = threadIdx.x;
   const int t = tid % NP, bt = tid / NP;
-  const int64_t w = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t m2 = w / CT;
+  // workgroup w takes right-hand-side slice w % RS of the tile w / RS, so the
+  // slices of a tile, which read the same spectrum values, run side by side
+  const uint32_t RS = static_cast<uint32_t>(a.rhs_slices);
+  const uint32_t w = static_cast<uint32_t>(xcd_order(blockIdx.x, gridDim.x));
+  const uint32_t wt = RS == 1 ? w : w / RS;
+  const uint32_t slice = w - wt * RS;
+  const int64_t m2 = wt / CT;
   // tiles of a row in the order 0, CT-1, 1, CT-2, ...: a tile and its mirror
   // (which reads the same spectrum values) run back to back
-  const int64_t j = w % CT;
+  const int64_t j = wt % CT;
   const int64_t tile = (j & 1) ? CT - 1 - (j >> 1) : (j >> 1);
   const int64_t k3 = tile * NP + t;
   const bool act = k3 < L;
   const int64_t m3 = k3 <= L - k3 ? k3 : L - k3;  // the octant holds k3 and its mirror
+  const uint32_t nrhs = static_cast<uint32_t>(a.nrhs);
+  const uint32_t rper = RS == 1 ? nrhs : (nrhs + RS - 1) / RS;
+  const int64_t r_lo = static_cast<int64_t>(slice) * rper;
+  const int64_t r_hi = r_lo + rper < a.nrhs ? r_lo + rper : a.nrhs;
   const cx<T>* __restrict__ kh = static_cast<const cx<T>*>(a.khat);
   // The twiddle table is staged in LDS: read from global memory inside a
   // stage, a twiddle would wait behind every tile load still in flight
@@ -329,16 +338,16 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
     }
   }
   const int64_t nvar = (m2 != 0 && m2 != n) ? 2 : 1;  // uniform over the workgroup
-  const int64_t ntile = nvar * a.nrhs;
+  const int64_t ntile = r_lo < r_hi ? nvar * (r_hi - r_lo) : 0;
   const int64_t emask = (int64_t{1} << a.e_lg) - 1;
-  // tiles in the order (k2 = m2, rhs 0..R-1), (k2 = L - m2, rhs 0..R-1),
-  // walked with counters (no division by R per tile)
-  int64_t nx_rhs = 0, nx_var = 0;
+  // tiles in the order (k2 = m2, rhs r_lo..r_hi-1), (k2 = L - m2, the same
+  // right-hand sides), walked with counters (no division per tile)
+  int64_t nx_rhs = r_lo, nx_var = 0;
   auto next_base = [&]() -> int64_t {
     const int64_t k2 = nx_var ? L - m2 : m2;
     const int64_t base = nx_rhs * a.batch_stride + k2 * a.o_stride + k3;
-    if (++nx_rhs == a.nrhs) {
-      nx_rhs = 0;
+    if (++nx_rhs == r_hi) {
+      nx_rhs = r_lo;
       ++nx_var;
     }
     return base;
@@ -365,6 +374,7 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
     });
     __syncthreads();
   };
+  if (ntile == 0) return;  // an empty right-hand-side slice (uniform over the workgroup)
   if constexpr (PF) {
     // two register sets in turn: the loads of tile it + 1 are in flight while
     // tile it is transformed
@@ -556,7 +566,9 @@ int64_t zpass_blocks(int fprec, int np_sel, int64_t n) {
 
 template <typename T, int NP>
 hipError_t zpass_t(const ZArgs& a, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>((a.n + 1) * ((2 * a.n + NP - 1) / NP))), block(NP * z_tpp<T>());
+  if (a.rhs_slices < 1 || a.rhs_slices > a.nrhs) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((a.n + 1) * ((2 * a.n + NP - 1) / NP) * a.rhs_slices)),
+      block(NP * z_tpp<T>());
   if (a.prefetch)
     hipLaunchKernelGGL((k_zpass<T, NP, true>), grid, block, 0, st, a);
   else
