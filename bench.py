@@ -76,6 +76,28 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
+VALU_LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9  # MI355X: CUs x SIMDs x lanes x clock
+
+
+def read_profile_value(name, key):
+    """A number from a committed profiles/ summary taken on the current kernel
+    sources (its source_sha line), else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != kernel_sources_sha():
+        return None
+    try:
+        return float(kv[key])
+    except (KeyError, ValueError):
+        return None
+
+
 def read_traffic(kernel, n, layout):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources with the same pass layout; else
@@ -126,7 +148,11 @@ def next_workload(a):
     gradient  n = 128, k = 5: J = sum |u - t|^2 with t the solution at 1.2 h,
             and dJ/dh by one adjoint solve (ori_gradient, complex128);
             value = gradients per second
-    A step loads the problem and solves it (the gradient: forward + adjoint).
+    field   n = 64, k = 5: the scattered field at 4096 points and the far
+            field in 4096 directions by direct FP64 sums over the cells of a
+            solved problem; value = point-cell pairs per second
+    A step loads the problem and solves it (the gradient: forward + adjoint;
+    the field: the two sums only).
     The roofline entry is the dominant pass of an untimed profiled step, its
     algorithmic bytes scaled by the batch (the spectrum is read once per
     launch).  No CPU baseline: the oracle's rate is that of the default
@@ -197,6 +223,30 @@ def next_workload(a):
         metric = "adjoint gradient dJ/dh: gradients/sec, n=128, complex128"
         desc = {"workload": f"ori_red_gradient_n{n}_k{k:g}", "n": n, "k": k,
                 "objective": "sum |u - t|^2, t = solution at 1.2 h", "precision": "fp64", "tol": a.tol, "seed": 3}
+    elif a.workload == "field":
+        n, k, M = 64, 5.0, 4096
+        case = workloads.make_case(n, k, seed=2)
+        h, N, u0 = gpu(case["h"]), gpu(case["N"]), gpu(case["u0"])
+        ctx = ori.ori_create(n)
+        ori.ori_load(ctx, k, h, N, u0)
+        u = torch.empty(n ** 3, dtype=torch.complex128, device=dev)
+        ori.ori_solve(ctx, u, tol=a.tol)
+        # M points on the sphere of radius 2 about the cube's centre, and M
+        # far-field directions (Fibonacci sphere)
+        dirs = gpu(workloads.fibonacci_directions(M))
+        pts = (0.5 + 2.0 * dirs).contiguous()
+        v = torch.empty(M, dtype=torch.complex128, device=dev)
+        A = torch.empty(M, dtype=torch.complex128, device=dev)
+
+        def step():
+            ori.ori_scattered_field(ctx, u, pts, v)
+            ori.ori_far_field(ctx, u, dirs, A)
+            return {"pairs": 2 * M * n ** 3}
+
+        unit, count = "point_cell_pairs/s", lambda info: info["pairs"]
+        metric = "scattered and far field by direct sums: point-cell pairs/sec, n=64, 4096 points + 4096 directions"
+        desc = {"workload": f"ori_field_n{n}_k{k:g}_m{M}", "n": n, "k": k, "points": M, "directions": M,
+                "points_at": "radius 2 about the cube centre", "precision": "fp64", "seed": 2}
     else:
         sys.exit(f"unknown --workload {a.workload!r}")
     log(f"[bench] workload {desc['workload']} steps={a.steps} warmup={a.warmup}")
@@ -212,6 +262,7 @@ def next_workload(a):
         ori.ori_profile_enable(ctx, False)
         kernel_ms = {kk: round(v[0], 5) for kk, v in prof.items()}
         passes = [kk for kk in prof if kk.split(".")[0] in ("f1", "f2", "zpass", "i2", "i1", "update")]
+    if ctx is not None and passes:
         dom = max(passes, key=lambda kk: prof[kk][0] * prof[kk][1])
         kind, tag = dom.split(".")
         elem = 16 if tag == "c128" else 8
@@ -233,13 +284,25 @@ def next_workload(a):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     value = sum(count(i) for i in infos) / wall
+    if a.workload == "field":
+        # direct sums: bound by VALU issue.  peak = the chip's VALU lane-issue
+        # rate (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz) / the VALU instructions
+        # per point-cell pair counted by rocprofv3 (committed summary, taken on
+        # the current kernel sources), or null without one
+        ipp = read_profile_value(f"field_n{n}_valu.txt", "valu_insts_per_pair")
+        peak = VALU_LANE_ISSUE_PER_S / ipp if ipp else None
+        roofline = {"bound": "alu", "kernel": "k_field_partial", "achieved": round(value, 1), "peak": peak,
+                    "unit": "point_cell_pairs/s", "frac": round(value / peak, 4) if peak else None,
+                    "traffic": None, "valu_insts_per_pair": ipp,
+                    "peak_model": "VALU lane-issue rate / VALU instructions per pair"}
     log(f"[bench] {value:.3f} {unit}, {wall / a.steps * 1e3:.2f} ms/step, last {infos[-1]}")
     if ctx is not None:
         ctx.close()
     out = {
         "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(wall / a.steps * 1e3, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c128" if a.workload == "gradient" else "c64+f64",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128" if a.workload in ("gradient", "field") else "c64+f64",
         "data": "synthetic", "config": desc, "roofline": roofline, "cpu_baseline": None,
         "last_step": infos[-1], "kernel_ms_untimed_step": kernel_ms,
         "kernel_sources_sha": kernel_sources_sha(),
@@ -262,7 +325,7 @@ def main():
                     help="pass layout LG,NP,PF,ZNP[/LG,NP,PF,ZNP] (complex128 / complex64 passes: i1 row block, "
                          "narrow strided tiles, Z prefetch, narrow Z tiles); the default is what ori_tune picks "
                          "at n = 256 on MI355X; 'auto' tunes before timing, 'default' keeps the library's")
-    ap.add_argument("--workload", default="solve", choices=("solve", "batch", "uneven", "gradient"),
+    ap.add_argument("--workload", default="solve", choices=("solve", "batch", "uneven", "gradient", "field"),
                     help="solve: the n = 256 (or --n) load + solve (the default line); batch, uneven, gradient: "
                          "the extension workloads (see next_workload)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

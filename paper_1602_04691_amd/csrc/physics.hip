@@ -46,10 +46,20 @@ __device__ __forceinline__ cxd block_sum_cx(cxd v) {
   return s;
 }
 
+// floor(v / n) for 0 <= v < 2^31 and n <= 1024 without an integer division:
+// (v + 1/2) / n lies at least 1/(2n) from an integer, and its FP64 product
+// with the rounded reciprocal of n is off by less than 2^-21, so truncation
+// gives the quotient exactly
+__device__ __forceinline__ int32_t quot(int32_t v, double inv_n) {
+  return static_cast<int32_t>((static_cast<double>(v) + 0.5) * inv_n);
+}
+
 // cell point of p = (i1 n + i2) n + i3: origin + side (i + offset) / n
-__device__ __forceinline__ void cell_point(const FieldArgs& a, int64_t p, double (&x)[3]) {
-  const int64_t i3 = p % a.n, r = p / a.n, i2 = r % a.n, i1 = r / a.n;
-  const int64_t i[3] = {i1, i2, i3};
+__device__ __forceinline__ void cell_point(const FieldArgs& a, int64_t p, double inv_n, double (&x)[3]) {
+  const int32_t n = static_cast<int32_t>(a.n), pp = static_cast<int32_t>(p);
+  const int32_t r = quot(pp, inv_n), i3 = pp - r * n;
+  const int32_t i1 = quot(r, inv_n), i2 = r - i1 * n;
+  const int32_t i[3] = {i1, i2, i3};
 #pragma unroll
   for (int d = 0; d < 3; ++d) x[d] = a.origin[d] + a.side * (static_cast<double>(i[d]) + a.offset) / a.dn;
 }
@@ -62,10 +72,11 @@ __global__ void __launch_bounds__(kFieldThreads) k_field_partial(FieldArgs a) {
   const double y0 = y[0], y1 = y[1], y2 = y[2];
   const cxd* __restrict__ u = a.u + rhs * a.P;
   const int64_t p0 = chunk * a.chunk, p1 = p0 + a.chunk < a.P ? p0 + a.chunk : a.P;
+  const double inv_n = 1.0 / a.dn;
   cxd acc{0.0, 0.0};
   for (int64_t p = p0 + threadIdx.x; p < p1; p += kFieldThreads) {
     double x[3];
-    cell_point(a, p, x);
+    cell_point(a, p, inv_n, x);
     const cxd q = scale(a.D[p] * u[p], -1.0);  // Q_p
     double s, c;
     if (FAR) {
