@@ -161,6 +161,9 @@ struct ori_ctx_s {
   // create, after every kernel launch
   std::vector<unsigned char*> guards;
   bool check_guards = false;
+  // ORI_TRACE=1 in the environment at create: the residual of every
+  // right-hand side on stderr after every check of a solve
+  bool trace = false;
 
   // captured COCG iteration blocks, one per vector precision
   struct IterGraph {
@@ -607,9 +610,22 @@ ori_status run_cocg(ori_ctx c, int prec, void* x, void* r, void* p, void* q, con
   return ORI_OK;
 }
 
+// one line per right-hand side: its iterations so far, ||r|| and ||r|| / ||r0||
+// (r0 the residual this COCG run started from)
+void trace_cocg(ori_ctx c, int prec) {
+  if (!c->trace) return;
+  for (int64_t i = 0; i < c->nrhs; ++i) {
+    const ScalarBlock& s = c->sc_host[i];
+    std::fprintf(stderr, "[ori] cocg %s rhs %lld iter %d res %.6e rel %.6e%s\n", prec == PREC_F32 ? "c64" : "c128",
+                 (long long)i, s.iters, std::sqrt(s.rr), s.rr0 > 0.0 ? std::sqrt(s.rr / s.rr0) : 0.0,
+                 (s.flags & FLAG_DONE) ? " done" : "");
+  }
+}
+
 ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
                           int check_every, bool use_graph, CocgOut* out) {
   ORI_TRY(sync_scalars(c));
+  trace_cocg(c, prec);
   if (all_done(c)) {
     out->all_done = true;
     return ORI_OK;
@@ -632,6 +648,7 @@ ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* 
     out->iters += blk;
     out->matvecs += blk;
     ORI_TRY(sync_scalars(c));
+    trace_cocg(c, prec);
     if (all_done(c)) {
       out->all_done = true;
       return ORI_OK;
@@ -819,6 +836,9 @@ ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const s
     for (int64_t i = 0; i < R; ++i) {
       const ScalarBlock& s = c->sc_host[i];
       oc->info[i].rel_res_recursive = bb[i] > 0 ? std::sqrt(s.rr / bb[i]) : 0.0;
+      if (c->trace)
+        std::fprintf(stderr, "[ori] refine %d rhs %lld fp64 rel %.6e\n", outer, (long long)i,
+                     oc->info[i].rel_res_recursive);
       if (done[i] == 0 && (s.rr <= target[i] || s.rr == 0.0)) done[i] = 1;
       if (done[i] == 0 && outer == 0 && (s.flags & FLAG_BREAKDOWN_RHO)) done[i] = 2;
       c->outer_m_host[i] = done[i] ? 0.0 : std::sqrt(s.rr);
@@ -1071,6 +1091,7 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
   c->bnorm2.assign(nrhs, 0.0);
   choose_layout(c);
   if (const char* e = std::getenv("ORI_CHECK_GUARDS")) c->check_guards = std::atoi(e) != 0;
+  if (const char* e = std::getenv("ORI_TRACE")) c->trace = std::atoi(e) != 0;
   c->stream = static_cast<hipStream_t>(stream);
   auto fail = [&](ori_status st) {
     g_last_error = c->err;
