@@ -54,17 +54,14 @@ __device__ __forceinline__ int32_t quot(int32_t v, double inv_n) {
   return static_cast<int32_t>((static_cast<double>(v) + 0.5) * inv_n);
 }
 
-// cell point of p = (i1 n + i2) n + i3: origin + side (i + offset) / n
-__device__ __forceinline__ void cell_point(const FieldArgs& a, int64_t p, double inv_n, double (&x)[3]) {
-  const int32_t n = static_cast<int32_t>(a.n), pp = static_cast<int32_t>(p);
-  const int32_t r = quot(pp, inv_n), i3 = pp - r * n;
-  const int32_t i1 = quot(r, inv_n), i2 = r - i1 * n;
-  const int32_t i[3] = {i1, i2, i3};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) x[d] = a.origin[d] + a.side * (static_cast<double>(i[d]) + a.offset) / a.dn;
-}
+constexpr int kFieldMaxN = 512;
 
-// grid (chunks, points, right-hand sides): partial sum over one chunk of cells
+// grid (chunks, points, right-hand sides): partial sum over one chunk of cells.
+// The cell points lie on a grid, so a workgroup first tabulates the
+// coordinate origin + side (i + offset) / n of every index along each axis
+// and, for the far field, the phase e^{-ik beta_d x_d} of each (the phase of
+// a cell is the product of its three axis phases): no division and no sine
+// per cell.
 template <bool FAR>
 __global__ void __launch_bounds__(kFieldThreads) k_field_partial(FieldArgs a) {
   const int64_t chunk = blockIdx.x, m = blockIdx.y, rhs = blockIdx.z;
@@ -72,23 +69,39 @@ __global__ void __launch_bounds__(kFieldThreads) k_field_partial(FieldArgs a) {
   const double y0 = y[0], y1 = y[1], y2 = y[2];
   const cxd* __restrict__ u = a.u + rhs * a.P;
   const int64_t p0 = chunk * a.chunk, p1 = p0 + a.chunk < a.P ? p0 + a.chunk : a.P;
+  const int n = static_cast<int>(a.n);
+  __shared__ double xs[3 * kFieldMaxN];
+  __shared__ cxd ph[FAR ? 3 * kFieldMaxN : 1];
+  for (int t = threadIdx.x; t < 3 * n; t += kFieldThreads) {
+    const int d = t / n, i = t - d * n;
+    const double x = a.origin[d] + a.side * (static_cast<double>(i) + a.offset) / a.dn;
+    xs[t] = x;
+    if constexpr (FAR) {
+      const double yd = d == 0 ? y0 : d == 1 ? y1 : y2;
+      double s, c;
+      sincos(-a.k * (yd * x), &s, &c);
+      ph[t] = cxd{c, s};
+    }
+  }
+  __syncthreads();
   const double inv_n = 1.0 / a.dn;
   cxd acc{0.0, 0.0};
   for (int64_t p = p0 + threadIdx.x; p < p1; p += kFieldThreads) {
-    double x[3];
-    cell_point(a, p, inv_n, x);
+    // p = (i1 n + i2) n + i3
+    const int32_t pp = static_cast<int32_t>(p);
+    const int32_t r = quot(pp, inv_n), i3 = pp - r * n;
+    const int32_t i1 = quot(r, inv_n), i2 = r - i1 * n;
     const cxd q = scale(a.D[p] * u[p], -1.0);  // Q_p
-    double s, c;
     if (FAR) {
       // e^{-ik beta.x_p} Q_p
-      sincos(-a.k * (y0 * x[0] + y1 * x[1] + y2 * x[2]), &s, &c);
-      acc = acc + cxd{c, s} * q;
+      acc = acc + (ph[i1] * ph[n + i2]) * ph[2 * n + i3] * q;
     } else {
-      const double d0 = y0 - x[0], d1 = y1 - x[1], d2 = y2 - x[2];
-      const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      if (r > 0.0) {
-        sincos(a.k * r, &s, &c);
-        const double g = 1.0 / (kFourPi * r);  // G = e^{ikr} / (4 pi r)
+      const double d0 = y0 - xs[i1], d1 = y1 - xs[n + i2], d2 = y2 - xs[2 * n + i3];
+      const double r2 = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      if (r2 > 0.0) {
+        double s, c;
+        sincos(a.k * r2, &s, &c);
+        const double g = 1.0 / (kFourPi * r2);  // G = e^{ikr} / (4 pi r)
         acc = acc + cxd{c * g, s * g} * q;
       }
     }
@@ -218,6 +231,7 @@ __global__ void __launch_bounds__(256) k_max(const double* __restrict__ v, int64
 }  // namespace
 
 hipError_t launch_field(const FieldArgs& a, bool far, hipStream_t st) {
+  if (a.n < 1 || a.n > kFieldMaxN || a.n * a.n * a.n != a.P) return hipErrorInvalidValue;  // the axis tables
   const dim3 grid(static_cast<unsigned>(a.nchunk), static_cast<unsigned>(a.mb), static_cast<unsigned>(a.nrhs));
   if (far)
     hipLaunchKernelGGL((k_field_partial<true>), grid, dim3(kFieldThreads), 0, st, a);
