@@ -144,7 +144,8 @@ def next_workload(a):
             one context (one launch per pass over the whole block), mixed
             precision to tol; value = right-hand-side products per second
     uneven  four independent problems, n = 32, 48, 64, 96, solved side by
-            side (solve_many); value = problems per second
+            side (solve_many, contexts kept between steps); value = problems
+            per second
     gradient  n = 128, k = 5: J = sum |u - t|^2 with t the solution at 1.2 h,
             and dJ/dh by one adjoint solve (ori_gradient, complex128);
             value = gradients per second
@@ -195,13 +196,15 @@ def next_workload(a):
         n = 96
 
         def step():
-            res = ori.solve_many(probs, tol=a.tol, precision=ori.ORI_MIXED)
+            # contexts (workspaces and streams) are kept between steps, as the
+            # default workload keeps its one; the warmup step creates them
+            res = ori.solve_many(probs, tol=a.tol, precision=ori.ORI_MIXED, reuse_contexts=True)
             return {"matvecs": sum(i["matvecs"] for _, i in res), "solves": len(res)}
 
         unit, count = "solves/s", lambda info: info["solves"]
         metric = "uneven batch: problems solved/sec, n in {32,48,64,96}, mixed precision"
         desc = {"workload": "ori_red_uneven_n32_48_64_96_k5", "n": [32, 48, 64, 96], "k": k,
-                "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23]}
+                "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23], "contexts": "kept between steps"}
     elif a.workload == "gradient":
         n, k = 128, 5.0
         case = workloads.make_case(n, k, seed=3)
@@ -298,6 +301,7 @@ def next_workload(a):
     log(f"[bench] {value:.3f} {unit}, {wall / a.steps * 1e3:.2f} ms/step, last {infos[-1]}")
     if ctx is not None:
         ctx.close()
+    ori.release_contexts()
     out = {
         "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(wall / a.steps * 1e3, 4), "higher_is_better": True,

@@ -24,7 +24,7 @@ __all__ = [
     "ORI_OK", "ORI_ERR_INVALID_ARG", "ORI_ERR_OUT_OF_MEMORY", "ORI_ERR_DEVICE",
     "ORI_ERR_BREAKDOWN", "ORI_ERR_NOT_CONVERGED", "ORI_ERR_UNSUPPORTED",
     "ORI_FP64", "ORI_MIXED", "ORI_OP_SYSTEM", "ORI_OP_SYMMETRIC", "ORI_OP_GREEN",
-    "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve", "solve_many",
+    "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve", "solve_many", "release_contexts",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libori.so")
@@ -499,13 +499,32 @@ def OriSolve(h, u0, n, k, N=None, side=1.0, **opts):
     return _ORI_SOLVE_FN.apply(h, u0, N, int(n), float(k), float(side), dict(opts))
 
 
-def solve_many(problems, max_workers=4, **opts):
+_CTX_POOL = {}  # (device, n, side) -> idle contexts kept by solve_many(reuse_contexts=True)
+_CTX_POOL_LOCK = __import__("threading").Lock()
+
+
+def release_contexts():
+    """Destroy the idle contexts that solve_many(reuse_contexts=True) keeps."""
+    with _CTX_POOL_LOCK:
+        pooled = [c for lst in _CTX_POOL.values() for c in lst]
+        _CTX_POOL.clear()
+    for c in pooled:
+        c.close()
+
+
+__import__("atexit").register(release_contexts)  # while the HIP runtime is still up
+
+
+def solve_many(problems, max_workers=4, reuse_contexts=False, **opts):
     """Independent problems of any sizes, each on its own context and stream,
     solved concurrently from a thread pool (the library call releases the
     GIL), with eager launches (no graph replay unless graph=True is passed).
     problems: dicts with n, k, h, N, u0 (CUDA tensors).  At most max_workers
-    contexts (each holding its own workspaces) exist at a time.  Returns a
-    list of (u, info) in order."""
+    contexts (each holding its own workspaces) are in use at a time.  With
+    reuse_contexts, a context is kept after its solve (workspaces, stream)
+    and loaded with the next problem of the same grid instead of being
+    created again; release_contexts() frees the kept ones.  Returns a list of
+    (u, info) in order."""
     import concurrent.futures
     import torch
 
@@ -515,12 +534,30 @@ def solve_many(problems, max_workers=4, **opts):
     opts.setdefault("graph", False)
 
     def one(p):
-        s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            with ori_setup(p["n"], p["k"], p["h"], p.get("N"), p["u0"], side=p.get("side", 1.0), stream=s) as ctx:
-                u = torch.empty(int(p["n"]) ** 3, dtype=torch.complex128, device=p["h"].device)
+        n, side = int(p["n"]), float(p.get("side", 1.0))
+        key = (p["h"].device.index, n, side)
+        ctx = None
+        if reuse_contexts:
+            with _CTX_POOL_LOCK:
+                idle = _CTX_POOL.get(key)
+                ctx = idle.pop() if idle else None
+        if ctx is None:
+            ctx = ori_create(n, side=side, stream=torch.cuda.Stream(device=p["h"].device))
+        try:
+            s = ctx.stream
+            with torch.cuda.stream(s):
+                ori_load(ctx, p["k"], p["h"], p.get("N"), p["u0"])
+                u = torch.empty(n ** 3, dtype=torch.complex128, device=p["h"].device)
                 _, info = ori_solve(ctx, u, **opts)
-        s.synchronize()
+            s.synchronize()
+        except BaseException:
+            ctx.close()
+            raise
+        if reuse_contexts:
+            with _CTX_POOL_LOCK:
+                _CTX_POOL.setdefault(key, []).append(ctx)
+        else:
+            ctx.close()
         return u, info
 
     torch.cuda.synchronize()

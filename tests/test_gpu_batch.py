@@ -125,3 +125,25 @@ def test_uneven_batch_of_independent_problems():
         u_seq, info_seq = ori.solve(p["n"], p["k"], p["h"], p["N"], p["u0"], tol=1e-8, precision=ori.ORI_MIXED)
         assert torch.equal(u, u_seq), p["n"]
         assert info["rel_res_true"] < 1e-7
+
+
+def test_solve_many_reuses_contexts_bitwise():
+    # kept contexts are loaded with the next problem of their grid: the
+    # results equal those of fresh contexts bit for bit, on repeated calls
+    say("[uneven, reused contexts] n in {32, 48}")
+    probs = []
+    for j, n in enumerate((32, 48, 32)):
+        c = workloads.make_case(n, 5.0, seed=30 + j)
+        probs.append(dict(n=n, k=5.0, h=gpu(c["h"]), N=gpu(c["N"]), u0=gpu(c["u0"])))
+    fresh = ori.solve_many(probs, tol=1e-9)
+    try:
+        for _ in range(2):
+            kept = ori.solve_many(probs, tol=1e-9, reuse_contexts=True)
+            for (u, info), (uf, _) in zip(kept, fresh):
+                assert torch.equal(u, uf)
+                assert info["rel_res_true"] < 1e-8
+        assert sum(len(v) for v in ori._CTX_POOL.values()) >= 2
+    finally:
+        ori.release_contexts()
+    assert not ori._CTX_POOL
+
