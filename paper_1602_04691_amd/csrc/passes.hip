@@ -245,7 +245,8 @@ __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
 // A workgroup takes the octant row m2 and a tile of NP consecutive k3: it
 // loads its K values once into registers (the shape of the last forward
 // stage, so element e = b + j L/R of the transform meets K(min(e, L-e), m2,
-// k3) in place) and runs the tiles (k2 = m2 | L - m2) x (right-hand sides)
+// k3) in place) and runs the tiles (k2 = m2 | L - m2) x (the right-hand
+// sides of its slice: small grids split a batch over several workgroups)
 // one after the other (with PF, the loads of the next tile are issued before
 // the current one is transformed).  The spectrum is read from its octant: the
 // tiles k3 and L - k3 of a row m2 need the same values; the workgroups of a

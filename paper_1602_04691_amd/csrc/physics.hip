@@ -97,11 +97,13 @@ __global__ void __launch_bounds__(kFieldThreads) k_field_partial(FieldArgs a) {
       acc = acc + (ph[i1] * ph[n + i2]) * ph[2 * n + i3] * q;
     } else {
       const double d0 = y0 - xs[i1], d1 = y1 - xs[n + i2], d2 = y2 - xs[2 * n + i3];
-      const double r2 = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      if (r2 > 0.0) {
+      const double rsq = d0 * d0 + d1 * d1 + d2 * d2;
+      if (rsq > 0.0) {
+        // r and 1 / (4 pi r) from one reciprocal square root
+        const double ir = rsqrt(rsq), r = rsq * ir;
         double s, c;
-        sincos(a.k * r2, &s, &c);
-        const double g = 1.0 / (kFourPi * r2);  // G = e^{ikr} / (4 pi r)
+        sincos(a.k * r, &s, &c);
+        const double g = ir * (1.0 / kFourPi);  // G = e^{ikr} / (4 pi r)
         acc = acc + cxd{c * g, s * g} * q;
       }
     }
