@@ -60,6 +60,30 @@ def test_batch_equals_single_solves_bitwise():
 
 
 @pytest.mark.parametrize("prec", [ori.ORI_FP64, ori.ORI_MIXED])
+def test_batch_split_over_uneven_slices_bitwise(prec):
+    # n = 64 with 11 right-hand sides: the Z grid of one product (520
+    # workgroups in complex128, 1040 in complex64) is split over slices of
+    # the batch (6 slices of 2, 2, 2, 2, 2, 1 in complex128), each a
+    # workgroup per tile; every product still equals the single product bit
+    # for bit
+    n, k, R = 64, 5.0, 11
+    say(f"[uneven slices] n=64, {R} rhs, precision {prec}")
+    case = workloads.make_case(n, k, seed=6)
+    U0 = fields(n, k, workloads.fibonacci_directions(R))
+    hg, Ng = gpu(case["h"]), gpu(case["N"])
+    xs = gpu((U0 * (1.0 + 0.5j)).reshape(-1))
+    with ori.ori_create(n, nrhs=R) as ctx:
+        ori.ori_load(ctx, k, hg, Ng, gpu(U0.reshape(-1)))
+        yb = torch.empty_like(xs)
+        ori.ori_matvec(ctx, xs, yb, ori.ORI_OP_SYMMETRIC, prec)
+    with ori.ori_setup(n, k, hg, Ng, gpu(U0[0])) as c1:
+        for i in range(R):
+            y1 = torch.empty(n ** 3, dtype=torch.complex128, device="cuda")
+            ori.ori_matvec(c1, xs[i * n ** 3:(i + 1) * n ** 3].contiguous(), y1, ori.ORI_OP_SYMMETRIC, prec)
+            assert torch.equal(yb[i * n ** 3:(i + 1) * n ** 3], y1), i
+
+
+@pytest.mark.parametrize("prec", [ori.ORI_FP64, ori.ORI_MIXED])
 def test_batch_vs_lu(prec):
     n, k, R = 8, 4.0, 5
     say(f"[batch vs LU] prec={prec}")
