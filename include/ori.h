@@ -34,9 +34,12 @@
  *    ori_last_error(ctx) gives a text.  After ORI_ERR_DEVICE the context is
  *    poisoned: only ori_destroy is valid.
  *  - A context is not thread safe; distinct contexts are independent.
- *  - Supported n: 2n must factor as 2^a 3^b 5^c with 2n in
- *    {2,4,6,8,10,12,16,20,24,32,40,48,64,80,96,128,192,256,384,512,1024};
- *    any other n gives ORI_ERR_UNSUPPORTED.
+ *  - Supported n: every 1 <= n <= 512.  Each axis is padded to the
+ *    shortest planned FFT length L >= 2n - 1 from
+ *    {2,4,6,8,10,12,16,20,24,32,40,48,64,80,96,128,192,256,384,512,1024}
+ *    (the cyclic convolution of length L then holds every offset in
+ *    (-n, n): Section 3's zero padding); L = 2n whenever 2n is in the list
+ *    (n = 7 uses 16, n = 100 uses 256).  n > 512 gives ORI_ERR_UNSUPPORTED.
  */
 #ifndef ORI_H
 #define ORI_H
@@ -96,10 +99,12 @@ typedef struct {
   int32_t true_residual; /* 1: also compute ||u0 - A u|| / ||u0|| (one extra matvec) */
   int32_t graph;         /* 1: after the first check_every iterations, run each block
                             of check_every COCG iterations as one replay of a HIP
-                            graph captured once per context and precision (same
-                            kernels and arguments, so results are bitwise those of
-                            0: one launch per kernel).  Ignored while per-kernel
-                            profiling is enabled.                                   */
+                            graph built once per context and precision, node by
+                            node from the same kernels and arguments (no stream
+                            capture), so results are bitwise those of 0: one
+                            launch per kernel.  Safe while other threads use
+                            other contexts or the device.  Ignored while
+                            per-kernel profiling is enabled.                       */
 } ori_solve_opts;
 
 typedef struct {
@@ -144,8 +149,17 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
  *   u0 : device complex128[nrhs][P], incident fields u0(x_p) (eq. 2.4 or any
  *        field), one per right-hand side
  * NaN/Inf anywhere or N < 0 gives ORI_ERR_INVALID_ARG.  May be called again
- * on the same context with new data (no reallocation). */
+ * on the same context with new data (no reallocation); the spectrum is then
+ * reused while k is unchanged (ori_spectrum_cache). */
 ori_status ori_load(ori_ctx ctx, double k, const void* h, const double* N, const void* u0);
+
+/* The kernel spectrum depends only on the grid and k, so ori_load computes
+ * it only when k differs from the previous successful load on ctx (design
+ * loops that change h or N, or u0, skip it; the results are bitwise those of
+ * a fresh computation).  enable = 0 makes every ori_load compute it again
+ * (a benchmark that times whole loads); enable = 1 (the default) restores
+ * the reuse. */
+ori_status ori_spectrum_cache(ori_ctx ctx, int32_t enable);
 
 /* ori_create(g, 1, FP64|MIXED, 0, stream, out) followed by ori_load. */
 ori_status ori_setup(const ori_grid* g, double k, const void* h, const double* N,

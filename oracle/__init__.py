@@ -7,8 +7,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import it.  The GPU library never imports, links or calls
 anything here, and nothing here imports the GPU library: the two share no code.
 
-Everything is complex128 / float64 NumPy, with LAPACK (``numpy.linalg.solve``)
-as the only library primitive beyond ``numpy.fft`` in the Section 3 route.
+Everything is complex128 / float64 NumPy, with LAPACK (``numpy.linalg.solve``,
+the singular values and the ``zgecon`` condition estimate) as the only library
+primitive beyond ``numpy.fft`` in the Section 3 route.  ``rows.py`` spreads
+independent sampled rows of eq. 2.19 over forked worker processes; each row's
+arithmetic is the single-process function's.
 
 Parity pins: every function is pinned by a CPU test in
 ``tests/test_oracle_pins.py`` or ``tests/test_physics_pins.py`` (no function
@@ -26,6 +29,7 @@ from .ori_oracle import (  # noqa: F401
     system_matrix,
     symmetric_system_matrix,
     solve_direct,
+    condition_number,
     scatter_dense,
     sample_scatter_rows,
     sample_residual_rows,
@@ -43,6 +47,7 @@ from .section3 import (  # noqa: F401
     convolve_section3,
     scatter_section3,
 )
+from .rows import sample_rows_parallel  # noqa: F401
 from .physics import (  # noqa: F401
     sqrt_branch_0_2pi,
     refraction_from_h,

@@ -132,6 +132,34 @@ def scatter_dense(points, k, D, v, block=1024):
     return y
 
 
+def condition_number(A, method="svd"):
+    """Condition number of the system matrix: the check that A is invertible.
+
+    The paper's theory needs Im h <= 0, while its own experiment (Section 4)
+    and the synthetic cases use Im h > 0, so invertibility is checked
+    numerically rather than assumed.
+
+    method="svd": the 2-norm condition number sigma_max / sigma_min from the
+    singular values (LAPACK zgesdd via numpy.linalg.svd).
+    method="gecon": LAPACK's estimate of the 1-norm condition number from an
+    LU factorisation (zgetrf + zgecon), for sizes where an SVD is too slow.
+    """
+    A = np.asarray(A, dtype=np.complex128)
+    if method == "svd":
+        s = np.linalg.svd(A, compute_uv=False)
+        return float(s[0] / s[-1])
+    if method == "gecon":
+        import scipy.linalg
+        import scipy.linalg.lapack as lapack
+        lu, _piv = scipy.linalg.lu_factor(A, check_finite=False)
+        anorm = float(np.max(np.sum(np.abs(A), axis=0)))
+        rcond, info = lapack.zgecon(lu, anorm, norm="1")
+        if info != 0 or rcond <= 0.0:
+            return math.inf
+        return float(1.0 / rcond)
+    raise ValueError(f"unknown method {method!r}")
+
+
 def sample_scatter_rows(points, k, D, v, rows, chunk=1 << 20):
     """(G0 (D v))_q for the listed rows q, any size.
 

@@ -14,7 +14,7 @@ import os
 
 __all__ = [
     "OriError", "lib", "Grid", "SolveOpts", "SolveInfo", "Layout", "Context",
-    "ori_setup", "ori_create", "ori_load", "ori_solve", "ori_matvec", "ori_destroy",
+    "ori_setup", "ori_create", "ori_load", "ori_spectrum_cache", "ori_solve", "ori_matvec", "ori_destroy",
     "ori_adjoint", "ori_gradient", "OriSolve", "ori_batch_info",
     "ori_charges", "ori_scattered_field", "ori_far_field",
     "ori_refraction_index", "ori_design_impedance", "ori_interpolation_difference",
@@ -96,6 +96,7 @@ def lib():
             "ori_create": (ctypes.c_int, [ctypes.POINTER(Grid), I32, I32, I64, P, ctypes.POINTER(P)]),
             "ori_batch_info": (ctypes.c_int, [P, I32, ctypes.POINTER(SolveInfo)]),
             "ori_load": (ctypes.c_int, [P, D, P, P, P]),
+            "ori_spectrum_cache": (ctypes.c_int, [P, I32]),
             "ori_setup": (ctypes.c_int, [ctypes.POINTER(Grid), D, P, P, P, P, ctypes.POINTER(P)]),
             "ori_solve": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo)]),
             "ori_matvec": (ctypes.c_int, [P, I32, I32, P, P]),
@@ -232,6 +233,12 @@ def ori_load(ctx, k, h, N, u0):
     _check(lib().ori_load(ctx.handle, float(k), _dev(h, torch.complex128, ctx.P, "h"),
                           _dev(N, torch.float64, ctx.P, "N"),
                           _dev(u0, torch.complex128, ctx.nrhs * ctx.P, "u0")), ctx)
+
+
+def ori_spectrum_cache(ctx, enable=True):
+    """enable: ori_load reuses the kernel spectrum while k is unchanged (the
+    default); False: every ori_load computes it again."""
+    _check(lib().ori_spectrum_cache(ctx.handle, int(bool(enable))), ctx)
 
 
 def ori_setup(n, k, h, N, u0, side=1.0, origin=(0.0, 0.0, 0.0), cell_offset=0.5, stream=None):
@@ -518,7 +525,7 @@ __import__("atexit").register(release_contexts)  # while the HIP runtime is stil
 def solve_many(problems, max_workers=4, reuse_contexts=False, **opts):
     """Independent problems of any sizes, each on its own context and stream,
     solved concurrently from a thread pool (the library call releases the
-    GIL), with eager launches (no graph replay unless graph=True is passed).
+    GIL).
     problems: dicts with n, k, h, N, u0 (CUDA tensors).  At most max_workers
     contexts (each holding its own workspaces) are in use at a time.  With
     reuse_contexts, a context is kept after its solve (workspaces, stream)
@@ -527,11 +534,6 @@ def solve_many(problems, max_workers=4, reuse_contexts=False, **opts):
     (u, info) in order."""
     import concurrent.futures
     import torch
-
-    # eager launches: HIP graph capture has failed intermittently while other
-    # threads worked on the device (see the capture lock in the runtime), and
-    # graph replay gains nothing at the sizes solved side by side
-    opts.setdefault("graph", False)
 
     def one(p):
         n, side = int(p["n"]), float(p.get("side", 1.0))

@@ -5,6 +5,7 @@
 // (k_finalize) in a fixed order.
 #include "cx.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace ori {
 namespace {
@@ -384,105 +385,118 @@ dim3 red_grid(int64_t P, int64_t nrhs, int64_t cap = kRedBlocksMax) {
 
 hipError_t launch_coefficients(const void* h, const double* N, double vol, int64_t P, void* D, void* S, void* Sf,
                                double* cN, double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(k_coefficients, red_grid(P, 1), dim3(kRedThreads), 0, st, static_cast<const cxd*>(h), N, vol, P,
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_coefficients, red_grid(P, 1), dim3(kRedThreads), st, static_cast<const cxd*>(h), N, vol, P,
                      static_cast<cxd*>(D), static_cast<cxd*>(S), static_cast<cxf*>(Sf), cN, partials);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_finalize_coeff(const double* partials, int64_t nblk, ScalarBlock* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_coeff, dim3(1), dim3(kRedThreads), 0, st, partials, nblk, sc);
-  return hipGetLastError();
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_finalize_coeff, dim3(1), dim3(kRedThreads), st, partials, nblk, sc);
+  return e;
 }
 
 hipError_t launch_div(const void* w, const void* s, void* u, int64_t P, int64_t nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_div, dim3(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs)), dim3(256), 0, st,
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_div, dim3(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs)), dim3(256), st,
                      static_cast<const cxd*>(w), static_cast<const cxd*>(s), static_cast<cxd*>(u), P);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_rhs(const void* u0, const void* S, int64_t P, int64_t nrhs, void* b, void* u0c, double* partials,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<const cxd*>(u0),
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_rhs, red_grid(P, nrhs), dim3(kRedThreads), st, static_cast<const cxd*>(u0),
                      static_cast<const cxd*>(S), P, static_cast<cxd*>(b), static_cast<cxd*>(u0c), partials);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_finalize(const double* partials, int64_t nblk, int64_t nrhs, ScalarBlock* sc, int32_t mode,
                            double eps, double tol2, int32_t tol2_of_bb, const double* tol2_rhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>(nrhs)), dim3(kFinThreads), 0, st, partials, nblk, sc,
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_finalize, dim3(static_cast<unsigned>(nrhs)), dim3(kFinThreads), st, partials, nblk, sc,
                      mode, eps, tol2, tol2_of_bb, tol2_rhs);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* q, int64_t P, int64_t nrhs,
                          const ScalarBlock* sc, double* partials, hipStream_t st) {
+  hipError_t e = hipSuccess;
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_update<double>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<cxd*>(x),
+    e = launch_kernel(k_update<double>, red_grid(P, nrhs), dim3(kRedThreads), st, static_cast<cxd*>(x),
                        static_cast<const cxd*>(p), static_cast<cxd*>(r), static_cast<const cxd*>(q), P, sc, partials);
   else
-    hipLaunchKernelGGL(k_update<float>, red_grid(P, nrhs, kUpdateBlocksMaxF32), dim3(kRedThreads), 0, st, static_cast<cxf*>(x),
+    e = launch_kernel(k_update<float>, red_grid(P, nrhs, kUpdateBlocksMaxF32), dim3(kRedThreads), st, static_cast<cxf*>(x),
                        static_cast<const cxf*>(p), static_cast<cxf*>(r), static_cast<const cxf*>(q), P, sc, partials);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_x_flush(int prec, void* x, const void* p, int64_t P, int64_t nrhs, const ScalarBlock* sc,
                           hipStream_t st) {
+  hipError_t e = hipSuccess;
   const dim3 g(static_cast<unsigned>(grid_for(P, 256, 8192)), static_cast<unsigned>(nrhs));
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_x_flush<double>, g, dim3(256), 0, st, static_cast<cxd*>(x), static_cast<const cxd*>(p), P,
+    e = launch_kernel(k_x_flush<double>, g, dim3(256), st, static_cast<cxd*>(x), static_cast<const cxd*>(p), P,
                        sc);
   else
-    hipLaunchKernelGGL(k_x_flush<float>, g, dim3(256), 0, st, static_cast<cxf*>(x), static_cast<const cxf*>(p), P,
+    e = launch_kernel(k_x_flush<float>, g, dim3(256), st, static_cast<cxf*>(x), static_cast<const cxf*>(p), P,
                        sc);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_init(int prec, const void* b, const double* m, void* x, void* r, int64_t P, int64_t nrhs,
                        double* partials, hipStream_t st) {
+  hipError_t e = hipSuccess;
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_init<double>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<const cxd*>(b), m,
+    e = launch_kernel(k_init<double>, red_grid(P, nrhs), dim3(kRedThreads), st, static_cast<const cxd*>(b), m,
                        static_cast<cxd*>(x), static_cast<cxd*>(r), P, partials);
   else
-    hipLaunchKernelGGL(k_init<float>, red_grid(P, nrhs), dim3(kRedThreads), 0, st, static_cast<const cxd*>(b), m,
+    e = launch_kernel(k_init<float>, red_grid(P, nrhs), dim3(kRedThreads), st, static_cast<const cxd*>(b), m,
                        static_cast<cxf*>(x), static_cast<cxf*>(r), P, partials);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_axpy_batch(int prec_in, const double* m, const void* x, void* y, int64_t P, int64_t nrhs,
                              hipStream_t st) {
+  hipError_t e = hipSuccess;
   const dim3 g(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs));
   if (prec_in == PREC_F64)
-    hipLaunchKernelGGL(k_axpy_batch<double>, g, dim3(256), 0, st, m, static_cast<const cxd*>(x),
+    e = launch_kernel(k_axpy_batch<double>, g, dim3(256), st, m, static_cast<const cxd*>(x),
                        static_cast<cxd*>(y), P);
   else
-    hipLaunchKernelGGL(k_axpy_batch<float>, g, dim3(256), 0, st, m, static_cast<const cxf*>(x), static_cast<cxd*>(y),
+    e = launch_kernel(k_axpy_batch<float>, g, dim3(256), st, m, static_cast<const cxf*>(x), static_cast<cxd*>(y),
                        P);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_mul(const void* s, const void* x, void* y, int64_t P, int64_t nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_mul, dim3(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs)), dim3(256), 0, st,
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_mul, dim3(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs)), dim3(256), st,
                      static_cast<const cxd*>(s), static_cast<const cxd*>(x), static_cast<cxd*>(y), P);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_conj_diff(const void* u, const void* t, void* f, int64_t P, double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(k_conj_diff, red_grid(P, 1), dim3(kRedThreads), 0, st, static_cast<const cxd*>(u),
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_conj_diff, red_grid(P, 1), dim3(kRedThreads), st, static_cast<const cxd*>(u),
                      static_cast<const cxd*>(t), static_cast<cxd*>(f), P, partials);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_gradient(const double* c, const void* u, const void* q, double alpha, void* g, int64_t P,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_gradient, dim3(grid_for(P, 256, 8192)), dim3(256), 0, st, c, static_cast<const cxd*>(u),
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_gradient, dim3(grid_for(P, 256, 8192)), dim3(256), st, c, static_cast<const cxd*>(u),
                      static_cast<const cxd*>(q), alpha, static_cast<cxd*>(g), P);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_sub_mul(const void* f, const void* s, const void* x, void* lam, int64_t P, hipStream_t st) {
-  hipLaunchKernelGGL(k_sub_mul, dim3(grid_for(P, 256, 8192)), dim3(256), 0, st, static_cast<const cxd*>(f),
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_sub_mul, dim3(grid_for(P, 256, 8192)), dim3(256), st, static_cast<const cxd*>(f),
                      static_cast<const cxd*>(s), static_cast<const cxd*>(x), static_cast<cxd*>(lam), P);
-  return hipGetLastError();
+  return e;
 }
 
 }  // namespace ori

@@ -94,6 +94,7 @@ struct StridedArgs {
   const void* in;
   void* out;
   int64_t n_outer, C;
+  int64_t nv;  // entries present along the axis: inputs e < nv (half_in), outputs e < nv (half_out)
   int32_t in_lg, out_lg;
   int64_t in_hi, in_lo, in_axis;
   int64_t out_hi, out_lo, out_axis;
@@ -137,6 +138,7 @@ struct SpectrumArgs {
   void* kh;
   void* kout;
   void* koutf;
+  int64_t n;  // points per axis: the table is zero at offsets |d_i| >= n
   double k, spacing, scale;
   int32_t pass, pad;
   const void* tw;      // complex128 twiddles
@@ -151,7 +153,7 @@ struct LengthKernels {
   hipError_t (*zpass)(int fprec, const ZArgs&, hipStream_t);
   int64_t (*contig_blocks_per_rhs)(int64_t ppr);
   int64_t (*strided_blocks)(int fprec, int np_sel, int64_t n_outer, int64_t C);
-  int64_t (*zpass_blocks)(int fprec, int np_sel, int64_t n);
+  int64_t (*zpass_blocks)(int fprec, int np_sel);
   hipError_t (*spectrum)(const SpectrumArgs&, hipStream_t);
 };
 

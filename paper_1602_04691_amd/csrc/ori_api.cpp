@@ -17,15 +17,20 @@
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <shared_mutex>
 #include <string>
 #include <vector>
 
 #include "cx.h"
 #include "kernels.h"
+#include "launch.h"
 #include "plan.h"
 
 namespace ori {
+namespace {
+thread_local GraphBuild* t_graph = nullptr;
+}
+GraphBuild* graph_being_built() { return t_graph; }
+
 #define ORI_DECL(L) const LengthKernels* kernels_L##L();
 ORI_FOR_EACH_L(ORI_DECL)
 #undef ORI_DECL
@@ -100,18 +105,6 @@ struct Tuned {
 };
 std::mutex g_tune_mu;
 
-// Graph capture and other threads' work on the device.  A capture of COCG
-// iterations on one context has failed when other threads were working on
-// theirs at the same time (the capture invalidated, another thread's kernel
-// launch or the graph instantiation refused), though contexts are
-// independent.  So kernel launches and graph replays hold this lock shared,
-// and a capture with its instantiation, and the destruction of graphs and
-// capture streams, hold it exclusively.  The capturing thread's own launches
-// are recorded into the graph and skip the lock (t_capturing).  Work that
-// other threads do outside the library is not covered: solve_many, which
-// runs contexts from several threads, solves without graph replay.
-std::shared_mutex g_capture_mu;
-thread_local bool t_capturing = false;
 std::map<TuneKey, Tuned> g_tuned;
 
 struct ProfPending {
@@ -129,6 +122,11 @@ struct ori_ctx_s {
   double k = 0.0;
   bool loaded = false;
   bool poisoned = false;
+  // the kernel spectrum depends only on (n, side, k): ori_load keeps it while
+  // k is unchanged (spectrum_k), unless the cache is switched off
+  bool spectrum_cache = true;
+  bool spectrum_valid = false;
+  double spectrum_k = 0.0;
   hipStream_t stream = nullptr;
   int device = 0;
   const LengthKernels* K = nullptr;
@@ -165,14 +163,12 @@ struct ori_ctx_s {
   // right-hand side on stderr after every check of a solve
   bool trace = false;
 
-  // captured COCG iteration blocks, one per vector precision
+  // COCG iteration blocks as HIP graphs, one per vector precision
   struct IterGraph {
     hipGraphExec_t exec = nullptr;
     int iters = 0;
     const void* key[5] = {};
   } graphs[2];
-  hipStream_t cap_stream = nullptr;  // capture stream (the context stream may be the null stream)
-  hipError_t launch_err = hipSuccess;  // HIP error of the last failed kernel launch
 
   // profiling
   bool prof = false;
@@ -214,6 +210,19 @@ ori_status set_err(ori_ctx c, ori_status st, const char* fmt, ...) {
 
 bool finite(double v) { return std::isfinite(v); }
 
+// Padded length per axis: the shortest planned length L >= 2n - 1, so that
+// the cyclic convolution of length L holds every offset in (-n, n) without
+// wrap-around (the zero padding of Section 3, eq. 3.3.5); 0 beyond n = 512.
+int64_t padded_length(int64_t n) {
+  if (n < 1 || n > 512) return 0;
+  int64_t best = 0;
+#define ORI_PICK(Lc) \
+  if ((Lc) >= 2 * n - 1 && (best == 0 || (Lc) < best)) best = (Lc);
+  ORI_FOR_EACH_L(ORI_PICK)
+#undef ORI_PICK
+  return best;
+}
+
 ori_status check_grid(const ori_grid* g, int64_t* L_out) {
   if (!g) return set_err(nullptr, ORI_ERR_INVALID_ARG, "grid is NULL");
   if (g->n < 1) return set_err(nullptr, ORI_ERR_INVALID_ARG, "n = %lld must be >= 1", (long long)g->n);
@@ -222,10 +231,11 @@ ori_status check_grid(const ori_grid* g, int64_t* L_out) {
   for (int i = 0; i < 3; ++i)
     if (!finite(g->origin[i])) return set_err(nullptr, ORI_ERR_INVALID_ARG, "origin must be finite");
   if (!finite(g->cell_offset)) return set_err(nullptr, ORI_ERR_INVALID_ARG, "cell_offset must be finite");
-  if (g->n > 512 || !supported_length(static_cast<int>(2 * g->n)))
-    return set_err(nullptr, ORI_ERR_UNSUPPORTED, "no FFT plan for n = %lld (padded length %lld)",
-                   (long long)g->n, (long long)(2 * g->n));
-  *L_out = 2 * g->n;
+  const int64_t L = padded_length(g->n);
+  if (L == 0)
+    return set_err(nullptr, ORI_ERR_UNSUPPORTED, "n = %lld: no FFT plan of length >= 2n - 1 (n <= 512 is supported)",
+                   (long long)g->n);
+  *L_out = L;
   return ORI_OK;
 }
 
@@ -239,20 +249,21 @@ struct Layout {
 // largest reducing grid: I1 (at most n*n workgroups per right-hand side) and
 // the reduction kernels (red_blocks(P), update_blocks(P, prec) per right-hand side).
 Layout layout_for(int64_t n, int64_t nrhs, int provision) {
-  const int64_t P = n * n * n, kp = n + 1;
+  const int64_t L = padded_length(n);
+  const int64_t P = n * n * n, kp = L / 2 + 1;
   const bool mixed = provision & ORI_PROVISION_MIXED;
   Layout l{};
   // A (n*n*L) + B (n*L*L) complex128 per right-hand side; also the octant
   // scratch of the spectrum passes at load time
-  l.arena = align_up(std::max<int64_t>(nrhs * 6 * P, kp * kp * kp) * 16);
+  l.arena = align_up(std::max<int64_t>(nrhs * (n * n * L + n * L * L), kp * kp * kp) * 16);
   l.vec_d = align_up(P * 16);
   l.vec_f = align_up(P * 8);
-  l.kh = align_up(kp * kp * kp * 16);  // octant [n+1][n+1][n+1]
+  l.kh = align_up(kp * kp * kp * 16);  // octant [L/2+1]^3
   l.khf = mixed ? align_up(kp * kp * kp * 8) : 0;
   l.npart = nrhs * std::max({red_blocks(P), update_blocks(P, PREC_F32), n * n});
   const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
   const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
-  l.total = l.arena + shared + batch + l.kh + l.khf + align_up(2 * n * 16) + align_up(2 * n * 8) +
+  l.total = l.arena + shared + batch + l.kh + l.khf + align_up(L * 16) + align_up(L * 8) +
             align_up(l.npart * 4 * 8) + align_up(nrhs * (int64_t)sizeof(ScalarBlock)) + align_up(2 * nrhs * 8) +
             (mixed ? 24 : 18) * kGuardBytes;  // one guard band per allocation
   return l;
@@ -336,17 +347,11 @@ ori_status launch(ori_ctx c, int kind, int fprec, F&& f) {
     }
     ORI_HIP(c, hipEventRecord(c->ev[2 * evi], c->stream));
   }
-  hipError_t e;
-  {
-    std::shared_lock<std::shared_mutex> lk(g_capture_mu, std::defer_lock);
-    if (!t_capturing) lk.lock();
-    (void)hipGetLastError();  // the launch reports its own error, not an earlier call's
-    e = f();
-  }
-  if (e != hipSuccess) {
-    c->launch_err = e;
-    return set_err(c, ORI_ERR_DEVICE, "kernel %s launch failed: %s", kKindNames[kind], hipGetErrorString(e));
-  }
+  (void)hipGetLastError();  // the launch reports its own error, not an earlier call's
+  const hipError_t e = f();
+  if (e != hipSuccess)
+    return set_err(c, ORI_ERR_DEVICE, "kernel %s %s failed: %s", kKindNames[kind],
+                   graph_being_built() ? "graph node" : "launch", hipGetErrorString(e));
   if (c->check_guards) {
     int64_t bad = 0;
     ORI_TRY(count_damaged_guards(c, &bad));
@@ -404,19 +409,19 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   const int lg = kn.blk_lg;
   const int64_t Bk = int64_t{1} << lg;
   const int ns = kn.np_sel;
-  StridedArgs f2{A, B, R * n, L, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, ns, tw};
+  StridedArgs f2{A, B, R * n, L, n, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, ns, tw};
   ORI_TRY(launch(c, K_F2, fprec, [&] { return c->K->strided(fprec, f2, c->stream); }));
 
   // Small grids (a batch at small n) are split over the right-hand sides,
   // so that the pass has enough workgroups to fill the chip; no slice is
   // left empty.
-  const int64_t zbase = c->K->zpass_blocks(fprec, kn.z_np, n);
+  const int64_t zbase = c->K->zpass_blocks(fprec, kn.z_np);
   int64_t rs = std::min<int64_t>(R, (kZMinWorkgroups + zbase - 1) / zbase);
   if (rs > 1) rs = (R + (R + rs - 1) / rs - 1) / ((R + rs - 1) / rs);
-  ZArgs z{B, n, lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, static_cast<int32_t>(rs), kh, n + 1, tw};
+  ZArgs z{B, n, lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, static_cast<int32_t>(rs), kh, L / 2 + 1, tw};
   ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, z, c->stream); }));
 
-  StridedArgs i2{B, A, R * n, L, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};
+  StridedArgs i2{B, A, R * n, L, n, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};
   ORI_TRY(launch(c, K_I2, fprec, [&] { return c->K->strided(fprec, i2, c->stream); }));
 
   i1.in = A;
@@ -459,8 +464,8 @@ ContigInvArgs epi(void* y, const void* a0, double c0, const void* a1, double c1,
 ori_status compute_spectrum(ori_ctx c) {
   const double L = static_cast<double>(c->L);
   // the octant scratch of passes 1-2 lives in the (idle) FFT work arena
-  SpectrumArgs a{c->arena, c->kh, c->khf, c->k, c->grid.side / static_cast<double>(c->n), 1.0 / (L * L * L), 1, 0,
-                 c->twd};
+  SpectrumArgs a{c->arena, c->kh, c->khf, c->n, c->k, c->grid.side / static_cast<double>(c->n), 1.0 / (L * L * L), 1,
+                 0, c->twd};
   for (int pass = 1; pass <= 3; ++pass) {  // 1/L^3 of the inverse DFT is folded in by pass 3
     a.pass = pass;
     ORI_TRY(launch(c, K_SPEC_FFT, PREC_F64, [&] { return c->K->spectrum(a, c->stream); }));
@@ -508,7 +513,7 @@ bool all_done(ori_ctx c) {
 // iteration's step) and p = r + beta p (p = r when first) in F1, q = (I +
 // S G0 S) p with <p,q>, then alpha, r and rho.  The step x += alpha p of
 // the last iteration is left pending for flush_x.  No memset and no host
-// work, so it can be captured.
+// work, so its launches can also be built into a graph (iteration_graph).
 ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, bool first) {
   ContigFwdArgs f1{};
   f1.x = r;
@@ -528,18 +533,11 @@ ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* 
   return finalize(c, update_blocks(c->P, prec), FIN_RHO);
 }
 
-bool capture_error(hipError_t e) {
-  return e == hipErrorStreamCaptureInvalidated || e == hipErrorStreamCaptureUnsupported ||
-         e == hipErrorStreamCaptureImplicit;
-}
-
-// The graph of `iters` non-first iterations on (x, r, p, q, S), captured on
-// the context's capture stream and cached per precision.  The capture makes
-// no call that is unsafe during capture, so it uses the relaxed mode:
-// another thread's allocations or frees (other contexts, the caller's
-// allocator) must not end it.  If the runtime still invalidates it, nothing
-// captured has run, so *out is left NULL, the context stays usable and the
-// caller runs the block eagerly (same kernels, same results).
+// The graph of `iters` non-first iterations on (x, r, p, q, S), cached per
+// precision.  It is built node by node: with graph_being_built() set, every
+// launch of cocg_iteration appends a kernel node after the previous one
+// (launch.h), so it holds exactly the kernels and arguments of the eager
+// launches, in order, and no stream is put into capture mode.
 ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int iters,
                            hipGraphExec_t* out) {
   *out = nullptr;
@@ -549,45 +547,24 @@ ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void*
     *out = g.exec;
     return ORI_OK;
   }
-  std::unique_lock<std::shared_mutex> capture_lock(g_capture_mu);
   if (g.exec) {
     ORI_HIP(c, hipGraphExecDestroy(g.exec));
     g.exec = nullptr;
   }
-  if (!c->cap_stream) ORI_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  hipStream_t own = c->stream;
-  c->stream = c->cap_stream;
-  hipGraph_t graph = nullptr;
-  t_capturing = true;
-  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
-  ori_status st = e == hipSuccess ? ORI_OK : set_err(c, ORI_ERR_DEVICE, "hipStreamBeginCapture: %s",
-                                                     hipGetErrorString(e));
-  bool invalidated = false;
+  GraphBuild gb;
+  ORI_HIP(c, hipGraphCreate(&gb.graph, 0));
+  t_graph = &gb;
+  ori_status st = ORI_OK;
+  for (int it = 0; it < iters && st == ORI_OK; ++it) st = cocg_iteration(c, prec, x, r, p, q, S, false);
+  t_graph = nullptr;
   if (st == ORI_OK) {
-    c->launch_err = hipSuccess;
-    for (int it = 0; it < iters && st == ORI_OK; ++it) st = cocg_iteration(c, prec, x, r, p, q, S, false);
-    e = hipStreamEndCapture(c->cap_stream, &graph);
-    invalidated = (st != ORI_OK && capture_error(c->launch_err)) || (st == ORI_OK && capture_error(e));
-    if (st == ORI_OK && e != hipSuccess && !invalidated)
-      st = set_err(c, ORI_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-  }
-  c->stream = own;
-  t_capturing = false;
-  if (invalidated) {
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipGetLastError();  // the capture error is handled here
-    c->poisoned = false;
-    c->err = "no error";
-    return ORI_OK;
-  }
-  if (st == ORI_OK) {
-    e = hipGraphInstantiateWithFlags(&g.exec, graph, 0);
+    const hipError_t e = hipGraphInstantiateWithFlags(&g.exec, gb.graph, 0);
     if (e != hipSuccess) {
       g.exec = nullptr;
       st = set_err(c, ORI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
   }
-  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGraphDestroy(gb.graph);
   if (st != ORI_OK) return st;
   g.iters = iters;
   std::copy(key, key + 5, g.key);
@@ -634,12 +611,11 @@ ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* 
   int it = 0;
   while (it < max_iter) {
     // the first block runs eagerly (it holds the first iteration); later
-    // full blocks replay the captured graph
+    // full blocks replay the graph of check_every iterations
     const int blk = std::min(check_every, max_iter - it);
     hipGraphExec_t exec = nullptr;
     if (use_graph && it > 0 && blk == check_every) ORI_TRY(iteration_graph(c, prec, x, r, p, q, S, blk, &exec));
     if (exec) {
-      std::shared_lock<std::shared_mutex> lk(g_capture_mu);
       ORI_HIP(c, hipGraphLaunch(exec, c->stream));
     } else {
       for (int j = 0; j < blk; ++j) ORI_TRY(cocg_iteration(c, prec, x, r, p, q, S, it + j == 0));
@@ -735,7 +711,6 @@ void choose_layout(ori_ctx c) {
 
 // Captured graphs bake the layout into their kernel arguments.
 ori_status drop_graphs(ori_ctx c) {
-  std::unique_lock<std::shared_mutex> lk(g_capture_mu);
   for (auto& g : c->graphs) {
     if (g.exec) ORI_HIP(c, hipGraphExecDestroy(g.exec));
     g.exec = nullptr;
@@ -1151,8 +1126,8 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
     ORI_ALLOC(lay.khf, c->khf, cxf*);
   }
   ORI_ALLOC(lay.kh, c->kh, cxd*);
-  ORI_ALLOC(align_up(2 * g->n * 16), c->twd, cxd*);
-  ORI_ALLOC(align_up(2 * g->n * 8), c->twf, cxf*);
+  ORI_ALLOC(align_up(L * 16), c->twd, cxd*);
+  ORI_ALLOC(align_up(L * 8), c->twf, cxf*);
   ORI_ALLOC(align_up(lay.npart * 4 * 8), c->partials, double*);
   ORI_ALLOC(align_up(R * (int64_t)sizeof(ScalarBlock)), c->sc, ScalarBlock*);
   ORI_ALLOC(align_up(2 * R * 8), c->outer_m, double*);
@@ -1187,7 +1162,12 @@ ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const v
   ORI_TRY(check_dev_ptr(c, u0, R * P * 16, "u0"));
   c->loaded = false;
   c->k = k;
-  ORI_TRY(compute_spectrum(c));
+  if (!(c->spectrum_cache && c->spectrum_valid && c->spectrum_k == k)) {
+    c->spectrum_valid = false;
+    ORI_TRY(compute_spectrum(c));
+    c->spectrum_valid = true;
+    c->spectrum_k = k;
+  }
   const double vol = std::pow(c->grid.side / static_cast<double>(c->n), 3);
   // operator coefficients: the bad-input count lands in sc[0]
   ORI_TRY(launch(c, K_COEFF, PREC_F64, [&] {
@@ -1212,6 +1192,13 @@ ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const v
     c->u0norm2[i] = c->sc_host[i].aux;
   }
   c->loaded = true;
+  return ORI_OK;
+}
+
+ori_status ori_spectrum_cache(ori_ctx c, int32_t enable) {
+  ORI_TRY(guard(c));
+  c->spectrum_cache = enable != 0;
+  if (!c->spectrum_cache) c->spectrum_valid = false;
   return ORI_OK;
 }
 
@@ -1580,12 +1567,8 @@ void ori_destroy(ori_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);  // all of the context's work is on its stream
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-  {
-    std::unique_lock<std::shared_mutex> lk(g_capture_mu);
-    for (auto& g : c->graphs)
-      if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  }
+  for (auto& g : c->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   if (c->outer_m_host) (void)hipHostFree(c->outer_m_host);

@@ -15,8 +15,12 @@
 //       q = p + S conv and the bilinear partials p^T q             n*n pencils
 //
 // The work arrays are  A[i1][i2][k3]  (n*n*L)  and  B[i1][k2][k3]  (n*L*L).
+// L is the padded length of the plan; any n with 2n - 1 <= L gives the
+// linear convolution (offsets lie in (-n, n)).  Kernels with EX = true take
+// n = L/2 exactly; EX = false guards every read and write at n.
 #include "fft_engine.h"
 #include "kernels.h"
+#include "launch.h"
 
 #ifndef ORI_L
 #error "compile once per padded length with -DORI_L=<L>"
@@ -77,7 +81,7 @@ __device__ __forceinline__ int64_t two_level(int64_t o, int lg, int64_t hi, int6
 // ---------------------------------------------------------------------------
 // F1 (and the first spectrum pass): contiguous forward with prologue
 // ---------------------------------------------------------------------------
-template <typename V, typename T, bool HALF>
+template <typename V, typename T, bool EX>
 __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
   __shared__ cx<T> lds[NPC * padded_row(L)];
   using E = Engine<T, L, false>;
@@ -106,6 +110,9 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
 
   auto load = [&](int e) -> cx<T> {
     if (!act) return cx<T>{};
+    if constexpr (!EX) {
+      if (e >= a.in_pitch) return cx<T>{};  // zero padding between n and L/2
+    }
     const int64_t i = ib + e;
     cx<double> v;
     if (a.mode == 1) {
@@ -124,9 +131,9 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
     return cvt<T>(v);
   };
   typename E::template RegsOf<0> g;
-  E::template load_first<HALF>(g, bt, load);
+  E::template load_first<true>(g, bt, load);
   LdsPencil<T> lp{lds + t * padded_row(L), 0};
-  E::template run<HALF>(g, bt, lp, tw, [&](auto& gl) {
+  E::template run<true>(g, bt, lp, tw, [&](auto& gl) {
     E::template store_last<KEEP_ALL>(gl, bt, [&](int e, cx<T> v) {
       if (act) out[ob + e] = v;
     });
@@ -136,7 +143,7 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_fwd(ContigFwdArgs a) {
 // ---------------------------------------------------------------------------
 // I1: contiguous inverse, keep e < out_pitch (= n), epilogue and partials
 // ---------------------------------------------------------------------------
-template <typename V, typename T>
+template <typename V, typename T, bool EX>
 __global__ void __launch_bounds__(BLOCK_C) k_contig_inv(ContigInvArgs a) {
   __shared__ cx<T> lds[NPC * padded_row(L)];
   using E = Engine<T, L, true>;
@@ -165,6 +172,9 @@ __global__ void __launch_bounds__(BLOCK_C) k_contig_inv(ContigInvArgs a) {
   E::template run<false>(g, bt, lp, tw, [&](auto& gl) {
     E::template store_last<KEEP_HALF>(gl, bt, [&](int e, cx<T> c) {
       if (!act) return;
+      if constexpr (!EX) {
+        if (e >= a.out_pitch) return;
+      }
       const int64_t i = ob + e;
       cx<double> conv = cvt<double>(c);
       if (so) conv = conv * cvt<double>(so[db + e]);
@@ -201,7 +211,7 @@ __device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t G) {
   return x * q + (x < r ? x : r) + j;
 }
 
-template <typename T, int NP, bool INV, bool HIN, bool HOUT>
+template <typename T, int NP, bool INV, bool HIN, bool HOUT, bool EX>
 __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
   __shared__ cx<T> lds[NP * L];
   using E = Engine<T, L, INV>;
@@ -226,12 +236,20 @@ __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
   const int64_t ib = two_level(o, a.in_lg, a.in_hi, a.in_lo) + c;
   const int64_t ob = two_level(o, a.out_lg, a.out_hi, a.out_lo) + c;
 
-  auto load = [&](int e) -> cx<T> { return act ? in[ib + e * a.in_axis] : cx<T>{}; };
+  auto load = [&](int e) -> cx<T> {
+    if constexpr (HIN && !EX) {
+      if (e >= a.nv) return cx<T>{};
+    }
+    return act ? in[ib + e * a.in_axis] : cx<T>{};
+  };
   typename E::template RegsOf<0> g;
   E::template load_first<HIN>(g, bt, load);
   LdsPencil<T> lp{lds + t, NP};
   E::template run<HIN>(g, bt, lp, tw, [&](auto& gl) {
     E::template store_last<HOUT ? KEEP_HALF : KEEP_ALL>(gl, bt, [&](int e, cx<T> v) {
+      if constexpr (HOUT && !EX) {
+        if (e >= a.nv) return;
+      }
       if (act) out[ob + e * a.out_axis] = v;
     });
   });
@@ -282,9 +300,9 @@ template <typename T>
 using ZRegs = typename Engine<T, L, false, z_tpp<T>(), z_plan<T>()>::template RegsOf<
     Stages<L, false, z_tpp<T>(), z_plan<T>()>::NS - 1>;
 
-template <typename T, int NP, bool PF>
+template <typename T, int NP, bool PF, bool EX>
 __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k_zpass(ZArgs a) {
-  constexpr int n = L / 2;
+  constexpr int half = L / 2;
   constexpr int ZT = z_tpp<T>();
   using EF = Engine<T, L, false, ZT, z_plan<T>()>;
   using EI = Engine<T, L, true, ZT, z_plan<T>()>;
@@ -338,7 +356,7 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
       kv.v[i][j] = ok ? kh[(m1 * a.kp + m2) * a.kp + m3] : cx<T>{};
     }
   }
-  const int64_t nvar = (m2 != 0 && m2 != n) ? 2 : 1;  // uniform over the workgroup
+  const int64_t nvar = (m2 != 0 && m2 != half) ? 2 : 1;  // uniform over the workgroup
   const int64_t ntile = r_lo < r_hi ? nvar * (r_hi - r_lo) : 0;
   const int64_t emask = (int64_t{1} << a.e_lg) - 1;
   // tiles in the order (k2 = m2, rhs r_lo..r_hi-1), (k2 = L - m2, the same
@@ -357,7 +375,12 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
     return base + (e >> a.e_lg) * a.e_hi + (e & emask) * a.e_lo;
   };
   auto fetch = [&](G0& g, int64_t base) {
-    EF::template load_first<true>(g, bt, [&](int e) -> cx<T> { return act ? buf[addr(base, e)] : cx<T>{}; });
+    EF::template load_first<true>(g, bt, [&](int e) -> cx<T> {
+      if constexpr (!EX) {
+        if (e >= a.n) return cx<T>{};  // zero padding between n and L/2
+      }
+      return act ? buf[addr(base, e)] : cx<T>{};
+    });
   };
   LdsPencil<T> lp{lds + t, NP};
   auto transform = [&](G0& g, int64_t base) {
@@ -369,6 +392,9 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
       }
       EI::template run<false>(gl, bt, lp, tw, [&](auto& gi) {
         EI::template store_last<KEEP_HALF>(gi, bt, [&](int e, cx<T> v) {
+          if constexpr (!EX) {
+            if (e >= a.n) return;
+          }
           if (act) buf[addr(base, e)] = v;
         });
       });
@@ -412,14 +438,16 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
 // kernel spectrum on its octant (SpectrumArgs)
 // ---------------------------------------------------------------------------
 // The Green's table on the padded grid: c(m) = G(spacing |d|), wrapped
-// offsets d_i = m_i (m_i < n) or m_i - L (m_i > n); zero at m = 0 (the
-// excluded self term, eq. 2.19) and where some m_i = n (never reached).
-__device__ __forceinline__ cxd green_table(int m1, int m2, int m3, double k, double spacing) {
-  constexpr int n = L / 2;
-  if (m1 == n || m2 == n || m3 == n || (m1 | m2 | m3) == 0) return cxd{0.0, 0.0};
-  const double d1 = m1 < n ? m1 : m1 - L;
-  const double d2 = m2 < n ? m2 : m2 - L;
-  const double d3 = m3 < n ? m3 : m3 - L;
+// offsets d_i = m_i (m_i <= L/2) or m_i - L (m_i > L/2); zero at m = 0 (the
+// excluded self term, eq. 2.19) and wherever some |d_i| >= n (offsets that
+// two of the n points per axis never have).
+__device__ __forceinline__ cxd green_table(int m1, int m2, int m3, double k, double spacing, int n) {
+  constexpr int half = L / 2;
+  const int d1i = m1 <= half ? m1 : m1 - L;
+  const int d2i = m2 <= half ? m2 : m2 - L;
+  const int d3i = m3 <= half ? m3 : m3 - L;
+  if (abs(d1i) >= n || abs(d2i) >= n || abs(d3i) >= n || (m1 | m2 | m3) == 0) return cxd{0.0, 0.0};
+  const double d1 = d1i, d2 = d2i, d3 = d3i;
   const double r = spacing * sqrt(d1 * d1 + d2 * d2 + d3 * d3);
   double sn, cs;
   sincos(k * r, &sn, &cs);
@@ -439,7 +467,7 @@ __global__ void __launch_bounds__(BLOCK_C) k_spectrum_first(SpectrumArgs a) {
   const int m1 = act ? static_cast<int>(pid / kp) : 0;
   const int m2 = act ? static_cast<int>(pid % kp) : 0;
   cxd* __restrict__ kh = static_cast<cxd*>(a.kh);
-  auto load = [&](int e) -> cxd { return act ? green_table(m1, m2, e, a.k, a.spacing) : cxd{}; };
+  auto load = [&](int e) -> cxd { return act ? green_table(m1, m2, e, a.k, a.spacing, static_cast<int>(a.n)) : cxd{}; };
   typename E::template RegsOf<0> g;
   E::template load_first<false>(g, bt, load);
   LdsPencil<double> lp{lds + t * padded_row(L), 0};
@@ -514,44 +542,64 @@ int64_t strided_blocks(int fprec, int np_sel, int64_t n_outer, int64_t C) {
   return n_outer * ((C + np - 1) / np);
 }
 
-hipError_t contig_fwd(int vp, int fp, const ContigFwdArgs& a, hipStream_t st) {
+template <bool EX>
+hipError_t contig_fwd_t(int vp, int fp, const ContigFwdArgs& a, hipStream_t st) {
+  hipError_t e = hipSuccess;
   const dim3 grid(static_cast<unsigned>(a.nrhs * contig_blocks_per_rhs(a.ppr))), block(BLOCK_C);
-  if (!a.half_in) return hipErrorInvalidValue;
   if (vp == PREC_F64 && fp == PREC_F64) {
-    hipLaunchKernelGGL((k_contig_fwd<double, double, true>), grid, block, 0, st, a);
+    e = launch_kernel((k_contig_fwd<double, double, EX>), grid, block, st, a);
   } else if (vp == PREC_F32 && fp == PREC_F32) {
-    hipLaunchKernelGGL((k_contig_fwd<float, float, true>), grid, block, 0, st, a);
+    e = launch_kernel((k_contig_fwd<float, float, EX>), grid, block, st, a);
   } else if (vp == PREC_F64 && fp == PREC_F32) {
-    hipLaunchKernelGGL((k_contig_fwd<double, float, true>), grid, block, 0, st, a);
+    e = launch_kernel((k_contig_fwd<double, float, EX>), grid, block, st, a);
   } else {
     return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  return e;
+}
+
+hipError_t contig_fwd(int vp, int fp, const ContigFwdArgs& a, hipStream_t st) {
+  // the input is the first n <= L/2 entries of each pencil (zero padding)
+  if (!a.half_in || a.in_pitch < 1 || 2 * a.in_pitch - 1 > L || a.out_pitch != L) return hipErrorInvalidValue;
+  return 2 * a.in_pitch == L ? contig_fwd_t<true>(vp, fp, a, st) : contig_fwd_t<false>(vp, fp, a, st);
+}
+
+template <bool EX>
+hipError_t contig_inv_t(int vp, int fp, const ContigInvArgs& a, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  const dim3 grid(static_cast<unsigned>(a.nrhs * contig_blocks_per_rhs(a.ppr))), block(BLOCK_C);
+  if (vp == PREC_F64 && fp == PREC_F64)
+    e = launch_kernel((k_contig_inv<double, double, EX>), grid, block, st, a);
+  else if (vp == PREC_F32 && fp == PREC_F32)
+    e = launch_kernel((k_contig_inv<float, float, EX>), grid, block, st, a);
+  else if (vp == PREC_F64 && fp == PREC_F32)
+    e = launch_kernel((k_contig_inv<double, float, EX>), grid, block, st, a);
+  else
+    return hipErrorInvalidValue;
+  return e;
 }
 
 hipError_t contig_inv(int vp, int fp, const ContigInvArgs& a, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(a.nrhs * contig_blocks_per_rhs(a.ppr))), block(BLOCK_C);
-  if (vp == PREC_F64 && fp == PREC_F64)
-    hipLaunchKernelGGL((k_contig_inv<double, double>), grid, block, 0, st, a);
-  else if (vp == PREC_F32 && fp == PREC_F32)
-    hipLaunchKernelGGL((k_contig_inv<float, float>), grid, block, 0, st, a);
-  else if (vp == PREC_F64 && fp == PREC_F32)
-    hipLaunchKernelGGL((k_contig_inv<double, float>), grid, block, 0, st, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  // the output is the first n <= L/2 entries of each inverse transform
+  if (a.out_pitch < 1 || 2 * a.out_pitch - 1 > L || a.in_pitch != L) return hipErrorInvalidValue;
+  return 2 * a.out_pitch == L ? contig_inv_t<true>(vp, fp, a, st) : contig_inv_t<false>(vp, fp, a, st);
 }
 
 template <typename T, int NP>
 hipError_t strided_t(const StridedArgs& a, hipStream_t st) {
+  hipError_t e = hipSuccess;
   const dim3 grid(static_cast<unsigned>(a.n_outer * ((a.C + NP - 1) / NP))), block(NP * TPP);
+  if (a.nv < 1 || 2 * a.nv - 1 > L) return hipErrorInvalidValue;
+  const bool ex = 2 * a.nv == L;
   if (!a.inverse && a.half_in && !a.half_out)
-    hipLaunchKernelGGL((k_strided<T, NP, false, true, false>), grid, block, 0, st, a);
+    e = ex ? launch_kernel((k_strided<T, NP, false, true, false, true>), grid, block, st, a)
+           : launch_kernel((k_strided<T, NP, false, true, false, false>), grid, block, st, a);
   else if (a.inverse && !a.half_in && a.half_out)
-    hipLaunchKernelGGL((k_strided<T, NP, true, false, true>), grid, block, 0, st, a);
+    e = ex ? launch_kernel((k_strided<T, NP, true, false, true, true>), grid, block, st, a)
+           : launch_kernel((k_strided<T, NP, true, false, true, false>), grid, block, st, a);
   else
     return hipErrorInvalidValue;
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t strided(int fp, const StridedArgs& a, hipStream_t st) {
@@ -560,40 +608,47 @@ hipError_t strided(int fp, const StridedArgs& a, hipStream_t st) {
   return a.np_sel ? strided_t<float, np_narrow<float>()>(a, st) : strided_t<float, nps<float>()>(a, st);
 }
 
-int64_t zpass_blocks(int fprec, int np_sel, int64_t n) {
+// Z workgroups per right-hand-side slice: octant rows m2 in [0, L/2] times
+// the tiles of k3 in [0, L)
+int64_t zpass_blocks(int fprec, int np_sel) {
   const int64_t np = fprec == PREC_F64 ? np_of<double>(np_sel) : np_of<float>(np_sel);
-  return (n + 1) * ((2 * n + np - 1) / np);
+  return (L / 2 + 1) * ((L + np - 1) / np);
 }
 
 template <typename T, int NP>
 hipError_t zpass_t(const ZArgs& a, hipStream_t st) {
+  hipError_t e = hipSuccess;
   if (a.rhs_slices < 1 || a.rhs_slices > a.nrhs) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>((a.n + 1) * ((2 * a.n + NP - 1) / NP) * a.rhs_slices)),
-      block(NP * z_tpp<T>());
+  const dim3 grid(static_cast<unsigned>((L / 2 + 1) * ((L + NP - 1) / NP) * a.rhs_slices)), block(NP * z_tpp<T>());
+  const bool ex = 2 * a.n == L;
   if (a.prefetch)
-    hipLaunchKernelGGL((k_zpass<T, NP, true>), grid, block, 0, st, a);
+    e = ex ? launch_kernel((k_zpass<T, NP, true, true>), grid, block, st, a)
+           : launch_kernel((k_zpass<T, NP, true, false>), grid, block, st, a);
   else
-    hipLaunchKernelGGL((k_zpass<T, NP, false>), grid, block, 0, st, a);
-  return hipGetLastError();
+    e = ex ? launch_kernel((k_zpass<T, NP, false, true>), grid, block, st, a)
+           : launch_kernel((k_zpass<T, NP, false, false>), grid, block, st, a);
+  return e;
 }
 
 hipError_t spectrum(const SpectrumArgs& a, hipStream_t st) {
+  if (a.n < 1 || 2 * a.n - 1 > L) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
   constexpr int64_t kp = L / 2 + 1;
   if (a.pass == 1) {
-    hipLaunchKernelGGL(k_spectrum_first, dim3(static_cast<unsigned>(contig_blocks_per_rhs(kp * kp))), dim3(BLOCK_C), 0, st,
+    e = launch_kernel(k_spectrum_first, dim3(static_cast<unsigned>(contig_blocks_per_rhs(kp * kp))), dim3(BLOCK_C), st,
                        a);
   } else if (a.pass == 2 || a.pass == 3) {
     const int64_t np = nps<double>();
     const dim3 grid(static_cast<unsigned>(kp * ((kp + np - 1) / np)));
-    hipLaunchKernelGGL(k_spectrum_strided, grid, dim3(block_s<double>()), 0, st, a);
+    e = launch_kernel(k_spectrum_strided, grid, dim3(block_s<double>()), st, a);
   } else {
     return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t zpass(int fp, const ZArgs& a, hipStream_t st) {
-  if (a.n != L / 2) return hipErrorInvalidValue;
+  if (a.n < 1 || 2 * a.n - 1 > L || a.kp != L / 2 + 1) return hipErrorInvalidValue;
   if (fp == PREC_F64) return a.np_sel ? zpass_t<double, np_narrow<double>()>(a, st) : zpass_t<double, nps<double>()>(a, st);
   return a.np_sel ? zpass_t<float, np_narrow<float>()>(a, st) : zpass_t<float, nps<float>()>(a, st);
 }

@@ -20,6 +20,7 @@
 // deterministic.
 #include "cx.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace ori {
 namespace {
@@ -233,25 +234,26 @@ __global__ void __launch_bounds__(256) k_max(const double* __restrict__ v, int64
 }  // namespace
 
 hipError_t launch_field(const FieldArgs& a, bool far, hipStream_t st) {
+  hipError_t e = hipSuccess;
   if (a.n < 1 || a.n > kFieldMaxN || a.n * a.n * a.n != a.P) return hipErrorInvalidValue;  // the axis tables
   const dim3 grid(static_cast<unsigned>(a.nchunk), static_cast<unsigned>(a.mb), static_cast<unsigned>(a.nrhs));
   if (far)
-    hipLaunchKernelGGL((k_field_partial<true>), grid, dim3(kFieldThreads), 0, st, a);
+    e = launch_kernel((k_field_partial<true>), grid, dim3(kFieldThreads), st, a);
   else
-    hipLaunchKernelGGL((k_field_partial<false>), grid, dim3(kFieldThreads), 0, st, a);
-  hipError_t e = hipGetLastError();
+    e = launch_kernel((k_field_partial<false>), grid, dim3(kFieldThreads), st, a);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_field_finalize, dim3(static_cast<unsigned>((a.mb + 63) / 64), static_cast<unsigned>(a.nrhs)),
-                     dim3(64), 0, st, a, far ? 1 : 0);
-  return hipGetLastError();
+  e = launch_kernel(k_field_finalize, dim3(static_cast<unsigned>((a.mb + 63) / 64), static_cast<unsigned>(a.nrhs)),
+                     dim3(64), st, a, far ? 1 : 0);
+  return e;
 }
 
 hipError_t launch_charges(const void* D, const void* u, int64_t P, int64_t nrhs, void* q, hipStream_t st) {
+  hipError_t e = hipSuccess;
   int64_t g = (P + 255) / 256;
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_charges, dim3(static_cast<unsigned>(g), static_cast<unsigned>(nrhs)), dim3(256), 0, st,
+  e = launch_kernel(k_charges, dim3(static_cast<unsigned>(g), static_cast<unsigned>(nrhs)), dim3(256), st,
                      static_cast<const cxd*>(D), static_cast<const cxd*>(u), P, static_cast<cxd*>(q));
-  return hipGetLastError();
+  return e;
 }
 
 int64_t refraction_blocks(int64_t P) {
@@ -260,8 +262,9 @@ int64_t refraction_blocks(int64_t P) {
 }
 
 hipError_t launch_refraction(const RefractionArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_refraction, dim3(static_cast<unsigned>(refraction_blocks(a.P))), dim3(256), 0, st, a);
-  return hipGetLastError();
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_refraction, dim3(static_cast<unsigned>(refraction_blocks(a.P))), dim3(256), st, a);
+  return e;
 }
 
 int64_t max_blocks(int64_t P) {
@@ -270,12 +273,12 @@ int64_t max_blocks(int64_t P) {
 }
 
 hipError_t launch_cell_difference(const DiffArgs& a, int64_t P_coarse, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_cell_difference, dim3(static_cast<unsigned>(P_coarse)), dim3(kFieldThreads), 0, st, a);
-  hipError_t e = hipGetLastError();
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_cell_difference, dim3(static_cast<unsigned>(P_coarse)), dim3(kFieldThreads), st, a);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_max, dim3(static_cast<unsigned>(max_blocks(P_coarse))), dim3(256), 0, st, a.means, P_coarse,
+  e = launch_kernel(k_max, dim3(static_cast<unsigned>(max_blocks(P_coarse))), dim3(256), st, a.means, P_coarse,
                      part);
-  return hipGetLastError();
+  return e;
 }
 
 }  // namespace ori

@@ -68,7 +68,7 @@ int main(void) {
   CHECK(st == ORI_ERR_INVALID_ARG && ctx == NULL, "host pointer accepted (status %d)", (int)st);
   CHECK(strlen(ori_last_error(NULL)) > 0, "no error text");
   ori_grid bad = g;
-  bad.n = 7; /* 2n = 14 has no FFT plan */
+  bad.n = 513; /* beyond the largest planned length (n <= 512) */
   CHECK(ori_setup(&bad, k, h, N, u0, NULL, &ctx) == ORI_ERR_UNSUPPORTED, "unsupported n accepted");
 
   st = ori_setup(&g, k, h, N, u0, NULL, &ctx);

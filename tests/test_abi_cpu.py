@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_supported_lengths_match_header():
     text = open(HEADER).read()
-    m = re.search(r"2n in\s*\*\s*\{([0-9,\s*]+)\}", text)
+    m = re.search(r"L >= 2n - 1 from\s*\*\s*\{([0-9,\s*]+)\}", text)
     listed = [int(v) for v in re.findall(r"\d+", m.group(1))]
     assert listed == ori_build.supported_lengths()
 
@@ -67,13 +67,24 @@ def test_workspace_bytes_metric_size_fits_hbm():
 
 
 @pytest.mark.parametrize("n,status", [(0, ori.ORI_ERR_INVALID_ARG), (-3, ori.ORI_ERR_INVALID_ARG),
-                                      (7, ori.ORI_ERR_UNSUPPORTED), (11, ori.ORI_ERR_UNSUPPORTED),
-                                      (1024, ori.ORI_ERR_UNSUPPORTED)])
+                                      (513, ori.ORI_ERR_UNSUPPORTED), (1024, ori.ORI_ERR_UNSUPPORTED)])
 def test_bad_grid_rejected_on_host(n, status):
     with pytest.raises(ori.OriError) as e:
         ori.ori_workspace_bytes(n)
     assert e.value.status == status
     assert ori.ori_last_error() != "no error"
+
+
+@pytest.mark.parametrize("n,L", [(1, 2), (7, 16), (8, 16), (9, 20), (11, 24), (14, 32), (33, 80), (100, 256),
+                                 (256, 512), (257, 1024), (500, 1024), (512, 1024)])
+def test_any_n_up_to_512_pads_to_a_planned_length(n, L):
+    # every n <= 512 is accepted: the padded length is the shortest planned
+    # L >= 2n - 1 (the work arrays hold n*n*L + n*L*L elements per right-hand
+    # side and the spectrum octant (L/2 + 1)^3)
+    b = ori.ori_workspace_bytes(n, ori.ORI_PROVISION_FP64)
+    kp = L // 2 + 1
+    assert b >= (n * n * L + n * L * L) * 16 + kp ** 3 * 16 + 8 * n ** 3 * 16
+    assert b < (n * n * L + n * L * L) * 16 + kp ** 3 * 16 + 12 * n ** 3 * 16 + (1 << 24)
 
 
 def test_bad_side_and_null_grid():

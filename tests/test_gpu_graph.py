@@ -90,3 +90,41 @@ def test_graph_batch_and_adjoint():
             ori.ori_adjoint(ctx, u, f, gg, tol=1e-12, graph=graph)
             g.append(gg.cpu().numpy())
         assert np.array_equal(g[0], g[1])
+
+
+def test_graph_replay_in_concurrent_contexts():
+    # contexts driven from four threads at once, each building and replaying
+    # its own iteration graphs (graph replay on, the default), while a fifth
+    # thread allocates and frees device memory through torch: every result
+    # equals the same problem solved with eager launches in one thread, bit
+    # for bit, over three rounds
+    import random
+    import threading
+
+    say("[graph, threads] n in {12, 16, 20, 24}")
+    probs = []
+    for j, n in enumerate((12, 16, 20, 24)):
+        c = workloads.make_case(n, 4.0, seed=90 + j)
+        probs.append(dict(n=n, k=4.0, h=gpu(c["h"]), N=gpu(c["N"]), u0=gpu(c["u0"])))
+    ref = [ori.solve(p["n"], p["k"], p["h"], p["N"], p["u0"], tol=1e-10, graph=False)[0] for p in probs]
+    stop = threading.Event()
+
+    def churn():
+        rng = random.Random(5)
+        while not stop.is_set():
+            t = torch.empty(rng.randint(1, 64) << 18, dtype=torch.float32, device="cuda")
+            t.fill_(1.0)
+            del t
+            torch.cuda.empty_cache()
+
+    th = threading.Thread(target=churn)
+    th.start()
+    try:
+        for rnd in range(3):
+            res = ori.solve_many(probs, tol=1e-10, graph=True, max_workers=4)
+            for p, r, (u, info) in zip(probs, ref, res):
+                assert torch.equal(u, r), (rnd, p["n"])
+                assert info["rel_res_true"] < 1e-9
+    finally:
+        stop.set()
+        th.join()

@@ -329,4 +329,117 @@ def test_frozen_oracle_fixtures_reproduce():
         _, u, kappa = mk.compute(n, k, seed)
         ref = z[f"n{n}_u"]
         assert np.linalg.norm(u - ref) <= 1e-13 * np.linalg.norm(ref), n
-        assert abs(kappa - float(z[f"n{n}_kappa"])) <= 1e-10 * kappa, n
+        name = "kappa1" if mk.kappa_method(n) == "gecon" else "kappa"
+        assert abs(kappa - float(z[f"n{n}_{name}"])) <= 1e-10 * kappa, n
+
+
+# --- the residual sampler used at every size the dense LU cannot reach -------
+@pytest.mark.parametrize("n", [2, 3, 5, 6])
+def test_residual_sampler_equals_dense_residual(n, monkeypatch):
+    # r_q = u0_q - u_q - (G0 D u)_q is row q of u0 - A u with A = I + G0 D
+    # (eq. 2.19), for any u (here not a solution), on random rows; chunks
+    # smaller than P put the excluded self term in every position of a chunk
+    k = 3.1
+    pts, h, N, u0 = _varied_case(n, k, seed=40 + n, side=1.2, origin=(0.1, -0.3, 0.2))
+    D = O.coupling(h, N, n, 1.2)
+    A = O.system_matrix(pts, k, D)
+    rng = np.random.default_rng(50 + n)
+    P = n ** 3
+    u = rng.standard_normal(P) + 1j * rng.standard_normal(P)
+    rows = np.unique(np.concatenate([[0, P - 1], rng.integers(0, P, 6)]))
+    r_dense = (u0 - A @ u)[rows]
+    scale = np.max(np.abs(r_dense))
+    for chunk in (1 << 20, 7, 1):
+        r = O.sample_residual_rows(pts, k, D, u, u0, rows, chunk=chunk)
+        assert np.max(np.abs(r - r_dense)) <= 1e-13 * scale, chunk
+    # planted mistakes in the oracle, each of which this comparison must catch:
+    # the sign of the sum flipped, and u left out of the residual
+    real = O.ori_oracle.sample_scatter_rows
+    monkeypatch.setattr(O.ori_oracle, "sample_scatter_rows", lambda *a, **kw: -real(*a, **kw))
+    r_bad = O.sample_residual_rows(pts, k, D, u, u0, rows)
+    assert np.max(np.abs(r_bad - r_dense)) > 1e-3 * scale
+    # (the sum returned with u_q subtracted gives u0_q - (G0 D u)_q)
+    monkeypatch.setattr(O.ori_oracle, "sample_scatter_rows",
+                        lambda *a, **kw: real(*a, **kw) - np.asarray(a[3])[np.asarray(a[4])])
+    r_bad = O.sample_residual_rows(pts, k, D, u, u0, rows)
+    assert np.max(np.abs(r_bad - (u0 - (A - np.eye(P)) @ u)[rows])) <= 1e-13 * scale
+    assert np.max(np.abs(r_bad - r_dense)) > 1e-3 * scale
+
+
+def test_residual_sampler_vanishes_at_the_lu_solution():
+    # at the LU solution of eq. 2.19 every sampled residual row is at rounding level
+    n, k = 5, 4.4
+    pts, h, N, u0 = _varied_case(n, k, seed=61)
+    D = O.coupling(h, N, n)
+    u = O.solve_direct(O.system_matrix(pts, k, D), u0)
+    rows = np.arange(0, n ** 3, 9)
+    r = O.sample_residual_rows(pts, k, D, u, u0, rows, chunk=33)
+    assert np.max(np.abs(r)) <= 1e-13 * np.max(np.abs(u0))
+
+
+def test_parallel_rows_equal_serial_rows_bitwise():
+    # the multi-process mapper splits the rows only: each row's arithmetic is
+    # the single-process function's, so the results are bit for bit the same
+    n, k = 8, 2.2
+    pts, h, N, u0 = _varied_case(n, k, seed=62)
+    D = O.coupling(h, N, n)
+    rng = np.random.default_rng(63)
+    v = rng.standard_normal(n ** 3) + 1j * rng.standard_normal(n ** 3)
+    rows = rng.integers(0, n ** 3, 23)
+    s = O.sample_scatter_rows(pts, k, D, v, rows, chunk=100)
+    sp, w = O.sample_rows_parallel(pts, k, D, v, rows, workers=4, chunk=100)
+    assert w == 4 and np.array_equal(s, sp)
+    r = O.sample_residual_rows(pts, k, D, v, u0, rows, chunk=100)
+    rp, _ = O.sample_rows_parallel(pts, k, D, v, rows, u0=u0, workers=3, chunk=100)
+    assert np.array_equal(r, rp)
+
+
+# --- the condition number of the system ---------------------------------------
+def _two_per_side_spectrum(side, k, h, N):
+    # n = 2 with constant h and N: the 8 points are the corners of a cube of
+    # edge a = side/2 and G0 = sum_v g(a |v|) T_v over the 7 nonzero v in
+    # {0,1}^3, T_v the permutation x -> x xor v.  These commute and share the
+    # real orthogonal eigenvectors chi_s(x) = (-1)^(s.x); so A = I + D G0 is
+    # normal with eigenvalues mu_s = 1 + D sum_v g(a |v|) (-1)^(s.v), its
+    # singular values are |mu_s|, and A^-1 = sum_v b_v T_v with
+    # b_v = (1/8) sum_s (-1)^(s.v) / mu_s.
+    a = side / 2.0
+
+    def g(r):
+        return complex(math.cos(k * r), math.sin(k * r)) / (4 * math.pi * r)
+
+    Dc = 4 * math.pi * h * N * a ** 3
+    bits = lambda x: bin(x).count("1")
+    mu = [1.0 + Dc * sum(g(a * math.sqrt(bits(v))) * (-1) ** bits(s & v) for v in range(1, 8)) for s in range(8)]
+    a_v = [1.0] + [Dc * g(a * math.sqrt(bits(v))) for v in range(1, 8)]
+    b_v = [sum((-1) ** bits(s & v) / mu[s] for s in range(8)) / 8 for v in range(8)]
+    return mu, a_v, b_v
+
+
+@pytest.mark.parametrize("side,k,h,N", [(1.0, 1.0, -1 + 0.5j, 1.0), (1.3, 4.0, 0.7 - 2.0j, 2.5),
+                                        (0.2, 11.0, -30 + 1j, 0.25), (1.0, 2.0, -40 + 3j, 1.0)])
+def test_condition_number_closed_form_two_per_side(side, k, h, N):
+    mu, a_v, b_v = _two_per_side_spectrum(side, k, h, N)
+    pts = O.cell_points(2, side=side, origin=(0.4, -1.0, 2.0))
+    A = O.system_matrix(pts, k, O.coupling(np.full(8, h), np.full(8, N), 2, side))
+    kappa2 = max(abs(m) for m in mu) / min(abs(m) for m in mu)
+    assert abs(O.condition_number(A) - kappa2) <= 1e-12 * kappa2
+    # the 1-norm: every column of A (of A^-1) holds the values a_v (b_v), so
+    # kappa_1 = sum |a_v| * sum |b_v|; LAPACK's estimate is a lower bound of it
+    # that is exact or close on such small matrices
+    kappa1 = sum(abs(x) for x in a_v) * sum(abs(x) for x in b_v)
+    est = O.condition_number(A, "gecon")
+    assert kappa1 / 3.0 <= est <= kappa1 * (1 + 1e-12)
+    # a transposed or dropped coupling would change the spectrum: the
+    # identity (no particles) has condition number 1
+    assert abs(O.condition_number(np.eye(8, dtype=complex)) - 1.0) <= 1e-15
+
+
+def test_condition_number_single_cube_and_scaling():
+    # n = 1 gives A = [1]; a scaled identity and a diagonal matrix have the
+    # obvious condition numbers
+    A = O.system_matrix(O.cell_points(1), 2.0, O.coupling(np.array([-1 + 0.5j]), None, 1))
+    assert O.condition_number(A) == 1.0
+    d = np.array([3.0, -0.5j, 2.0 + 2.0j, 0.25])
+    assert abs(O.condition_number(np.diag(d)) - 3.0 / 0.25) <= 1e-13 * 12
+    assert abs(O.condition_number(np.diag(d), "gecon") - 3.0 / 0.25) <= 1e-13 * 12
