@@ -206,6 +206,26 @@ ori_status ori_gradient(ori_ctx ctx, const ori_solve_opts* opts, const void* u_t
  * stay complex128).  Used by tests and the benchmark. */
 ori_status ori_matvec(ori_ctx ctx, int32_t op, int32_t precision, const void* x, void* y);
 
+/* y = G0 x, the same product as ori_matvec(ctx, ORI_OP_GREEN, precision, x,
+ * y) on a context of grid g loaded with wave number k, for callers that
+ * cannot allocate device memory: code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc.  No context is needed and nothing
+ * is allocated: the kernel spectrum, the twiddle tables and the FFT work
+ * arrays live in one static device array of 32 MiB that the library holds
+ * on every device it runs on until the process ends, which limits n to 64
+ * (larger n give ORI_ERR_UNSUPPORTED with the bytes needed).  x, y: device
+ * complex128[P] of the current device (P = n^3), caller owned.  precision:
+ * ORI_FP64 or ORI_MIXED (complex64 FFT stages).  Every step -- twiddles,
+ * the spectrum of k, the five FFT passes -- is enqueued on `stream` (a
+ * hipStream_t, or NULL) with kernel launches only (no memset, copy or
+ * synchronization), and the call returns without waiting: y is ready once
+ * the stream's work is.  Every call on a device shares that device's
+ * array, so calls whose work overlaps on one device (other streams, other
+ * threads) race and must be ordered by the caller.  Errors are returned
+ * before anything is enqueued; ori_last_error(NULL) gives the text. */
+ori_status ori_green_noalloc(const ori_grid* g, double k, int32_t precision, const void* x, void* y,
+                             void* stream);
+
 /* ---- what the solution is used for (Section 2, Section 4) ---------------- */
 
 /* Charges of the cells: q_p = -D_p u_p = -c_S h_p N_p |Delta_p| u_p, the sum

@@ -14,7 +14,7 @@ import os
 
 __all__ = [
     "OriError", "lib", "Grid", "SolveOpts", "SolveInfo", "Layout", "Context",
-    "ori_setup", "ori_create", "ori_load", "ori_spectrum_cache", "ori_solve", "ori_matvec", "ori_destroy",
+    "ori_setup", "ori_create", "ori_load", "ori_spectrum_cache", "ori_solve", "ori_matvec", "ori_green_noalloc", "ori_destroy",
     "ori_adjoint", "ori_gradient", "OriSolve", "ori_batch_info",
     "ori_charges", "ori_scattered_field", "ori_far_field",
     "ori_refraction_index", "ori_design_impedance", "ori_interpolation_difference",
@@ -100,6 +100,7 @@ def lib():
             "ori_setup": (ctypes.c_int, [ctypes.POINTER(Grid), D, P, P, P, P, ctypes.POINTER(P)]),
             "ori_solve": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo)]),
             "ori_matvec": (ctypes.c_int, [P, I32, I32, P, P]),
+            "ori_green_noalloc": (ctypes.c_int, [ctypes.POINTER(Grid), D, I32, P, P, P]),
             "ori_adjoint": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), P, P, P, P, ctypes.POINTER(SolveInfo)]),
             "ori_gradient": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), P, P, ctypes.POINTER(D), P,
                                             ctypes.POINTER(SolveInfo)]),
@@ -305,6 +306,18 @@ def ori_matvec(ctx, x, y, op=ORI_OP_SYSTEM, precision=ORI_FP64):
     import torch
     _check(lib().ori_matvec(ctx.handle, int(op), int(precision), _dev(x, torch.complex128, ctx.nrhs * ctx.P, "x"),
                             _dev(y, torch.complex128, ctx.nrhs * ctx.P, "y")), ctx)
+
+
+def ori_green_noalloc(n, k, x, y, precision=ORI_FP64, side=1.0, origin=(0.0, 0.0, 0.0), cell_offset=0.5,
+                      stream=None):
+    """y = G0 x (complex128 CUDA tensors, n^3 entries) without a context and
+    without allocating (static device workspace, n <= 64).  The work is
+    enqueued on the stream and not waited for."""
+    import torch
+    P = int(n) ** 3
+    _check(lib().ori_green_noalloc(ctypes.byref(_grid(n, side, origin, cell_offset)), float(k), int(precision),
+                                   _dev(x, torch.complex128, P, "x"), _dev(y, torch.complex128, P, "y"),
+                                   _stream(stream)))
 
 
 def ori_batch_info(ctx, i):

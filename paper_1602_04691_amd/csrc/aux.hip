@@ -370,6 +370,23 @@ __global__ void __launch_bounds__(256) k_sub_mul(const cxd* __restrict__ f, cons
   ORI_RHS_LOOP(i) y[i] = f[i] - s[i] * x[i];
 }
 
+// Twiddles exp(-2 pi i m / L), m < L, in FP64 and FP32, exact at the
+// quarter turns (the device counterpart of the host's long double table).
+__global__ void __launch_bounds__(256) k_twiddles(int64_t L, cxd* __restrict__ twd, cxf* __restrict__ twf) {
+  const int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= L) return;
+  double cs, sn;
+  if ((4 * m) % L == 0) {
+    const int64_t q = 4 * m / L;
+    cs = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+    sn = q == 1 ? 1.0 : (q == 3 ? -1.0 : 0.0);
+  } else {
+    sincospi(2.0 * static_cast<double>(m) / static_cast<double>(L), &sn, &cs);
+  }
+  twd[m] = cxd{cs, -sn};
+  twf[m] = cxf{static_cast<float>(cs), static_cast<float>(-sn)};
+}
+
 unsigned grid_for(int64_t P, int threads, int64_t cap) {
   int64_t g = (P + threads - 1) / threads;
   if (g > cap) g = cap;
@@ -496,6 +513,13 @@ hipError_t launch_sub_mul(const void* f, const void* s, const void* x, void* lam
   hipError_t e = hipSuccess;
   e = launch_kernel(k_sub_mul, dim3(grid_for(P, 256, 8192)), dim3(256), st, static_cast<const cxd*>(f),
                      static_cast<const cxd*>(s), static_cast<const cxd*>(x), static_cast<cxd*>(lam), P);
+  return e;
+}
+
+hipError_t launch_twiddles(int64_t L, void* twd, void* twf, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  e = launch_kernel(k_twiddles, dim3(static_cast<unsigned>((L + 255) / 256)), dim3(256), st, L, static_cast<cxd*>(twd),
+                    static_cast<cxf*>(twf));
   return e;
 }
 

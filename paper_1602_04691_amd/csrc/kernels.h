@@ -274,6 +274,8 @@ hipError_t launch_conj_diff(const void* u, const void* t, void* f, int64_t P, do
 // g = alpha * c * u * q  (c real)
 hipError_t launch_gradient(const double* c, const void* u, const void* q, double alpha, void* g, int64_t P,
                            hipStream_t st);
+// twd[m] = exp(-2 pi i m / L) (complex128) and twf[m] the same in complex64, m < L
+hipError_t launch_twiddles(int64_t L, void* twd, void* twf, hipStream_t st);
 // lam = f - s * x
 hipError_t launch_sub_mul(const void* f, const void* s, const void* x, void* lam, int64_t P, hipStream_t st);
 

@@ -1006,6 +1006,64 @@ ori_status refraction(ori_ctx c, double k, double c_s, const void* n0, const voi
                    design ? "<=" : "<");
   return ORI_OK;
 }
+// ---------------------------------------------------------------------------
+// The Green's product without allocation (ori_green_noalloc): every
+// workspace of the product -- the work arrays, the spectrum octant and the
+// twiddle tables -- is a slice of one static device array.
+// ---------------------------------------------------------------------------
+constexpr int64_t kStaticBytes = int64_t{32} << 20;  // 32 MiB per device
+constexpr int kMaxStaticDevices = 64;
+
+struct StaticLayout {
+  int64_t arena, kh, khf, twd, twf, total;
+};
+
+// The context layout_for gives one right-hand side, restricted to what the
+// product needs: the arena (A and B, also the spectrum passes' octant
+// scratch), the octant and its complex64 copy, and the two twiddle tables.
+StaticLayout static_layout(int64_t n, int64_t L, bool mixed) {
+  const int64_t kp = L / 2 + 1;
+  StaticLayout s{};
+  s.arena = 0;
+  s.kh = align_up(std::max<int64_t>(n * n * L + n * L * L, kp * kp * kp) * 16);
+  s.khf = s.kh + align_up(kp * kp * kp * 16);
+  s.twd = s.khf + (mixed ? align_up(kp * kp * kp * 8) : 0);
+  s.twf = s.twd + align_up(L * 16);
+  s.total = s.twf + align_up(L * 8);
+  return s;
+}
+
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices] = {};
+
+}  // namespace
+
+// The array itself.  In host code its name is only a stand-in: kernels get
+// the device address that hipGetSymbolAddress returns for the current
+// device, kept per device in g_static_ptr.
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+// Device address of the static array on device dev (looked up once per
+// device, with that device current).
+ori_status static_workspace(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxStaticDevices)
+    return set_err(nullptr, ORI_ERR_UNSUPPORTED, "device %d: the static workspace covers devices 0..%d", dev,
+                   kMaxStaticDevices - 1);
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_err(nullptr, ORI_ERR_DEVICE, "hipGetSymbolAddress of the static workspace failed: %s",
+                     hipGetErrorString(e));
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return ORI_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1304,6 +1362,55 @@ ori_status ori_interpolation_difference(ori_ctx c, const void* y, const void* x_
   for (double v : part) m = std::max(m, v);
   *diff = m;
   return ORI_OK;
+}
+
+ori_status ori_green_noalloc(const ori_grid* g, double k, int32_t precision, const void* x, void* y, void* stream) {
+  int64_t L = 0;
+  ORI_TRY(check_grid(g, &L));
+  if (!(k > 0.0) || !std::isfinite(k)) return set_err(nullptr, ORI_ERR_INVALID_ARG, "k must be finite and > 0");
+  if (precision != ORI_FP64 && precision != ORI_MIXED) return set_err(nullptr, ORI_ERR_INVALID_ARG, "bad precision");
+  const bool mixed = precision == ORI_MIXED;
+  const StaticLayout sl = static_layout(g->n, L, mixed);
+  if (sl.total > kStaticBytes)
+    return set_err(nullptr, ORI_ERR_UNSUPPORTED,
+                   "n = %lld needs %lld bytes of workspace; the static workspace holds %lld (n <= 64)",
+                   (long long)g->n, (long long)sl.total, (long long)kStaticBytes);
+  const LengthKernels* K = kernels_for_length(static_cast<int>(L));
+  if (!K) return set_err(nullptr, ORI_ERR_UNSUPPORTED, "no kernels for padded length %lld", (long long)L);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_err(nullptr, ORI_ERR_DEVICE, "hipGetDevice failed (no GPU?)");
+  void* base = nullptr;
+  ORI_TRY(static_workspace(dev, &base));
+  // A context on the stack that owns nothing: its workspaces are slices of
+  // the static array, and it is never destroyed through ori_destroy.
+  ori_ctx_s c;
+  c.grid = *g;
+  c.n = g->n;
+  c.L = L;
+  c.P = g->n * g->n * g->n;
+  c.nrhs = 1;
+  c.provision = ORI_PROVISION_FP64 | (mixed ? ORI_PROVISION_MIXED : 0);
+  c.k = k;
+  c.device = dev;
+  c.K = K;
+  c.stream = static_cast<hipStream_t>(stream);
+  choose_layout(&c);
+  char* b = static_cast<char*>(base);
+  c.arena = b + sl.arena;
+  c.kh = reinterpret_cast<cxd*>(b + sl.kh);
+  c.khf = mixed ? reinterpret_cast<cxf*>(b + sl.khf) : nullptr;
+  c.twd = reinterpret_cast<cxd*>(b + sl.twd);
+  c.twf = reinterpret_cast<cxf*>(b + sl.twf);
+  ori_status st = check_dev_ptr(&c, x, c.P * 16, "x");
+  if (st == ORI_OK) st = check_dev_ptr(&c, y, c.P * 16, "y");
+  if (st == ORI_OK)
+    st = launch(&c, K_ELEMWISE, PREC_F64, [&] { return launch_twiddles(L, c.twd, c.twf, c.stream); });
+  if (st == ORI_OK) st = compute_spectrum(&c);
+  if (st == ORI_OK)
+    st = matvec(&c, PREC_F64, mixed ? PREC_F32 : PREC_F64, plain_f1(x, nullptr),
+                epi(y, nullptr, 0.0, nullptr, 0.0, nullptr, 1.0, nullptr, 0), nullptr);
+  if (st != ORI_OK) g_last_error = c.err;
+  return st;
 }
 
 ori_status ori_get_layout(ori_ctx c, int32_t precision, ori_layout* out) {
