@@ -14,10 +14,21 @@
 // adjacent strided pencils); the stages in between exchange through LDS.
 #pragma once
 
+#include <type_traits>
+
 #include "cx.h"
 #include "plan.h"
 
 namespace ori {
+
+// f(integral_constant<int, I>) for I = 0 .. N-1
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void unroll(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    unroll<N, I + 1>(f);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // DFT butterflies, natural order in and out.  Forward uses exp(-2 pi i/R).
@@ -203,6 +214,20 @@ struct Stages {
     return true;
   }
   static_assert(NS > 0 && ns(NS) == L && radices_ok(), "plan must factor L into radices 2, 3, 4, 5, 8, 16");
+  // Largest twiddle table index any stage reads: the powers r = 1, 2, 4, 8
+  // below R of w^(k TS), k < ns(s), TS = L / (ns(s) R).  Below L/2 when every
+  // radix is a power of two, so a table staged in LDS can stop there.
+  static constexpr int max_twiddle_index() {
+    int m = 0;
+    for (int s = 1; s < NS; ++s) {
+      const int R = radix(s), TS = L / (ns(s) * R);
+      int p = 1;
+      while (p * 2 < R) p *= 2;
+      const int v = p * (ns(s) - 1) * TS;
+      if (v > m) m = v;
+    }
+    return m;
+  }
 };
 
 // One thread's view of its pencil in LDS.  Strided passes interleave NP
@@ -211,15 +236,39 @@ struct Stages {
 // passes keep each pencil in one row with one padding slot after every 8
 // elements (element e at base[e + e / 8]), which breaks the power-of-two
 // strides of the Stockham writes across the LDS banks.
+//
+// Narrow interleaves (NP pencils of fewer than 128 bytes per element row)
+// add one padding row after every 8 rows (element e at base[(e + e/8) es],
+// pad = 1).  A group of lanes served together then spans two butterflies b
+// and b + 1 of its NP pencils: their rows differ by 1 in every read and in
+// every write after the first stage, and by the radix R = 8 in the first
+// stage's writes, which the padding turns into 9 -- an odd number of rows,
+// so the two runs fall on disjoint banks instead of the same ones.  Every
+// offset between the accesses of one thread stays a compile-time constant.
 template <typename T>
 struct LdsPencil {
   cx<T>* base;
-  int es;  // 0: padded contiguous row; otherwise the interleave stride
-  __device__ __forceinline__ cx<T>& at(int e) const { return es ? base[e * es] : base[e + (e >> 3)]; }
+  int es;   // 0: padded contiguous row; otherwise the interleave stride
+  int pad;  // interleave: one padding row after every 8 rows
+  __device__ __forceinline__ cx<T>& at(int e) const {
+    return es ? base[(pad ? e + (e >> 3) : e) * es] : base[e + (e >> 3)];
+  }
+  // Element b + C for a compile-time C.  SPLIT: the caller guarantees
+  // (b + C) / 8 = b / 8 + C / 8 (C a multiple of 8, or b % 8 + C % 8 < 8),
+  // so the padded position is the thread's own b + b / 8 plus a constant,
+  // and every access of a butterfly shares one address register.
+  template <int C, bool SPLIT>
+  __device__ __forceinline__ cx<T>& at(int b) const {
+    if (es && !pad) return base[(b + C) * es];
+    const int row = SPLIT ? b + (b >> 3) + (C + (C >> 3)) : (b + C) + ((b + C) >> 3);
+    return es ? base[row * es] : base[row];
+  }
 };
 
 // LDS slots of one padded contiguous pencil row
 constexpr int padded_row(int L) { return L + L / 8; }
+// LDS rows of an interleave of length L, with or without the padding rows
+constexpr int interleave_rows(int L, bool pad) { return pad ? L + L / 8 : L; }
 
 enum Keep : int { KEEP_ALL = 0, KEEP_HALF = 1, KEEP_HALF1 = 2 };
 
@@ -229,11 +278,43 @@ struct Regs {
   cx<T> v[C][R];
 };
 
-template <typename T, int L, bool INV, int TP = threads_per_pencil(L), int PV = 0>
+// TWM selects where the twiddles of a stage come from:
+//  0: tw is the length-L table exp(-2 pi i m / L); the powers w, w^2, w^4,
+//     w^8 are read, the other powers are products of two of them;
+//  1: tw is the stage-major table (stage_table): every power w^r of every
+//     k is read, no products (fewer vector instructions, more table).
+template <typename T, int L, bool INV, int TP = threads_per_pencil(L), int PV = 0, int TWM = 0>
 struct Engine {
   using St = Stages<L, INV, TP, PV>;
   static constexpr int NS = St::NS;
   static constexpr int TPP = St::TPP;
+
+  // Stage-major twiddle table: stage s >= 1 holds w^(r k TS) for r = 1..R-1
+  // and k < ns(s) (TS = L / (ns(s) R)) at stage_offset(s) + (r - 1) ns(s) + k,
+  // forward sign (the inverse conjugates on use).  Consecutive k of one r are
+  // adjacent, so the lanes of a wavefront read adjacent entries.
+  static constexpr int stage_offset(int s) {
+    int o = 0;
+    for (int q = 1; q < s; ++q) o += (St::radix(q) - 1) * St::ns(q);
+    return o;
+  }
+  static constexpr int stage_table_size() { return stage_offset(NS); }
+
+  // Fill the stage-major table from the length-L table (every thread of the
+  // workgroup takes entries tid, tid + nthreads, ... of each stage).
+  __device__ __forceinline__ static void build_stage_table(cx<T>* dst, const cx<T>* __restrict__ tw_full, int tid,
+                                                           int nthreads) {
+    unroll<NS>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      if constexpr (q >= 1) {
+        constexpr int nsq = St::ns(q), R = St::radix(q), TS = L / (nsq * R);
+        for (int idx = tid; idx < (R - 1) * nsq; idx += nthreads) {
+          const int r = idx / nsq + 1, k = idx % nsq;
+          dst[stage_offset(q) + idx] = tw_full[r * k * TS];
+        }
+      }
+    });
+  }
 
   template <int s>
   using RegsOf = Regs<T, St::cnt(s), St::radix(s)>;
@@ -269,7 +350,12 @@ struct Engine {
       if constexpr (NSs > 1) {
         const int k = b % NSs;
         cx<T> w[R];
-        twiddles<R, TS>(w, k, tw);
+        if constexpr (TWM == 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) w[r] = tw[stage_offset(s) + (r - 1) * NSs + k];
+        } else {
+          twiddles<R, TS>(w, k, tw);
+        }
 #pragma unroll
         for (int r = 1; r < R; ++r) g.v[i][r] = twiddle<INV>(g.v[i][r], w[r]);
       }
@@ -292,8 +378,13 @@ struct Engine {
       if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
       const int k = b % NSs;
       const int base = (b - k) * R + k;
-#pragma unroll
-      for (int j = 0; j < R; ++j) p.at(base + j * NSs) = g.v[i][j];
+      // (base + j NSs) / 8 splits when NSs is a multiple of 8, or in the
+      // first stage (NSs = 1, base = b R) for a power-of-two R
+      constexpr bool SPLIT = NSs % 8 == 0 || (NSs == 1 && (R & (R - 1)) == 0);
+      unroll<R>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        p.template at<j * NSs, SPLIT>(base) = g.v[i][j];
+      });
     }
   }
 
@@ -306,8 +397,10 @@ struct Engine {
     for (int i = 0; i < St::cnt(s); ++i) {
       const int b = bt + i * TPP;
       if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
-#pragma unroll
-      for (int r = 0; r < R; ++r) g.v[i][r] = p.at(b + r * STRIDE);
+      unroll<R>([&](auto J) {
+        constexpr int r = decltype(J)::value;
+        g.v[i][r] = p.template at<r * STRIDE, STRIDE % 8 == 0>(b);
+      });
     }
   }
 
@@ -336,6 +429,49 @@ struct Engine {
     }
   }
 
+  // The same loads with the index of each value in the thread's registers:
+  // load(slot, e), slot = i * R0 + r (a compile-time constant once unrolled).
+  template <bool HALF_IN, class Load>
+  __device__ __forceinline__ static void load_first_slots(RegsOf<0>& g, int bt, Load&& load) {
+    constexpr int R = St::radix(0);
+    constexpr int STRIDE = L / R;
+    constexpr bool SKIP = HALF_IN && (R % 2 == 0);
+#pragma unroll
+    for (int i = 0; i < St::cnt(0); ++i) {
+      const int b = bt + i * TPP;
+      if (St::nbf(0) % TPP != 0 && b >= St::nbf(0)) continue;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (SKIP && r >= R / 2) {
+          g.v[i][r] = cx<T>{};
+        } else if (HALF_IN && !SKIP) {
+          const int e = b + r * STRIDE;
+          g.v[i][r] = e < L / 2 ? load(i * R + r, e) : cx<T>{};
+        } else {
+          g.v[i][r] = load(i * R + r, b + r * STRIDE);
+        }
+      }
+    }
+  }
+
+  // Every element index e that load_first<HALF_IN> reads, with its slot:
+  // f(slot, e) (slots as in load_first_slots).
+  template <bool HALF_IN, class F>
+  __device__ __forceinline__ static void first_slots(int bt, F&& f) {
+    constexpr int R = St::radix(0);
+    constexpr int STRIDE = L / R;
+#pragma unroll
+    for (int i = 0; i < St::cnt(0); ++i) {
+      const int b = bt + i * TPP;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = b + r * STRIDE;
+        if (HALF_IN && (R % 2 == 0) && r >= R / 2) continue;
+        f(i * R + r, e);
+      }
+    }
+  }
+
   // Last-stage outputs to a functor: store(e, value) for e = b + j L/R_last.
   // KEEP selects the outputs: KEEP_ALL, KEEP_HALF (e < L/2: the discarded
   // half of a padded inverse is never written) or KEEP_HALF1 (e <= L/2: the
@@ -356,6 +492,46 @@ struct Engine {
         if (KEEP == KEEP_HALF && e >= L / 2) continue;
         if (KEEP == KEEP_HALF1 && e > L / 2) continue;
         store(e, g.v[i][j]);
+      }
+    }
+  }
+
+  // The same stores with the slot of each value: store(slot, e, value),
+  // slot = i * R_last + j.
+  template <int KEEP, class Store>
+  __device__ __forceinline__ static void store_last_slots(const RegsOf<NS - 1>& g, int bt, Store&& store) {
+    constexpr int s = NS - 1;
+    constexpr int R = St::radix(s);
+    constexpr int STRIDE = L / R;
+#pragma unroll
+    for (int i = 0; i < St::cnt(s); ++i) {
+      const int b = bt + i * TPP;
+      if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int e = b + j * STRIDE;
+        if (KEEP == KEEP_HALF && (R % 2 == 0) && j >= R / 2) continue;
+        if (KEEP == KEEP_HALF && e >= L / 2) continue;
+        if (KEEP == KEEP_HALF1 && e > L / 2) continue;
+        store(i * R + j, e, g.v[i][j]);
+      }
+    }
+  }
+
+  // Every element index e that store_last<KEEP> may write (bounds on b
+  // aside), with its slot: f(slot, e).
+  template <int KEEP, class F>
+  __device__ __forceinline__ static void last_slots(int bt, F&& f) {
+    constexpr int s = NS - 1;
+    constexpr int R = St::radix(s);
+    constexpr int STRIDE = L / R;
+#pragma unroll
+    for (int i = 0; i < St::cnt(s); ++i) {
+      const int b = bt + i * TPP;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (KEEP == KEEP_HALF && (R % 2 == 0) && j >= R / 2) continue;
+        f(i * R + j, b + j * STRIDE);
       }
     }
   }

@@ -74,6 +74,40 @@ __device__ __forceinline__ void block_partials(double (&v)[4], void* lds_scratch
   }
 }
 
+// Raw buffer accesses: the base address in a buffer resource (scalar
+// registers; no stride, num_records bytes of range, dword 3 as on every
+// gfx9 part) and a 32-bit byte offset per lane, so that per-tile address
+// arithmetic stays off the vector ALU.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, int32_t bytes) {
+  // the base is uniform over the workgroup: read it from the first lane so
+  // that the resource is built in scalar registers
+  const uint64_t b = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+  void* p = reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, 0, bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0));
+  } else {
+    return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t off, cx<T> v) {
+  using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+  using V2 = __attribute__((ext_vector_type(2))) unsigned int;
+  if constexpr (sizeof(T) == 8) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, static_cast<int>(off), 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, static_cast<int>(off), 0, 0);
+  }
+}
+
 __device__ __forceinline__ int64_t two_level(int64_t o, int lg, int64_t hi, int64_t lo) {
   return (o >> lg) * hi + (o & ((int64_t{1} << lg) - 1)) * lo;
 }
@@ -213,7 +247,8 @@ __device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t G) {
 
 template <typename T, int NP, bool INV, bool HIN, bool HOUT, bool EX>
 __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
-  __shared__ cx<T> lds[NP * L];
+  constexpr bool PADL = NP * int(sizeof(cx<T>)) < 128 && L <= 512;  // narrow interleave: padding rows (LdsPencil)
+  __shared__ cx<T> lds[NP * interleave_rows(L, PADL)];
   using E = Engine<T, L, INV>;
   const int tid = threadIdx.x;
   const int t = tid % NP, bt = tid / NP;
@@ -244,7 +279,7 @@ __global__ void __launch_bounds__(NP * TPP) k_strided(StridedArgs a) {
   };
   typename E::template RegsOf<0> g;
   E::template load_first<HIN>(g, bt, load);
-  LdsPencil<T> lp{lds + t, NP};
+  LdsPencil<T> lp{lds + t, NP, PADL ? 1 : 0};
   E::template run<HIN>(g, bt, lp, tw, [&](auto& gl) {
     E::template store_last<HOUT ? KEEP_HALF : KEEP_ALL>(gl, bt, [&](int e, cx<T> v) {
       if constexpr (HOUT && !EX) {
@@ -281,13 +316,13 @@ constexpr int z_tpp() {
 }
 
 // Waves per SIMD that the register allocation must allow.  At L = 512 the
-// complex64 pass on 512-thread workgroups (36 KB of LDS) fits three
-// workgroups per CU once it stays within 80 VGPRs (it needs 81
-// unconstrained, which allows two): 0.366 vs 0.441 ms at n = 256.  At other
-// lengths the same bound spills.
+// complex64 pass on 512-thread workgroups fits three workgroups per CU
+// within 80 VGPRs: 0.366 vs 0.441 ms at n = 256 when it needed 81 (it now
+// needs 59, and four workgroups fit its LDS).
 template <typename T, int NP, bool PF>
 constexpr int z_min_waves() {
-  return (L == 512 && sizeof(T) == 4 && !PF && NP * z_tpp<T>() == 512) ? 6 : 1;
+  if (L == 512 && sizeof(T) == 4 && !PF && NP * z_tpp<T>() == 512) return 6;
+  return 1;
 }
 
 // plan variant of the Z pass (plan.h: radix_plan(L, variant))
@@ -296,23 +331,39 @@ constexpr int z_plan() {
   return sizeof(T) == 8 ? 1 : 0;
 }
 
+// Twiddle source of the Z pass (fft_engine.h, TWM): the complex64 pass is
+// bound by vector instructions, so up to L = 512 it reads every power of
+// each twiddle from a stage-major table in LDS instead of multiplying two
+// of them; the complex128 pass keeps the short table (its LDS is full).
 template <typename T>
-using ZRegs = typename Engine<T, L, false, z_tpp<T>(), z_plan<T>()>::template RegsOf<
+constexpr int z_twm() {
+  return (sizeof(T) == 4 && L <= 512) ? 1 : 0;
+}
+
+template <typename T>
+using ZRegs = typename Engine<T, L, false, z_tpp<T>(), z_plan<T>(), z_twm<T>()>::template RegsOf<
     Stages<L, false, z_tpp<T>(), z_plan<T>()>::NS - 1>;
 
 template <typename T, int NP, bool PF, bool EX>
 __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k_zpass(ZArgs a) {
   constexpr int half = L / 2;
   constexpr int ZT = z_tpp<T>();
-  using EF = Engine<T, L, false, ZT, z_plan<T>()>;
-  using EI = Engine<T, L, true, ZT, z_plan<T>()>;
+  constexpr int TWM = z_twm<T>();
+  using EF = Engine<T, L, false, ZT, z_plan<T>(), TWM>;
+  using EI = Engine<T, L, true, ZT, z_plan<T>(), TWM>;
   using St = Stages<L, false, ZT, z_plan<T>()>;
   using G0 = typename EF::template RegsOf<0>;
   constexpr int SL = St::NS - 1;
   constexpr int RL = St::radix(SL);
   constexpr int STRIDE = L / RL;
   constexpr int64_t CT = (L + NP - 1) / NP;
-  __shared__ cx<T> lds[NP * L];
+  // NP interleaved pencils, with padding rows when a row of the interleave
+  // is narrower than 128 bytes (the lanes served together then span two
+  // butterflies; see LdsPencil).  Up to L = 512 only: longer pencils give a
+  // thread several butterflies per stage, whose padded rows each take an
+  // address register (at L = 1024 the pass then loses occupancy).
+  constexpr bool PADL = NP * int(sizeof(cx<T>)) < 128 && L <= 512;
+  __shared__ cx<T> lds[NP * interleave_rows(L, PADL)];
   const int tid = threadIdx.x;
   const int t = tid % NP, bt = tid / NP;
   // workgroup w takes right-hand-side slice w % RS of the tile w / RS, so the
@@ -334,16 +385,40 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
   const int64_t r_lo = static_cast<int64_t>(slice) * rper;
   const int64_t r_hi = r_lo + rper < a.nrhs ? r_lo + rper : a.nrhs;
   const cx<T>* __restrict__ kh = static_cast<const cx<T>*>(a.khat);
-  // The twiddle table is staged in LDS: read from global memory inside a
-  // stage, a twiddle would wait behind every tile load still in flight
-  // (vector-memory completions are counted in order).
-  __shared__ cx<T> twl[L];
+  // The twiddles are staged in LDS: read from global memory inside a stage,
+  // a twiddle would wait behind every tile load still in flight
+  // (vector-memory completions are counted in order).  TWM 0: the entries of
+  // the length-L table the stages read (below L/2 for power-of-two
+  // radices); TWM 1: the stage-major tables of the forward and inverse
+  // transforms (one table when the plan reads the same forwards and
+  // backwards).
+  constexpr bool SAME_TW = [] {
+    for (int q = 0; q < EF::NS; ++q)
+      if (EF::St::radix(q) != EI::St::radix(q)) return false;
+    return true;
+  }();
+  constexpr int NTW0 = (EF::St::max_twiddle_index() > EI::St::max_twiddle_index() ? EF::St::max_twiddle_index()
+                                                                                   : EI::St::max_twiddle_index()) + 1;
+  constexpr int NTW_F = TWM ? EF::stage_table_size() : NTW0;
+  constexpr int NTW_I = TWM ? (SAME_TW ? 0 : EI::stage_table_size()) : 0;
+  __shared__ cx<T> twl[NTW_F + NTW_I > 0 ? NTW_F + NTW_I : 1];
   {
     const cx<T>* __restrict__ src = static_cast<const cx<T>*>(a.tw);
-    for (int i = tid; i < L; i += NP * ZT) twl[i] = src[i];
+    if constexpr (TWM) {
+      EF::build_stage_table(twl, src, tid, NP * ZT);
+      if constexpr (!SAME_TW) EI::build_stage_table(twl + NTW_F, src, tid, NP * ZT);
+    } else {
+      for (int i = tid; i < NTW0; i += NP * ZT) twl[i] = src[i];
+    }
   }
   const cx<T>* tw = twl;
+  const cx<T>* twi = (TWM && !SAME_TW) ? twl + NTW_F : twl;
   cx<T>* buf = static_cast<cx<T>*>(a.buf);
+  // the spectrum values of this thread: octant entry (m1, m2, m3), m1 from
+  // the element of the last forward stage it holds (32-bit index: the octant
+  // has (L/2 + 1)^3 < 2^31 entries)
+  constexpr uint32_t KP = L / 2 + 1;
+  const uint32_t krow = static_cast<uint32_t>(m2) * KP + static_cast<uint32_t>(m3);
   ZRegs<T> kv;
 #pragma unroll
   for (int i = 0; i < St::cnt(SL); ++i) {
@@ -351,38 +426,71 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
 #pragma unroll
     for (int j = 0; j < RL; ++j) {
       const int e = b + j * STRIDE;
-      const int m1 = e <= L - e ? e : L - e;
+      const uint32_t m1 = static_cast<uint32_t>(e <= L - e ? e : L - e);
       const bool ok = act && (St::nbf(SL) % ZT == 0 || b < St::nbf(SL));
-      kv.v[i][j] = ok ? kh[(m1 * a.kp + m2) * a.kp + m3] : cx<T>{};
+      kv.v[i][j] = ok ? kh[m1 * (KP * KP) + krow] : cx<T>{};
     }
   }
   const int64_t nvar = (m2 != 0 && m2 != half) ? 2 : 1;  // uniform over the workgroup
   const int64_t ntile = r_lo < r_hi ? nvar * (r_hi - r_lo) : 0;
   const int64_t emask = (int64_t{1} << a.e_lg) - 1;
   // tiles in the order (k2 = m2, rhs r_lo..r_hi-1), (k2 = L - m2, the same
-  // right-hand sides), walked with counters (no division per tile)
+  // right-hand sides), walked with counters (no division per tile).  A
+  // tile's base (its first column, tile * NP) is the same for the whole
+  // workgroup; each thread adds its column t and the offset of each element.
+  // Up to L = 512 one right-hand side's work array is below 4 GB, so the
+  // offset of each element within a tile is a 32-bit byte count, the same
+  // for every tile: computed once below, added to the tile's base (uniform
+  // over the workgroup) at each access.  Longer lengths address each element
+  // from the thread's own base (k3 included) in 64 bits.
+  constexpr bool A32 = L <= 512;
   int64_t nx_rhs = r_lo, nx_var = 0;
   auto next_base = [&]() -> int64_t {
     const int64_t k2 = nx_var ? L - m2 : m2;
-    const int64_t base = nx_rhs * a.batch_stride + k2 * a.o_stride + k3;
+    const int64_t base = nx_rhs * a.batch_stride + k2 * a.o_stride + (A32 ? tile * NP : k3);
     if (++nx_rhs == r_hi) {
       nx_rhs = r_lo;
       ++nx_var;
     }
     return base;
   };
+  // offset of element e of this thread's pencil from the tile's base (32
+  // bits: A32 below)
+  auto elem_off32 = [&](int e) -> uint32_t {
+    return static_cast<uint32_t>(t) + (static_cast<uint32_t>(e) >> a.e_lg) * static_cast<uint32_t>(a.e_hi) +
+           (static_cast<uint32_t>(e) & static_cast<uint32_t>(emask)) * static_cast<uint32_t>(a.e_lo);
+  };
   auto addr = [&](int64_t base, int e) -> int64_t {
     return base + (e >> a.e_lg) * a.e_hi + (e & emask) * a.e_lo;
   };
+  constexpr int NIN = EF::St::cnt(0) * EF::St::radix(0);
+  constexpr int NOUT = EI::St::cnt(EI::NS - 1) * EI::St::radix(EI::NS - 1);
+  uint32_t off_in[NIN], off_out[NOUT];
+  if constexpr (A32) {
+    EF::template first_slots<true>(bt, [&](int slot, int e) { off_in[slot] = elem_off32(e) * sizeof(cx<T>); });
+    EI::template last_slots<KEEP_HALF>(bt, [&](int slot, int e) { off_out[slot] = elem_off32(e) * sizeof(cx<T>); });
+  }
+  // range of a tile's buffer resource: one right-hand side's work array
+  const int32_t range = A32 ? static_cast<int32_t>(a.batch_stride * int64_t{sizeof(cx<T>)}) : 0;
   auto fetch = [&](G0& g, int64_t base) {
-    EF::template load_first<true>(g, bt, [&](int e) -> cx<T> {
-      if constexpr (!EX) {
-        if (e >= a.n) return cx<T>{};  // zero padding between n and L/2
-      }
-      return act ? buf[addr(base, e)] : cx<T>{};
-    });
+    if constexpr (A32) {
+      const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(buf + base, range);
+      EF::template load_first_slots<true>(g, bt, [&](int slot, int e) -> cx<T> {
+        if constexpr (!EX) {
+          if (e >= a.n) return cx<T>{};  // zero padding between n and L/2
+        }
+        return act ? buffer_load<T>(rs, off_in[slot]) : cx<T>{};
+      });
+    } else {
+      EF::template load_first<true>(g, bt, [&](int e) -> cx<T> {
+        if constexpr (!EX) {
+          if (e >= a.n) return cx<T>{};
+        }
+        return act ? buf[addr(base, e)] : cx<T>{};
+      });
+    }
   };
-  LdsPencil<T> lp{lds + t, NP};
+  LdsPencil<T> lp{lds + t, NP, PADL ? 1 : 0};
   auto transform = [&](G0& g, int64_t base) {
     EF::template run<true>(g, bt, lp, tw, [&](auto& gl) {
 #pragma unroll
@@ -390,13 +498,23 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
 #pragma unroll
         for (int j = 0; j < RL; ++j) gl.v[i][j] = gl.v[i][j] * kv.v[i][j];
       }
-      EI::template run<false>(gl, bt, lp, tw, [&](auto& gi) {
-        EI::template store_last<KEEP_HALF>(gi, bt, [&](int e, cx<T> v) {
-          if constexpr (!EX) {
-            if (e >= a.n) return;
-          }
-          if (act) buf[addr(base, e)] = v;
-        });
+      EI::template run<false>(gl, bt, lp, twi, [&](auto& gi) {
+        if constexpr (A32) {
+          const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(buf + base, range);
+          EI::template store_last_slots<KEEP_HALF>(gi, bt, [&](int slot, int e, cx<T> v) {
+            if constexpr (!EX) {
+              if (e >= a.n) return;
+            }
+            if (act) buffer_store<T>(rs, off_out[slot], v);
+          });
+        } else {
+          EI::template store_last<KEEP_HALF>(gi, bt, [&](int e, cx<T> v) {
+            if constexpr (!EX) {
+              if (e >= a.n) return;
+            }
+            if (act) buf[addr(base, e)] = v;
+          });
+        }
       });
     });
     __syncthreads();
