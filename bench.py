@@ -62,13 +62,15 @@ def pass_bytes(n, elem):
 
 
 def kernel_sources_sha():
-    """Hash of the library sources with comments and blank space removed (a
-    counter summary stays valid across edits that change no code)."""
+    """Hash of the device sources (the .hip files and the headers they
+    include) with comments and blank space removed: a counter summary stays
+    valid across edits of host code or comments, and is dropped once any
+    kernel changes."""
     import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1602_04691_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h", ".cpp")):
+        if f.endswith((".hip", ".h")):
             text = open(os.path.join(d, f), encoding="utf-8").read()
             text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
             text = re.sub(r"//[^\n]*", " ", text)
@@ -77,6 +79,15 @@ def kernel_sources_sha():
 
 
 VALU_LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9  # MI355X: CUs x SIMDs x lanes x clock
+FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector peak (an FMA counts two)
+# Algorithmic FP64 operations per point-cell pair of the field sums, each
+# transcendental function counted as one operation:
+#   field (eq. 2.10): differences 3, r^2 5, reciprocal square root 1, r 1,
+#     k r 1, sine and cosine 2, 1/(4 pi r) 1, e^{ikr}/(4 pi r) 2, complex
+#     multiply-add with q_p 8  -> 24
+#   far field: beta . x_p 5, k (beta . x_p) 1, sine and cosine 2, complex
+#     multiply-add with q_p 8  -> 16
+FIELD_FLOPS = {"field": 24, "far": 16}
 
 
 def read_profile_value(name, key):
@@ -118,24 +129,69 @@ def read_traffic(kernel, n, layout):
         return None
 
 
+def host_cpu():
+    """CPU model and the host cores this process may use."""
+    import oracle as O
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, O.rows.default_workers()
+
+
+def sample_rows(n, n_random, seed):
+    """The 8 corners, 12 edge midpoints and 6 face centres of the n^3 grid and
+    n_random random cells (flat indices)."""
+    import numpy as np
+    lo, mid, hi = 0, n // 2, n - 1
+    pts = {(a, b, c) for a in (lo, hi) for b in (lo, hi) for c in (lo, hi)}
+    for a in (lo, hi):
+        for b in (lo, hi):
+            pts |= {(mid, a, b), (a, mid, b), (a, b, mid)}
+        pts |= {(a, mid, mid), (mid, a, mid), (mid, mid, a)}
+    rows = [(i1 * n + i2) * n + i3 for i1, i2, i3 in pts]
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.array(rows, np.int64), rng.integers(0, n ** 3, n_random)]))
+
+
+def oracle_residual(case, u, rows):
+    """||(u0 - A u)[rows]|| / ||u0[rows]|| of eq. 2.19, the rows from the CPU
+    oracle (on all host cores)."""
+    import numpy as np
+    import oracle as O
+    n, k = case["n"], case["k"]
+    pts = O.cell_points(n)
+    D = O.coupling(case["h"], case["N"], n)
+    r, _ = O.sample_rows_parallel(pts, k, D, u, rows, u0=case["u0"])
+    return float(np.linalg.norm(r) / np.linalg.norm(case["u0"][rows]))
+
+
 def cpu_baseline(case, budget_s, x):
-    """Time the CPU oracle's dense rows of the same operator (bounded sample)."""
+    """Time the CPU oracle's dense rows of the same operator (bounded sample)
+    on all host cores: one row alone sets the row count for about budget_s
+    of work, then the rows run on a pool of one process per core."""
     import numpy as np
     import oracle as O
     n, k = case["n"], case["k"]
     P = n ** 3
     pts = O.cell_points(n)
     D = O.coupling(case["h"], case["N"], n)
+    model, workers = host_cpu()
     rng = np.random.default_rng(123)
-    rows, vals = [], []
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        q = int(rng.integers(0, P))
-        vals.append(O.sample_scatter_rows(pts, k, D, x, [q])[0])
-        rows.append(q)
+    O.sample_scatter_rows(pts, k, D, x, [int(rng.integers(0, P))])
+    t_row = time.perf_counter() - t0
+    nrows = workers * max(1, int(budget_s / max(t_row, 1e-6)))
+    rows = rng.integers(0, P, nrows)
+    t0 = time.perf_counter()
+    vals, used = O.sample_rows_parallel(pts, k, D, x, rows, workers=workers)
     dt = time.perf_counter() - t0
     rate = len(rows) / dt / P  # full matvecs per second
-    return rows, np.array(vals), dt, rate
+    return rows, vals, dt, rate, used, model
 
 
 def next_workload(a):
@@ -195,17 +251,26 @@ def next_workload(a):
             c = workloads.make_case(nn, k, seed=20 + j)
             probs.append(dict(n=nn, k=k, h=gpu(c["h"]), N=gpu(c["N"]), u0=gpu(c["u0"])))
         n = 96
+        # one group (the four problems' workspaces and streams), made once like
+        # the default workload's context; a step loads every problem and solves
+        # them together: each iteration block of the problems still running is
+        # one graph replay, the problems side by side on the GPU
+        grp = ori.ori_group_create([p["n"] for p in probs])
+        us = [torch.empty(p["n"] ** 3, dtype=torch.complex128, device=dev) for p in probs]
 
         def step():
-            # contexts (workspaces and streams) are kept between steps, as the
-            # default workload keeps its one; the warmup step creates them
-            res = ori.solve_many(probs, tol=a.tol, precision=ori.ORI_MIXED, reuse_contexts=True)
-            return {"matvecs": sum(i["matvecs"] for _, i in res), "solves": len(res)}
+            for i, p in enumerate(probs):
+                ori.ori_group_load(grp, i, p["k"], p["h"], p["N"], p["u0"])
+            _, infos = ori.ori_group_solve(grp, us, tol=a.tol, precision=ori.ORI_MIXED)
+            return {"matvecs": sum(i["matvecs"] for i in infos), "solves": len(infos),
+                    "iterations": [i["iterations"] for i in infos]}
 
         unit, count = "solves/s", lambda info: info["solves"]
         metric = "uneven batch: problems solved/sec, n in {32,48,64,96}, mixed precision"
         desc = {"workload": "ori_red_uneven_n32_48_64_96_k5", "n": [32, 48, 64, 96], "k": k,
-                "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23], "contexts": "kept between steps"}
+                "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23],
+                "solver": "ori_group: a stream per problem for eager work, one graph replay per iteration "
+                          "block holding every running problem's chain"}
     elif a.workload == "gradient":
         n, k = 128, 5.0
         case = workloads.make_case(n, k, seed=3)
@@ -290,27 +355,49 @@ def next_workload(a):
     wall = time.perf_counter() - t0
     value = sum(count(i) for i in infos) / wall
     if a.workload == "field":
-        # direct sums: bound by VALU issue.  peak = the chip's VALU lane-issue
-        # rate (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz) / the VALU instructions
-        # per point-cell pair counted by rocprofv3 (committed summary, taken on
-        # the current kernel sources), or null without one
+        # direct FP64 sums, bound by the vector ALU: algorithmic FP64 work per
+        # point-cell pair from a fixed count (FIELD_FLOPS) against the chip's
+        # FP64 vector peak; the VALU instructions per pair that rocprofv3
+        # counts (committed summary on the current sources) as context
+        flops = value / 2 * (FIELD_FLOPS["field"] + FIELD_FLOPS["far"])  # M points + M directions
         ipp = read_profile_value(f"field_n{n}_valu.txt", "valu_insts_per_pair")
-        peak = VALU_LANE_ISSUE_PER_S / ipp if ipp else None
-        roofline = {"bound": "alu", "kernel": "k_field_partial", "achieved": round(value, 1), "peak": peak,
-                    "unit": "point_cell_pairs/s", "frac": round(value / peak, 4) if peak else None,
-                    "traffic": None, "valu_insts_per_pair": ipp,
-                    "peak_model": "VALU lane-issue rate / VALU instructions per pair"}
+        roofline = {"bound": "alu", "kernel": "k_field_partial", "achieved": round(flops / 1e12, 4),
+                    "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(flops / 1e12 / FP64_VECTOR_TFLOPS, 4), "traffic": None,
+                    "flops_per_pair": FIELD_FLOPS, "valu_insts_per_pair": ipp,
+                    "peak_model": "FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz"}
     log(f"[bench] {value:.3f} {unit}, {wall / a.steps * 1e3:.2f} ms/step, last {infos[-1]}")
+    extra = {}
+    if a.workload == "uneven":
+        # the same steps with the group created and destroyed inside each step
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            g2 = ori.ori_group_create([p["n"] for p in probs])
+            for i, p in enumerate(probs):
+                ori.ori_group_load(g2, i, p["k"], p["h"], p["N"], p["u0"])
+            ori.ori_group_solve(g2, us, tol=a.tol, precision=ori.ORI_MIXED)
+            g2.close()
+        torch.cuda.synchronize()
+        extra["solves_per_s_with_group_created_each_step"] = round(len(probs) * a.steps / (time.perf_counter() - t0), 1)
+        # and every solution against the oracle: sampled rows of eq. 2.19
+        res = []
+        for p, uu in zip(probs, us):
+            c = workloads.make_case(p["n"], p["k"], seed=20 + [32, 48, 64, 96].index(p["n"]))
+            res.append(oracle_residual(c, uu.cpu().numpy(), sample_rows(p["n"], 6, seed=p["n"])))
+        extra["oracle_rows_rel_residual"] = res
+        log(f"[bench] with the group made each step: {extra['solves_per_s_with_group_created_each_step']} solves/s; "
+            f"oracle rows {res}")
+        grp.close()
     if ctx is not None:
         ctx.close()
-    ori.release_contexts()
     out = {
         "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(wall / a.steps * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "c128" if a.workload in ("gradient", "field") else "c64+f64",
         "data": "synthetic", "config": desc, "roofline": roofline, "cpu_baseline": None,
-        "last_step": infos[-1], "kernel_ms_untimed_step": kernel_ms,
+        "last_step": infos[-1], "kernel_ms_untimed_step": kernel_ms, **extra,
         "kernel_sources_sha": kernel_sources_sha(),
     }
     print(json.dumps(out), flush=True)
@@ -464,6 +551,7 @@ def main():
         _, solvemx = ori.ori_solve(ctx, u, tol=a.tol, precision=ori.ORI_MIXED)
         t_solvemx = time.perf_counter() - t0
         diff = float(torch.linalg.vector_norm(u - u64) / torch.linalg.vector_norm(u64))
+        umx = u.clone()
         mvm = sum(i["matvecs"] for i in infos_m)
         mixed = {
             "matvecs_per_s": mvm / wall_m,
@@ -529,17 +617,33 @@ def main():
 
     # ---- CPU baseline: the oracle on a bounded sample of the same operator --
     cpu = None
+    fp64_oracle = None
     if not a.no_cpu_baseline:
         xs = x.cpu().numpy()
         ori.ori_matvec(ctx, x, y, ori.ORI_OP_SYSTEM, ori.ORI_FP64)
         yg = (y - x).cpu().numpy()
-        rows, vals, dt, rate = cpu_baseline(case, a.cpu_budget, xs)
+        ori.ori_matvec(ctx, x, y, ori.ORI_OP_SYSTEM, ori.ORI_MIXED)
+        ygm = (y - x).cpu().numpy()
+        rows, vals, dt, rate, used, model = cpu_baseline(case, a.cpu_budget / 2, xs)
         err = float(np.linalg.norm(yg[rows] - vals) / np.linalg.norm(vals))
-        cpu = {"value": rate, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(rows)} dense rows of G0 D x at n={n} (P={P}) in {dt:.1f}s, "
-                         f"scaled to full matvecs/s",
-               "gpu_vs_oracle_rel_err_on_sample": err}
-        log(f"[bench] cpu oracle: {len(rows)} rows in {dt:.1f}s -> {rate:.3e} matvecs/s; GPU err {err:.2e}")
+        errm = float(np.linalg.norm(ygm[rows] - vals) / np.linalg.norm(vals))
+        cpu = {"value": rate, "unit": "matvecs/s", "cores": used, "kind": "oracle",
+               "sample": f"{len(rows)} dense rows of G0 D x at n={n} (P={P}) in {dt:.1f}s on {used} host "
+                         f"processes ({model}), scaled to full matvecs/s",
+               "cpu_model": model,
+               "gpu_vs_oracle_rel_err_on_sample": {"c128": err, "c64": errm}}
+        log(f"[bench] cpu oracle: {len(rows)} rows in {dt:.1f}s on {used} cores -> {rate:.3e} matvecs/s; "
+            f"GPU product err c128 {err:.2e} c64 {errm:.2e}")
+        # every solution of the timed step against the oracle: sampled rows
+        # of eq. 2.19 (corners, edges, faces, random cells)
+        rrows = sample_rows(n, 6, seed=7)
+        res64 = oracle_residual(case, u64.cpu().numpy(), rrows)
+        fp64_oracle = {"rows": int(len(rrows)), "rel_residual_rows": res64}
+        log(f"[bench] oracle rows of eq. 2.19: fp64 solution {res64:.2e}")
+        if mixed is not None:
+            resm = oracle_residual(case, umx.cpu().numpy(), rrows)
+            mixed["oracle_rows"] = {"rows": int(len(rrows)), "rel_residual_rows": resm}
+            log(f"[bench] oracle rows of eq. 2.19: mixed solution {resm:.2e}")
 
     if a.calib_copy_mib > 0:
         # a plain streaming kernel of known traffic (reads and writes exactly
@@ -576,6 +680,7 @@ def main():
                  "event_s_per_step": ev_s / a.steps,
                  "iteration_kernel_ms": round(it_ms, 4),
                  "iteration_model_gbs": round(it_bytes / (it_ms * 1e-3) / 1e9, 1),
+                 "oracle_rows": fp64_oracle,
                  "kernel_ms_untimed_step": {kk: round(v[0], 5) for kk, v in prof_all64.items()}},
         "mixed": mixed,
         "matvec_only": {"per_s": {kk: round(v, 2) for kk, v in mv_rates.items()}, "device_time": mv_stats,

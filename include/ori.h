@@ -226,6 +226,42 @@ ori_status ori_matvec(ori_ctx ctx, int32_t op, int32_t precision, const void* x,
 ori_status ori_green_noalloc(const ori_grid* g, double k, int32_t precision, const void* x, void* y,
                              void* stream);
 
+/* ---- several independent problems solved together ------------------------ */
+
+typedef struct ori_group_s* ori_group; /* opaque; owns its problems' workspaces */
+
+/* A group of nprob (1..64) independent problems of eq. 2.19 -- the uneven
+ * batch: each its own grid (any n <= 512), wave number, h, N and incident
+ * field (one right-hand side), so that no two share an operator.  Allocates
+ * what ori_create(&grids[i], 1, provision, 0, ., .) would for each problem,
+ * and a stream per problem (so the problems' launches run side by side).
+ * stream: the caller's stream (hipStream_t or NULL); every group call starts
+ * after the work already queued on it and returns after all of its own work
+ * has completed.  Errors of the ori_group_* calls: ori_last_error(NULL). */
+ori_status ori_group_create(const ori_grid* grids, int32_t nprob, int32_t provision, void* stream, ori_group* out);
+
+/* ori_load of problem i (0 <= i < nprob): wave number, h, N, incident field
+ * (device arrays of that problem's size, as for ori_load). */
+ori_status ori_group_load(ori_group g, int32_t i, double k, const void* h, const double* N, const void* u0);
+
+/* Solve every problem (eq. 2.19 by COCG on its complex-symmetric form, as
+ * ori_solve).  The problems run in lockstep: after the first iteration,
+ * each block of check_every COCG iterations of the problems still running is
+ * one replay of a HIP graph in which every problem is an independent chain
+ * of its own kernels (built node by node, as in ori_solve), so the GPU runs
+ * the problems side by side; a problem leaves once it has converged.  Every
+ * problem runs exactly the kernels of its own ori_solve, in the same order,
+ * so each result is bitwise that of solving the problem alone.
+ *   opts: as ori_solve, the same for every problem (NULL: defaults)
+ *   u:    host array of nprob pointers, u[i] device complex128[n_i^3]
+ *   info: host array of nprob entries, or NULL
+ * Returns ORI_OK, or the status of the first problem that did not converge
+ * (every u[i] is filled either way). */
+ori_status ori_group_solve(ori_group g, const ori_solve_opts* opts, void* const* u, ori_solve_info* info);
+
+/* Release the group and its problems' workspaces (NULL is ignored). */
+void ori_group_destroy(ori_group g);
+
 /* ---- what the solution is used for (Section 2, Section 4) ---------------- */
 
 /* Charges of the cells: q_p = -D_p u_p = -c_S h_p N_p |Delta_p| u_p, the sum

@@ -24,7 +24,8 @@ __all__ = [
     "ORI_OK", "ORI_ERR_INVALID_ARG", "ORI_ERR_OUT_OF_MEMORY", "ORI_ERR_DEVICE",
     "ORI_ERR_BREAKDOWN", "ORI_ERR_NOT_CONVERGED", "ORI_ERR_UNSUPPORTED",
     "ORI_FP64", "ORI_MIXED", "ORI_OP_SYSTEM", "ORI_OP_SYMMETRIC", "ORI_OP_GREEN",
-    "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve", "solve_many", "release_contexts",
+    "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve", "solve_many",
+    "Group", "ori_group_create", "ori_group_load", "ori_group_solve", "ori_group_destroy",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libori.so")
@@ -95,6 +96,11 @@ def lib():
             "ori_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Grid), I32, I32, ctypes.POINTER(I64)]),
             "ori_create": (ctypes.c_int, [ctypes.POINTER(Grid), I32, I32, I64, P, ctypes.POINTER(P)]),
             "ori_batch_info": (ctypes.c_int, [P, I32, ctypes.POINTER(SolveInfo)]),
+            "ori_group_create": (ctypes.c_int, [ctypes.POINTER(Grid), I32, I32, P, ctypes.POINTER(P)]),
+            "ori_group_load": (ctypes.c_int, [P, I32, D, P, P, P]),
+            "ori_group_solve": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(P),
+                                               ctypes.POINTER(SolveInfo)]),
+            "ori_group_destroy": (None, [P]),
             "ori_load": (ctypes.c_int, [P, D, P, P, P]),
             "ori_spectrum_cache": (ctypes.c_int, [P, I32]),
             "ori_setup": (ctypes.c_int, [ctypes.POINTER(Grid), D, P, P, P, P, ctypes.POINTER(P)]),
@@ -330,6 +336,10 @@ def ori_destroy(ctx):
     ctx.close()
 
 
+def ori_group_destroy(group):
+    group.close()
+
+
 def ori_charges(ctx, u, q=None):
     """q = -D u (cell charges) for a solution u of the loaded problem."""
     import torch
@@ -519,62 +529,81 @@ def OriSolve(h, u0, n, k, N=None, side=1.0, **opts):
     return _ORI_SOLVE_FN.apply(h, u0, N, int(n), float(k), float(side), dict(opts))
 
 
-_CTX_POOL = {}  # (device, n, side) -> idle contexts kept by solve_many(reuse_contexts=True)
-_CTX_POOL_LOCK = __import__("threading").Lock()
+class Group:
+    """An ori_group: independent problems (each its own grid) solved together."""
 
+    def __init__(self, handle, ns, stream):
+        self.handle = handle
+        self.ns = [int(n) for n in ns]
+        self.stream = stream
 
-def release_contexts():
-    """Destroy the idle contexts that solve_many(reuse_contexts=True) keeps."""
-    with _CTX_POOL_LOCK:
-        pooled = [c for lst in _CTX_POOL.values() for c in lst]
-        _CTX_POOL.clear()
-    for c in pooled:
-        c.close()
+    def close(self):
+        if self.handle:
+            lib().ori_group_destroy(self.handle)
+            self.handle = None
 
-
-__import__("atexit").register(release_contexts)  # while the HIP runtime is still up
-
-
-def solve_many(problems, max_workers=4, reuse_contexts=False, **opts):
-    """Independent problems of any sizes, each on its own context and stream,
-    solved concurrently from a thread pool (the library call releases the
-    GIL).
-    problems: dicts with n, k, h, N, u0 (CUDA tensors).  At most max_workers
-    contexts (each holding its own workspaces) are in use at a time.  With
-    reuse_contexts, a context is kept after its solve (workspaces, stream)
-    and loaded with the next problem of the same grid instead of being
-    created again; release_contexts() frees the kept ones.  Returns a list of
-    (u, info) in order."""
-    import concurrent.futures
-    import torch
-
-    def one(p):
-        n, side = int(p["n"]), float(p.get("side", 1.0))
-        key = (p["h"].device.index, n, side)
-        ctx = None
-        if reuse_contexts:
-            with _CTX_POOL_LOCK:
-                idle = _CTX_POOL.get(key)
-                ctx = idle.pop() if idle else None
-        if ctx is None:
-            ctx = ori_create(n, side=side, stream=torch.cuda.Stream(device=p["h"].device))
+    def __del__(self):
         try:
-            s = ctx.stream
-            with torch.cuda.stream(s):
-                ori_load(ctx, p["k"], p["h"], p.get("N"), p["u0"])
-                u = torch.empty(n ** 3, dtype=torch.complex128, device=p["h"].device)
-                _, info = ori_solve(ctx, u, **opts)
-            s.synchronize()
-        except BaseException:
-            ctx.close()
-            raise
-        if reuse_contexts:
-            with _CTX_POOL_LOCK:
-                _CTX_POOL.setdefault(key, []).append(ctx)
-        else:
-            ctx.close()
-        return u, info
+            self.close()
+        except Exception:
+            pass
 
-    torch.cuda.synchronize()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(int(max_workers), len(problems)))) as ex:
-        return list(ex.map(one, problems))
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def ori_group_create(grids, provision=ORI_PROVISION_FP64 | ORI_PROVISION_MIXED, stream=None):
+    """grids: one entry per problem, an int n or a dict with n, side, origin, cell_offset."""
+    import torch
+    specs = [g if isinstance(g, dict) else {"n": g} for g in grids]
+    arr = (Grid * len(specs))()
+    for i, g in enumerate(specs):
+        arr[i] = _grid(g["n"], g.get("side", 1.0), g.get("origin", (0.0, 0.0, 0.0)), g.get("cell_offset", 0.5))
+    h = ctypes.c_void_p()
+    _check(lib().ori_group_create(arr, len(specs), provision, _stream(stream), ctypes.byref(h)))
+    return Group(h, [g["n"] for g in specs], stream if stream is not None else torch.cuda.current_stream())
+
+
+def ori_group_load(group, i, k, h, N, u0):
+    import torch
+    P = group.ns[i] ** 3
+    _check(lib().ori_group_load(group.handle, int(i), float(k), _dev(h, torch.complex128, P, "h"),
+                                _dev(N, torch.float64, P, "N"), _dev(u0, torch.complex128, P, "u0")))
+
+
+def ori_group_solve(group, us, raise_on_error=True, **opts):
+    """Solve every problem of the group into us[i] (complex128 CUDA tensors).
+    Returns (status, [info dict per problem])."""
+    import torch
+    M = len(group.ns)
+    if len(us) != M:
+        raise ValueError(f"expected {M} output tensors, got {len(us)}")
+    ptrs = (ctypes.c_void_p * M)(*[_dev(u, torch.complex128, n ** 3, f"u[{i}]").value
+                                   for i, (u, n) in enumerate(zip(us, group.ns))])
+    infos = (SolveInfo * M)()
+    o = _opts(**opts)
+    st = lib().ori_group_solve(group.handle, ctypes.byref(o), ptrs, infos)
+    d = [infos[i].as_dict() for i in range(M)]
+    if raise_on_error:
+        _check(st, None, d)
+    return st, d
+
+
+def solve_many(problems, **opts):
+    """Independent problems of any sizes solved together as one group (one
+    stream; each iteration block of all problems is one graph replay, the
+    problems side by side on the GPU).  problems: dicts with n, k, h, N, u0
+    (CUDA tensors) and optionally side.  Returns a list of (u, info) in
+    order; each result equals that problem's ori_solve bit for bit."""
+    import torch
+    grids = [{"n": int(p["n"]), "side": float(p.get("side", 1.0))} for p in problems]
+    dev = problems[0]["h"].device
+    with ori_group_create(grids) as g:
+        for i, p in enumerate(problems):
+            ori_group_load(g, i, p["k"], p["h"], p.get("N"), p["u0"])
+        us = [torch.empty(int(p["n"]) ** 3, dtype=torch.complex128, device=dev) for p in problems]
+        _, infos = ori_group_solve(g, us, **opts)
+    return list(zip(us, infos))

@@ -107,6 +107,15 @@ std::mutex g_tune_mu;
 
 std::map<TuneKey, Tuned> g_tuned;
 
+// A cached HIP graph of COCG iteration blocks: `iters` iterations of each
+// context in `members`, one independent chain per context.
+struct IterGraph {
+  hipGraphExec_t exec = nullptr;
+  int iters = 0;
+  std::vector<ori_ctx> members;
+  hipEvent_t done = nullptr;  // recorded after a replay, waited on by each member's stream
+};
+
 struct ProfPending {
   int slot;  // kind * 2 + (fprec == F32)
   int ev;
@@ -164,11 +173,7 @@ struct ori_ctx_s {
   bool trace = false;
 
   // COCG iteration blocks as HIP graphs, one per vector precision
-  struct IterGraph {
-    hipGraphExec_t exec = nullptr;
-    int iters = 0;
-    const void* key[5] = {};
-  } graphs[2];
+  IterGraph graphs[2];
 
   // profiling
   bool prof = false;
@@ -497,11 +502,6 @@ void fill_twiddles(int64_t L, std::vector<cxd>& d, std::vector<cxf>& f) {
 // done (per right-hand side targets set); a right-hand side that converges
 // or breaks down is frozen on the device (alpha = 0) while the others go on.
 // ---------------------------------------------------------------------------
-struct CocgOut {
-  int iters = 0;  // batched iterations run
-  int64_t matvecs = 0;
-  bool all_done = false;
-};
 
 bool all_done(ori_ctx c) {
   for (int64_t i = 0; i < c->nrhs; ++i)
@@ -533,58 +533,76 @@ ori_status cocg_iteration(ori_ctx c, int prec, void* x, void* r, void* p, void* 
   return finalize(c, update_blocks(c->P, prec), FIN_RHO);
 }
 
-// The graph of `iters` non-first iterations on (x, r, p, q, S), cached per
-// precision.  It is built node by node: with graph_being_built() set, every
-// launch of cocg_iteration appends a kernel node after the previous one
-// (launch.h), so it holds exactly the kernels and arguments of the eager
-// launches, in order, and no stream is put into capture mode.
-ori_status iteration_graph(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int iters,
-                           hipGraphExec_t* out) {
+// The COCG vectors of precision prec of a context (the FFTs run in the same
+// precision).
+struct PrecVecs {
+  void *x, *r, *p, *q;
+  const void* S;
+};
+PrecVecs vecs(ori_ctx c, int prec) {
+  if (prec == PREC_F32) return PrecVecs{c->xf, c->rf, c->pf, c->qf, c->Sf};
+  return PrecVecs{c->x, c->r, c->p, c->q, c->S};
+}
+
+ori_status iteration(ori_ctx c, int prec, bool first) {
+  const PrecVecs v = vecs(c, prec);
+  return cocg_iteration(c, prec, v.x, v.r, v.p, v.q, v.S, first);
+}
+
+// Several contexts solved in lockstep: the members of an ori_group (a
+// stream each), or a single context.
+using Members = std::vector<ori_ctx>;
+
+// The graph of `iters` non-first iterations of every context of `active`,
+// cached in `cache`.  It is built node by node: with graph_being_built()
+// set, every launch of an iteration appends a kernel node after the previous
+// node of the same context (launch.h), so each context is one chain holding
+// exactly the kernels and arguments of its eager launches, in order; the
+// chains of different contexts are independent, so the GPU runs them side
+// by side.  No stream is put into capture mode.
+ori_status iteration_graph(const Members& active, int prec, int iters, IterGraph& cache, hipGraphExec_t* out) {
   *out = nullptr;
-  auto& g = c->graphs[prec == PREC_F32 ? 1 : 0];
-  const void* key[5] = {x, r, p, q, S};
-  if (g.exec && g.iters == iters && std::equal(key, key + 5, g.key)) {
-    *out = g.exec;
+  ori_ctx c0 = active.front();
+  if (cache.exec && cache.iters == iters && cache.members == active) {
+    *out = cache.exec;
     return ORI_OK;
   }
-  if (g.exec) {
-    ORI_HIP(c, hipGraphExecDestroy(g.exec));
-    g.exec = nullptr;
+  if (cache.exec) {
+    ORI_HIP(c0, hipGraphExecDestroy(cache.exec));
+    cache.exec = nullptr;
   }
+  if (!cache.done) ORI_HIP(c0, hipEventCreateWithFlags(&cache.done, hipEventDisableTiming));
   GraphBuild gb;
-  ORI_HIP(c, hipGraphCreate(&gb.graph, 0));
+  ORI_HIP(c0, hipGraphCreate(&gb.graph, 0));
   t_graph = &gb;
   ori_status st = ORI_OK;
-  for (int it = 0; it < iters && st == ORI_OK; ++it) st = cocg_iteration(c, prec, x, r, p, q, S, false);
+  for (ori_ctx c : active) {
+    gb.last = nullptr;  // a chain of its own
+    for (int it = 0; it < iters && st == ORI_OK; ++it) st = iteration(c, prec, false);
+    if (st != ORI_OK) {
+      if (c != c0) set_err(c0, st, "%s", c->err.c_str());
+      break;
+    }
+  }
   t_graph = nullptr;
   if (st == ORI_OK) {
-    const hipError_t e = hipGraphInstantiateWithFlags(&g.exec, gb.graph, 0);
+    const hipError_t e = hipGraphInstantiateWithFlags(&cache.exec, gb.graph, 0);
     if (e != hipSuccess) {
-      g.exec = nullptr;
-      st = set_err(c, ORI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      cache.exec = nullptr;
+      st = set_err(c0, ORI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
   }
   (void)hipGraphDestroy(gb.graph);
   if (st != ORI_OK) return st;
-  g.iters = iters;
-  std::copy(key, key + 5, g.key);
-  *out = g.exec;
+  cache.iters = iters;
+  cache.members = active;
+  *out = cache.exec;
   return ORI_OK;
 }
 
 // x += alpha p left pending by the last iteration
 ori_status flush_x(ori_ctx c, int prec, void* x, const void* p) {
   return launch(c, K_UPDATE, prec, [&] { return launch_x_flush(prec, x, p, c->P, c->nrhs, c->sc, c->stream); });
-}
-
-ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
-                          int check_every, bool use_graph, CocgOut* out);
-
-ori_status run_cocg(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
-                    int check_every, bool use_graph, CocgOut* out) {
-  ORI_TRY(run_cocg_steps(c, prec, x, r, p, q, S, max_iter, check_every, use_graph, out));
-  if (out->iters > 0) ORI_TRY(flush_x(c, prec, x, p));
-  return ORI_OK;
 }
 
 // one line per right-hand side: its iterations so far, ||r|| and ||r|| / ||r0||
@@ -599,36 +617,73 @@ void trace_cocg(ori_ctx c, int prec) {
   }
 }
 
-ori_status run_cocg_steps(ori_ctx c, int prec, void* x, void* r, void* p, void* q, const void* S, int max_iter,
-                          int check_every, bool use_graph, CocgOut* out) {
-  ORI_TRY(sync_scalars(c));
-  trace_cocg(c, prec);
-  if (all_done(c)) {
-    out->all_done = true;
-    return ORI_OK;
+// The scalar blocks of every member on the host: one copy each on the
+// member's stream, then one wait per stream.
+ori_status sync_members(const Members& ms) {
+  for (ori_ctx c : ms)
+    ORI_HIP(c, hipMemcpyAsync(c->sc_host, c->sc, c->nrhs * sizeof(ScalarBlock), hipMemcpyDeviceToHost, c->stream));
+  for (size_t i = 0; i < ms.size(); ++i) {
+    bool seen = false;
+    for (size_t j = 0; j < i; ++j) seen = seen || ms[j]->stream == ms[i]->stream;
+    if (!seen) ORI_HIP(ms[i], hipStreamSynchronize(ms[i]->stream));
   }
-  use_graph = use_graph && !c->prof && !c->check_guards;
+  return ORI_OK;
+}
+
+// COCG on every member in lockstep, vectors (and FFTs) of precision prec.
+// Expects each member's x, r initialised and FIN_INIT done.  Member i runs
+// at most budget[i] iterations and leaves when all its right-hand sides are
+// done (a right-hand side that converges or breaks down is frozen on the
+// device, alpha = 0, while the others of its context go on); ran[i]
+// receives the iterations it ran.  The first block runs eagerly (it holds
+// the first iteration); later full blocks of check_every iterations replay
+// one graph over the members still running.  Each member runs exactly the
+// kernels of its own solve, so results do not depend on the other members.
+ori_status group_cocg(const Members& ms, int prec, const std::vector<int>& budget, int check_every, bool use_graph,
+                      IterGraph& cache, std::vector<int>* ran) {
+  ran->assign(ms.size(), 0);
+  ORI_TRY(sync_members(ms));
+  for (ori_ctx c : ms) {
+    trace_cocg(c, prec);
+    use_graph = use_graph && !c->prof && !c->check_guards;
+  }
+  std::vector<size_t> act;
+  for (size_t i = 0; i < ms.size(); ++i)
+    if (!all_done(ms[i]) && budget[i] > 0) act.push_back(i);
   int it = 0;
-  while (it < max_iter) {
-    // the first block runs eagerly (it holds the first iteration); later
-    // full blocks replay the graph of check_every iterations
-    const int blk = std::min(check_every, max_iter - it);
+  while (!act.empty()) {
+    int blk = check_every;
+    for (size_t i : act) blk = std::min(blk, budget[i] - (*ran)[i]);
+    Members active;
+    for (size_t i : act) active.push_back(ms[i]);
     hipGraphExec_t exec = nullptr;
-    if (use_graph && it > 0 && blk == check_every) ORI_TRY(iteration_graph(c, prec, x, r, p, q, S, blk, &exec));
+    if (use_graph && it > 0 && blk == check_every) ORI_TRY(iteration_graph(active, prec, blk, cache, &exec));
     if (exec) {
-      ORI_HIP(c, hipGraphLaunch(exec, c->stream));
+      // the replay runs every member's chain on the first member's stream;
+      // the other members' streams wait for it before their next work
+      ori_ctx c0 = active.front();
+      ORI_HIP(c0, hipGraphLaunch(exec, c0->stream));
+      ORI_HIP(c0, hipEventRecord(cache.done, c0->stream));
+      for (ori_ctx c : active)
+        if (c->stream != c0->stream) ORI_HIP(c, hipStreamWaitEvent(c->stream, cache.done, 0));
     } else {
-      for (int j = 0; j < blk; ++j) ORI_TRY(cocg_iteration(c, prec, x, r, p, q, S, it + j == 0));
+      for (int j = 0; j < blk; ++j)
+        for (ori_ctx c : active) ORI_TRY(iteration(c, prec, it + j == 0));
     }
     it += blk;
-    out->iters += blk;
-    out->matvecs += blk;
-    ORI_TRY(sync_scalars(c));
-    trace_cocg(c, prec);
-    if (all_done(c)) {
-      out->all_done = true;
-      return ORI_OK;
+    for (size_t i : act) (*ran)[i] += blk;
+    ORI_TRY(sync_members(active));
+    std::vector<size_t> next;
+    for (size_t i : act) {
+      trace_cocg(ms[i], prec);
+      if (!all_done(ms[i]) && (*ran)[i] < budget[i]) next.push_back(i);
     }
+    act.swap(next);
+  }
+  for (size_t i = 0; i < ms.size(); ++i) {
+    if ((*ran)[i] == 0) continue;
+    const PrecVecs v = vecs(ms[i], prec);
+    ORI_TRY(flush_x(ms[i], prec, v.x, v.p));
   }
   return ORI_OK;
 }
@@ -713,8 +768,11 @@ void choose_layout(ori_ctx c) {
 ori_status drop_graphs(ori_ctx c) {
   for (auto& g : c->graphs) {
     if (g.exec) ORI_HIP(c, hipGraphExecDestroy(g.exec));
+    if (g.done) ORI_HIP(c, hipEventDestroy(g.done));
     g.exec = nullptr;
+    g.done = nullptr;
     g.iters = 0;
+    g.members.clear();
   }
   return ORI_OK;
 }
@@ -780,119 +838,193 @@ ori_solve_info aggregate(const Outcome& oc) {
   return a;
 }
 
-// Solve (I + S G0 S) w = rhs into c->x for every right-hand side.  On entry
-// c->x and c->r hold the initial iterate and its residual, FIN_INIT done with
-// the stopping targets; bb[i] = ||rhs_i||^2 (host) sets the same targets for
-// the refinement loop.  Counts go to oc (added).
-ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const std::vector<double>& bb, Outcome* oc) {
-  const int64_t P = c->P, R = c->nrhs;
-  std::vector<double> target(R);
-  for (int64_t i = 0; i < R; ++i) target[i] = o.tol * o.tol * bb[i];
+// One member of a lockstep solve of (I + S G0 S) w = rhs: its right-hand
+// side (device), ||rhs_i||^2 per right-hand side (host) and its outcome.
+struct SymJob {
+  ori_ctx c;
+  const cxd* rhs;
+  std::vector<double> bb;
+  Outcome* oc;
+};
+
+// Solve (I + S G0 S) w = rhs into c->x for every right-hand side of every
+// member.  On entry each member's x and r hold the initial iterate and its
+// residual, FIN_INIT done with the stopping targets; bb sets the same
+// targets for the refinement loop.  Counts go to each member's outcome
+// (added).  Every member runs the kernels of its own solve in the same
+// order as alone, so its results do not depend on the others.
+ori_status solve_sym_group(std::vector<SymJob>& jobs, const ori_solve_opts& o, IterGraph* cache) {
+  const size_t M = jobs.size();
+  Members ms;
+  for (auto& j : jobs) ms.push_back(j.c);
+  std::vector<std::vector<double>> target(M);
+  for (size_t m = 0; m < M; ++m) {
+    target[m].resize(jobs[m].c->nrhs);
+    for (int64_t i = 0; i < jobs[m].c->nrhs; ++i) target[m][i] = o.tol * o.tol * jobs[m].bb[i];
+  }
+  std::vector<int> ran;
   if (o.precision == ORI_FP64) {
-    CocgOut co;
-    ORI_TRY(run_cocg(c, PREC_F64, c->x, c->r, c->p, c->q, c->S, o.max_iter, o.check_every, o.graph != 0, &co));
-    for (int64_t i = 0; i < R; ++i) {
-      const ScalarBlock& s = c->sc_host[i];
-      oc->info[i].iterations += s.iters;
-      oc->info[i].matvecs += s.iters;
-      oc->info[i].rel_res_recursive = bb[i] > 0 ? std::sqrt(s.rr / bb[i]) : 0.0;
-      const bool conv = (s.flags & (FLAG_CONVERGED | FLAG_ZERO_RESIDUAL)) != 0;
-      oc->state[i] = conv ? 0 : (s.flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU)) ? 2 : 1;
+    ORI_TRY(group_cocg(ms, PREC_F64, std::vector<int>(M, o.max_iter), o.check_every, o.graph != 0, cache[0], &ran));
+    for (auto& j : jobs) {
+      for (int64_t i = 0; i < j.c->nrhs; ++i) {
+        const ScalarBlock& s = j.c->sc_host[i];
+        j.oc->info[i].iterations += s.iters;
+        j.oc->info[i].matvecs += s.iters;
+        j.oc->info[i].rel_res_recursive = j.bb[i] > 0 ? std::sqrt(s.rr / j.bb[i]) : 0.0;
+        const bool conv = (s.flags & (FLAG_CONVERGED | FLAG_ZERO_RESIDUAL)) != 0;
+        j.oc->state[i] = conv ? 0 : (s.flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU)) ? 2 : 1;
+      }
     }
     return ORI_OK;
   }
   // iterative refinement: FP64 true residual, complex64 inner COCG on the
-  // normalised correction equation of every unconverged right-hand side
-  ORI_TRY(sync_scalars(c));
-  std::vector<int> done(R, 0);
-  int inner_left = o.max_iter;
+  // normalised correction equation of every unconverged right-hand side;
+  // a member leaves the loop when all its right-hand sides are done, its
+  // inner iterations are spent, its inner solve made no progress or after
+  // max_outer cycles
+  ORI_TRY(sync_members(ms));
+  std::vector<std::vector<int>> done(M);
+  for (size_t m = 0; m < M; ++m) done[m].assign(jobs[m].c->nrhs, 0);
+  std::vector<int> inner_left(M, o.max_iter);
+  std::vector<bool> stopped(M, false);
   for (int outer = 0;; ++outer) {
-    bool all = true;
-    for (int64_t i = 0; i < R; ++i) {
-      const ScalarBlock& s = c->sc_host[i];
-      oc->info[i].rel_res_recursive = bb[i] > 0 ? std::sqrt(s.rr / bb[i]) : 0.0;
-      if (c->trace)
-        std::fprintf(stderr, "[ori] refine %d rhs %lld fp64 rel %.6e\n", outer, (long long)i,
-                     oc->info[i].rel_res_recursive);
-      if (done[i] == 0 && (s.rr <= target[i] || s.rr == 0.0)) done[i] = 1;
-      if (done[i] == 0 && outer == 0 && (s.flags & FLAG_BREAKDOWN_RHO)) done[i] = 2;
-      c->outer_m_host[i] = done[i] ? 0.0 : std::sqrt(s.rr);
-      // inner tolerance: inner_tol, or looser when the outer tolerance needs
-      // less (the correction reduces the residual by about the inner
-      // tolerance; half of what is left is asked for)
-      double t = o.inner_tol;
-      if (!done[i] && s.rr > 0.0) t = std::max(t, 0.5 * std::sqrt(target[i] / s.rr));
-      c->outer_m_host[R + i] = std::min(t, 0.5) * std::min(t, 0.5);
-      all = all && done[i];
+    std::vector<size_t> act;
+    for (size_t m = 0; m < M; ++m) {
+      if (stopped[m]) continue;
+      ori_ctx c = jobs[m].c;
+      const int64_t R = c->nrhs;
+      bool all = true;
+      for (int64_t i = 0; i < R; ++i) {
+        const ScalarBlock& s = c->sc_host[i];
+        const double bbi = jobs[m].bb[i];
+        jobs[m].oc->info[i].rel_res_recursive = bbi > 0 ? std::sqrt(s.rr / bbi) : 0.0;
+        if (c->trace)
+          std::fprintf(stderr, "[ori] refine %d rhs %lld fp64 rel %.6e\n", outer, (long long)i,
+                       jobs[m].oc->info[i].rel_res_recursive);
+        int& d = done[m][i];
+        if (d == 0 && (s.rr <= target[m][i] || s.rr == 0.0)) d = 1;
+        if (d == 0 && outer == 0 && (s.flags & FLAG_BREAKDOWN_RHO)) d = 2;
+        c->outer_m_host[i] = d ? 0.0 : std::sqrt(s.rr);
+        // inner tolerance: inner_tol, or looser when the outer tolerance
+        // needs less (the correction reduces the residual by about the
+        // inner tolerance; half of what is left is asked for)
+        double t = o.inner_tol;
+        if (!d && s.rr > 0.0) t = std::max(t, 0.5 * std::sqrt(target[m][i] / s.rr));
+        c->outer_m_host[R + i] = std::min(t, 0.5) * std::min(t, 0.5);
+        all = all && d;
+      }
+      if (all || outer >= o.max_outer || inner_left[m] <= 0)
+        stopped[m] = true;
+      else
+        act.push_back(m);
     }
-    if (all || outer >= o.max_outer || inner_left <= 0) break;
-    ORI_HIP(c, hipMemcpyAsync(c->outer_m, c->outer_m_host, 2 * R * sizeof(double), hipMemcpyHostToDevice,
-                              c->stream));
-    ORI_TRY(launch(c, K_INIT, PREC_F32, [&] {
-      return launch_init(PREC_F32, c->r, c->outer_m, c->xf, c->rf, P, R, c->partials, c->stream);
-    }));
-    ORI_TRY(finalize(c, rblocks(c), FIN_INIT, 0.0, 0, c->outer_m + R));
-    CocgOut co;
-    ORI_TRY(run_cocg(c, PREC_F32, c->xf, c->rf, c->pf, c->qf, c->Sf, inner_left, o.check_every, o.graph != 0, &co));
-    inner_left -= co.iters;
-    bool progress = false;
-    for (int64_t i = 0; i < R; ++i) {
-      if (done[i]) continue;
-      const ScalarBlock& s = c->sc_host[i];
-      oc->info[i].iterations += s.iters;
-      oc->info[i].matvecs += s.iters;
-      oc->info[i].matvecs_c64 += s.iters;
-      if (s.iters == 0 && (s.flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU))) done[i] = 2;
-      progress = progress || s.iters > 0;
+    if (act.empty()) break;
+    Members am;
+    std::vector<int> budget;
+    for (size_t m : act) {
+      ori_ctx c = jobs[m].c;
+      const int64_t P = c->P, R = c->nrhs;
+      ORI_HIP(c, hipMemcpyAsync(c->outer_m, c->outer_m_host, 2 * R * sizeof(double), hipMemcpyHostToDevice,
+                                c->stream));
+      ORI_TRY(launch(c, K_INIT, PREC_F32, [&] {
+        return launch_init(PREC_F32, c->r, c->outer_m, c->xf, c->rf, P, R, c->partials, c->stream);
+      }));
+      ORI_TRY(finalize(c, rblocks(c), FIN_INIT, 0.0, 0, c->outer_m + R));
+      am.push_back(c);
+      budget.push_back(inner_left[m]);
     }
-    ORI_TRY(launch(c, K_ELEMWISE, PREC_F32, [&] {
-      return launch_axpy_batch(PREC_F32, c->outer_m, c->xf, c->x, P, R, c->stream);
-    }));
-    ORI_TRY(true_residual_sym(c, rhs, c->x, c->r, 0.0, 0));
-    for (int64_t i = 0; i < R; ++i) {
-      if (done[i]) continue;
-      oc->info[i].matvecs++;
-      oc->info[i].refinements++;
+    ORI_TRY(group_cocg(am, PREC_F32, budget, o.check_every, o.graph != 0, cache[1], &ran));
+    for (size_t a = 0; a < act.size(); ++a) {
+      const size_t m = act[a];
+      ori_ctx c = jobs[m].c;
+      const int64_t P = c->P, R = c->nrhs;
+      inner_left[m] -= ran[a];
+      bool progress = false;
+      for (int64_t i = 0; i < R; ++i) {
+        if (done[m][i]) continue;
+        const ScalarBlock& s = c->sc_host[i];
+        jobs[m].oc->info[i].iterations += s.iters;
+        jobs[m].oc->info[i].matvecs += s.iters;
+        jobs[m].oc->info[i].matvecs_c64 += s.iters;
+        if (s.iters == 0 && (s.flags & (FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU))) done[m][i] = 2;
+        progress = progress || s.iters > 0;
+      }
+      ORI_TRY(launch(c, K_ELEMWISE, PREC_F32, [&] {
+        return launch_axpy_batch(PREC_F32, c->outer_m, c->xf, c->x, P, R, c->stream);
+      }));
+      ORI_TRY(true_residual_sym(c, jobs[m].rhs, c->x, c->r, 0.0, 0));
+      for (int64_t i = 0; i < R; ++i) {
+        if (done[m][i]) continue;
+        jobs[m].oc->info[i].matvecs++;
+        jobs[m].oc->info[i].refinements++;
+      }
+      if (!progress) stopped[m] = true;
     }
-    ORI_TRY(sync_scalars(c));
-    if (!progress) break;
+    ORI_TRY(sync_members(am));
   }
-  for (int64_t i = 0; i < R; ++i) oc->state[i] = done[i] == 1 ? 0 : done[i] == 2 ? 2 : 1;
+  for (size_t m = 0; m < M; ++m)
+    for (int64_t i = 0; i < jobs[m].c->nrhs; ++i)
+      jobs[m].oc->state[i] = done[m][i] == 1 ? 0 : done[m][i] == 2 ? 2 : 1;
   return ORI_OK;
 }
 
-// Forward problem for every right-hand side: w = S u (guess) or 0, solve,
-// recover u (recover: w / S, or u0 - G0 S w), true residual.
-ori_status forward_solve(ori_ctx c, const ori_solve_opts& o, cxd* u, Outcome* oc) {
-  const int64_t P = c->P, R = c->nrhs;
-  oc->info.assign(R, ori_solve_info{});
-  oc->state.assign(R, 1);
+ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const std::vector<double>& bb, Outcome* oc) {
+  std::vector<SymJob> jobs{SymJob{c, rhs, bb, oc}};
+  return solve_sym_group(jobs, o, c->graphs);
+}
+
+// Forward problem for every right-hand side of every context: w = S u
+// (guess) or 0, solve (in lockstep), recover u (recover: w / S, or
+// u0 - G0 S w), true residual.
+ori_status forward_solve_group(const Members& ms, const ori_solve_opts& o, const std::vector<cxd*>& u,
+                               std::vector<Outcome>* ocs, IterGraph* cache) {
   const double tol2 = o.tol * o.tol;
-  if (o.use_x0) {
-    ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_mul(c->S, u, c->x, P, R, c->stream); }));
-    ORI_TRY(true_residual_sym(c, c->b, c->x, c->r, tol2, 1));
-    for (auto& i : oc->info) i.matvecs++;
-  } else {
-    ORI_TRY(launch(c, K_INIT, PREC_F64, [&] {
-      return launch_init(PREC_F64, c->b, nullptr, c->x, c->r, P, R, c->partials, c->stream);
-    }));
-    ORI_TRY(finalize(c, rblocks(c), FIN_INIT, tol2, 1));
+  ocs->resize(ms.size());
+  std::vector<SymJob> jobs;
+  for (size_t m = 0; m < ms.size(); ++m) {
+    ori_ctx c = ms[m];
+    const int64_t P = c->P, R = c->nrhs;
+    Outcome* oc = &(*ocs)[m];
+    oc->info.assign(R, ori_solve_info{});
+    oc->state.assign(R, 1);
+    if (o.use_x0) {
+      ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] { return launch_mul(c->S, u[m], c->x, P, R, c->stream); }));
+      ORI_TRY(true_residual_sym(c, c->b, c->x, c->r, tol2, 1));
+      for (auto& i : oc->info) i.matvecs++;
+    } else {
+      ORI_TRY(launch(c, K_INIT, PREC_F64, [&] {
+        return launch_init(PREC_F64, c->b, nullptr, c->x, c->r, P, R, c->partials, c->stream);
+      }));
+      ORI_TRY(finalize(c, rblocks(c), FIN_INIT, tol2, 1));
+    }
+    jobs.push_back(SymJob{c, c->b, c->bnorm2, oc});
   }
-  ORI_TRY(solve_sym(c, o, c->b, c->bnorm2, oc));
-  int rec = 0;
-  ORI_TRY(recover(c, c->x, u, &rec));
-  for (auto& i : oc->info) {
-    i.matvecs += rec;
-    i.rel_res_true = -1.0;
-  }
-  if (o.true_residual) {
-    std::vector<double> rel;
-    ORI_TRY(true_residual_orig(c, u, &rel));
-    for (int64_t i = 0; i < R; ++i) {
-      oc->info[i].matvecs++;
-      oc->info[i].rel_res_true = rel[i];
+  ORI_TRY(solve_sym_group(jobs, o, cache));
+  for (size_t m = 0; m < ms.size(); ++m) {
+    ori_ctx c = ms[m];
+    Outcome* oc = &(*ocs)[m];
+    int rec = 0;
+    ORI_TRY(recover(c, c->x, u[m], &rec));
+    for (auto& i : oc->info) {
+      i.matvecs += rec;
+      i.rel_res_true = -1.0;
+    }
+    if (o.true_residual) {
+      std::vector<double> rel;
+      ORI_TRY(true_residual_orig(c, u[m], &rel));
+      for (int64_t i = 0; i < c->nrhs; ++i) {
+        oc->info[i].matvecs++;
+        oc->info[i].rel_res_true = rel[i];
+      }
     }
   }
+  return ORI_OK;
+}
+
+ori_status forward_solve(ori_ctx c, const ori_solve_opts& o, cxd* u, Outcome* oc) {
+  std::vector<Outcome> ocs;
+  ORI_TRY(forward_solve_group(Members{c}, o, std::vector<cxd*>{u}, &ocs, c->graphs));
+  *oc = std::move(ocs[0]);
   return ORI_OK;
 }
 
@@ -1064,6 +1196,29 @@ ori_status static_workspace(int dev, void** out) {
   return ORI_OK;
 }
 
+}  // namespace
+
+// A group of independent problems solved together (ori_group_*).  Each
+// member context has a stream of its own, so the members' eager launches run
+// side by side; their COCG iteration blocks replay one graph with a chain
+// per member.  Group calls start after the work already queued on the
+// caller's stream (an event) and return after all of theirs is done.
+struct ori_group_s {
+  std::vector<ori_ctx> members;
+  std::vector<hipStream_t> streams;  // one per member, owned by the group
+  hipStream_t caller = nullptr;
+  hipEvent_t ready = nullptr;
+  IterGraph graphs[2];  // per vector precision
+};
+
+namespace {
+// order member m's stream after the work queued on the caller's stream
+ori_status group_wait_caller(ori_group g, size_t m) {
+  ori_ctx c = g->members[m];
+  ORI_HIP(c, hipEventRecord(g->ready, g->caller));
+  ORI_HIP(c, hipStreamWaitEvent(c->stream, g->ready, 0));
+  return ORI_OK;
+}
 }  // namespace
 
 // ===========================================================================
@@ -1533,6 +1688,110 @@ ori_status ori_solve(ori_ctx c, const ori_solve_opts* opts_in, void* u_out, ori_
   return end_status(c, oc, "COCG");
 }
 
+ori_status ori_group_create(const ori_grid* grids, int32_t nprob, int32_t provision, void* stream, ori_group* out) {
+  if (!out) return set_err(nullptr, ORI_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grids) return set_err(nullptr, ORI_ERR_INVALID_ARG, "grids is NULL");
+  if (nprob < 1 || nprob > 64) return set_err(nullptr, ORI_ERR_INVALID_ARG, "nprob = %d out of [1, 64]", nprob);
+  ori_group g = new ori_group_s();
+  g->caller = static_cast<hipStream_t>(stream);
+  if (hipEventCreateWithFlags(&g->ready, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    g->ready = nullptr;
+    ori_group_destroy(g);
+    return set_err(nullptr, ORI_ERR_DEVICE, "hipEventCreate failed (no GPU?)");
+  }
+  for (int32_t i = 0; i < nprob; ++i) {
+    hipStream_t sm = nullptr;
+    if (hipStreamCreateWithFlags(&sm, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      ori_group_destroy(g);
+      return set_err(nullptr, ORI_ERR_DEVICE, "problem %d: hipStreamCreate failed", i);
+    }
+    g->streams.push_back(sm);
+    ori_ctx c = nullptr;
+    const ori_status st = ori_create(&grids[i], 1, provision, 0, sm, &c);
+    if (st != ORI_OK) {
+      const std::string msg = g_last_error;
+      ori_group_destroy(g);
+      return set_err(nullptr, st, "problem %d: %s", i, msg.c_str());
+    }
+    g->members.push_back(c);
+  }
+  *out = g;
+  return ORI_OK;
+}
+
+ori_status ori_group_load(ori_group g, int32_t i, double k, const void* h, const double* N, const void* u0) {
+  if (!g) return set_err(nullptr, ORI_ERR_INVALID_ARG, "group is NULL");
+  if (i < 0 || i >= static_cast<int32_t>(g->members.size()))
+    return set_err(nullptr, ORI_ERR_INVALID_ARG, "problem %d out of [0, %zu)", i, g->members.size());
+  ori_ctx c = g->members[i];
+  ori_status st = guard(c);
+  if (st == ORI_OK) st = group_wait_caller(g, i);
+  if (st == ORI_OK) st = ori_load(c, k, h, N, u0);
+  if (st != ORI_OK) set_err(nullptr, st, "problem %d: %s", i, c->err.c_str());
+  return st;
+}
+
+ori_status ori_group_solve(ori_group g, const ori_solve_opts* opts_in, void* const* u, ori_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!g) return set_err(nullptr, ORI_ERR_INVALID_ARG, "group is NULL");
+  if (!u) return set_err(nullptr, ORI_ERR_INVALID_ARG, "u is NULL");
+  const size_t M = g->members.size();
+  ori_solve_opts o{};
+  std::vector<cxd*> us(M);
+  for (size_t m = 0; m < M; ++m) {
+    ori_ctx c = g->members[m];
+    ori_status st = guard(c);
+    if (st == ORI_OK) st = check_opts(c, opts_in, &o);
+    if (st == ORI_OK) st = check_dev_ptr(c, u[m], c->nrhs * c->P * 16, "u");
+    if (st == ORI_OK) st = group_wait_caller(g, m);
+    if (st != ORI_OK) return set_err(nullptr, st, "problem %zu: %s", m, c->err.c_str());
+    us[m] = static_cast<cxd*>(u[m]);
+  }
+  std::vector<Outcome> ocs;
+  ori_status st = forward_solve_group(g->members, o, us, &ocs, g->graphs);
+  for (size_t m = 0; m < M && st == ORI_OK; ++m) {
+    ori_ctx c = g->members[m];
+    if (hipStreamSynchronize(c->stream) != hipSuccess) st = set_err(c, ORI_ERR_DEVICE, "hipStreamSynchronize failed");
+  }
+  if (st != ORI_OK) {
+    for (ori_ctx c : g->members)
+      if (c->err != "no error") return set_err(nullptr, st, "%s", c->err.c_str());
+    return st;
+  }
+  const double secs = elapsed(t0);
+  ori_status worst = ORI_OK;
+  for (size_t m = 0; m < M; ++m) {
+    ori_ctx c = g->members[m];
+    for (auto& i : ocs[m].info) i.seconds = secs;
+    c->last_info = ocs[m].info;
+    if (info) {
+      info[m] = aggregate(ocs[m]);
+      info[m].seconds = secs;
+    }
+    const ori_status sm = end_status(c, ocs[m], "COCG");
+    if (sm != ORI_OK && worst == ORI_OK) {
+      worst = sm;
+      set_err(nullptr, sm, "problem %zu: %s", m, c->err.c_str());
+    }
+  }
+  return worst;
+}
+
+void ori_group_destroy(ori_group g) {
+  if (!g) return;
+  for (auto& gr : g->graphs) {
+    if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+    if (gr.done) (void)hipEventDestroy(gr.done);
+  }
+  for (ori_ctx c : g->members) ori_destroy(c);  // waits for each member's stream
+  for (hipStream_t sm : g->streams) (void)hipStreamDestroy(sm);
+  if (g->ready) (void)hipEventDestroy(g->ready);
+  delete g;
+}
+
 ori_status ori_batch_info(ori_ctx c, int32_t i, ori_solve_info* info) {
   if (!c) return set_err(nullptr, ORI_ERR_INVALID_ARG, "context is NULL");
   if (!info) return set_err(c, ORI_ERR_INVALID_ARG, "info is NULL");
@@ -1674,8 +1933,10 @@ void ori_destroy(ori_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);  // all of the context's work is on its stream
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-  for (auto& g : c->graphs)
+  for (auto& g : c->graphs) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.done) (void)hipEventDestroy(g.done);
+  }
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   if (c->outer_m_host) (void)hipHostFree(c->outer_m_host);

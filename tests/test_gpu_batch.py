@@ -159,23 +159,40 @@ def test_uneven_batch_of_independent_problems():
         assert res <= 5 * tol
 
 
-def test_solve_many_reuses_contexts_bitwise():
-    # kept contexts are loaded with the next problem of their grid: the
-    # results equal those of fresh contexts bit for bit, on repeated calls
-    say("[uneven, reused contexts] n in {32, 48}")
-    probs = []
-    for j, n in enumerate((32, 48, 32)):
-        c = workloads.make_case(n, 5.0, seed=30 + j)
-        probs.append(dict(n=n, k=5.0, h=gpu(c["h"]), N=gpu(c["N"]), u0=gpu(c["u0"])))
-    fresh = ori.solve_many(probs, tol=1e-9)
-    try:
-        for _ in range(2):
-            kept = ori.solve_many(probs, tol=1e-9, reuse_contexts=True)
-            for (u, info), (uf, _) in zip(kept, fresh):
-                assert torch.equal(u, uf)
-                assert info["rel_res_true"] < 1e-8
-        assert sum(len(v) for v in ori._CTX_POOL.values()) >= 2
-    finally:
-        ori.release_contexts()
-    assert not ori._CTX_POOL
+def test_group_reloaded_and_both_precisions_bitwise():
+    # one group (n = 12, 20, 9 and 16: three padded lengths, one of them
+    # with zeros between n and L/2) solved, reloaded with other data and
+    # solved again, with and without graph replay, in both precisions: every
+    # result equals the problem's own ori_solve bit for bit
+    say("[group] n in {12, 20, 9, 16}")
+    ns = (12, 20, 9, 16)
+    with ori.ori_group_create(ns) as g:
+        for rnd in range(2):
+            cases = [workloads.make_case(n, 3.0 + j, seed=40 + 10 * rnd + j) for j, n in enumerate(ns)]
+            for j, (n, c) in enumerate(zip(ns, cases)):
+                ori.ori_group_load(g, j, 3.0 + j, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]))
+            for prec, graph in ((ori.ORI_FP64, True), (ori.ORI_MIXED, True), (ori.ORI_FP64, False)):
+                us = [torch.empty(n ** 3, dtype=torch.complex128, device="cuda") for n in ns]
+                _, infos = ori.ori_group_solve(g, us, tol=1e-10, precision=prec, graph=graph)
+                for j, (n, c) in enumerate(zip(ns, cases)):
+                    u1, i1 = ori.solve(n, 3.0 + j, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]), tol=1e-10,
+                                       precision=prec)
+                    assert torch.equal(us[j], u1), (rnd, prec, graph, n)
+                    assert infos[j]["iterations"] == i1["iterations"]
+                    assert infos[j]["rel_res_true"] == i1["rel_res_true"]
 
+
+def test_group_reports_nonconvergence_of_one_problem():
+    # an iteration cap that one problem cannot meet: its status comes back,
+    # the others are solved and every output is filled
+    ns = (8, 12)
+    with ori.ori_group_create(ns) as g:
+        cases = [workloads.make_case(n, 5.0, seed=70 + n) for n in ns]
+        for j, (n, c) in enumerate(zip(ns, cases)):
+            ori.ori_group_load(g, j, 5.0, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]))
+        us = [torch.full((n ** 3,), complex("nan"), dtype=torch.complex128, device="cuda") for n in ns]
+        st, infos = ori.ori_group_solve(g, us, tol=1e-14, max_iter=3, raise_on_error=False)
+        assert st == ori.ORI_ERR_NOT_CONVERGED
+        assert all(i["iterations"] == 3 for i in infos)
+        assert all(torch.isfinite(torch.view_as_real(u)).all() for u in us)
+        assert "problem 0" in ori.ori_last_error()

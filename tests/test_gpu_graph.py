@@ -93,11 +93,11 @@ def test_graph_batch_and_adjoint():
 
 
 def test_graph_replay_in_concurrent_contexts():
-    # contexts driven from four threads at once, each building and replaying
-    # its own iteration graphs (graph replay on, the default), while a fifth
-    # thread allocates and frees device memory through torch: every result
-    # equals the same problem solved with eager launches in one thread, bit
-    # for bit, over three rounds
+    # contexts driven from four threads at once (each its own stream), each
+    # building and replaying its own iteration graphs (graph replay on, the
+    # default), while a fifth thread allocates and frees device memory through
+    # torch: every result equals the same problem solved with eager launches
+    # in one thread, bit for bit, over three rounds
     import random
     import threading
 
@@ -107,7 +107,9 @@ def test_graph_replay_in_concurrent_contexts():
         c = workloads.make_case(n, 4.0, seed=90 + j)
         probs.append(dict(n=n, k=4.0, h=gpu(c["h"]), N=gpu(c["N"]), u0=gpu(c["u0"])))
     ref = [ori.solve(p["n"], p["k"], p["h"], p["N"], p["u0"], tol=1e-10, graph=False)[0] for p in probs]
+    torch.cuda.synchronize()
     stop = threading.Event()
+    errors = []
 
     def churn():
         rng = random.Random(5)
@@ -117,14 +119,27 @@ def test_graph_replay_in_concurrent_contexts():
             del t
             torch.cuda.empty_cache()
 
+    def worker(p, r, rnd):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                u, info = ori.solve(p["n"], p["k"], p["h"], p["N"], p["u0"], tol=1e-10, graph=True)
+            s.synchronize()
+            if not torch.equal(u, r) or not info["rel_res_true"] < 1e-9:
+                errors.append((rnd, p["n"]))
+        except BaseException as e:  # reported below
+            errors.append((rnd, p["n"], repr(e)))
+
     th = threading.Thread(target=churn)
     th.start()
     try:
         for rnd in range(3):
-            res = ori.solve_many(probs, tol=1e-10, graph=True, max_workers=4)
-            for p, r, (u, info) in zip(probs, ref, res):
-                assert torch.equal(u, r), (rnd, p["n"])
-                assert info["rel_res_true"] < 1e-9
+            ws = [threading.Thread(target=worker, args=(p, r, rnd)) for p, r in zip(probs, ref)]
+            for w in ws:
+                w.start()
+            for w in ws:
+                w.join()
     finally:
         stop.set()
         th.join()
+    assert not errors, errors
