@@ -414,8 +414,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle rows for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--layout", default="2,0,0,1/3,0,0,1",
-                    help="pass layout LG,NP,PF,ZNP[/LG,NP,PF,ZNP] (complex128 / complex64 passes: i1 row block, "
+    ap.add_argument("--layout", default="2,0,0,1,0/3,0,0,1,0",
+                    help="pass layout LG,NP,PF,ZNP,ZPLAN[/...] (complex128 / complex64 passes: i1 row block, "
                          "narrow strided tiles, Z prefetch, narrow Z tiles); the default is what ori_tune picks "
                          "at n = 256 on MI355X; 'auto' tunes before timing, 'default' keeps the library's")
     ap.add_argument("--workload", default="solve", choices=("solve", "batch", "uneven", "gradient", "field"),
@@ -469,15 +469,15 @@ def main():
         parts = a.layout.split("/")
         for prec, spec in zip((ori.ORI_FP64, ori.ORI_MIXED), parts if len(parts) == 2 else parts * 2):
             vals = [int(v) for v in spec.split(",")]
-            if len(vals) not in (3, 4):
-                sys.exit(f"--layout: expected LG,NP,PF[,ZNP], got {spec!r}")
+            if len(vals) not in (3, 4, 5):
+                sys.exit(f"--layout: expected LG,NP,PF[,ZNP[,ZPLAN]], got {spec!r}")
             ori.ori_set_layout(ctx, prec, *vals)
 
     def lay_str(prec):
         d = ori.ori_get_layout(ctx, prec)
-        return f"{d['blk_lg']},{d['narrow']},{d['prefetch']},{d['znarrow']}"
+        return f"{d['blk_lg']},{d['narrow']},{d['prefetch']},{d['znarrow']},{d['zplan']}"
     layout = {"fp64": lay_str(ori.ORI_FP64), "c64": lay_str(ori.ORI_MIXED)}
-    log(f"[bench] layout (blk_lg,narrow,prefetch,znarrow): {layout}")
+    log(f"[bench] layout (blk_lg,narrow,prefetch,znarrow,zplan): {layout}")
 
     def step(precision):
         ori.ori_load(ctx, k, h, N, u0)

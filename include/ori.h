@@ -314,8 +314,8 @@ ori_status ori_interpolation_difference(ori_ctx ctx, const void* y, const void* 
                                        double fine_offset, double* diff);
 
 /* Layout of the FFT passes of one precision.  Performance only: blk_lg and
- * prefetch leave every result bitwise unchanged; narrow tiles may change
- * results at the level of rounding. */
+ * prefetch leave every result bitwise unchanged; narrow tiles and the radix
+ * plan may change results at the level of rounding. */
 typedef struct {
   int32_t blk_lg;   /* log2 of the row block (along i1) of the work array between
                        the strided and Z passes, 0..6, n divisible by 2^blk_lg  */
@@ -323,6 +323,12 @@ typedef struct {
                        workgroup) in the two strided passes                     */
   int32_t prefetch; /* 1: the Z pass loads its next tile while it transforms one */
   int32_t znarrow;  /* 1: narrow pencil tiles in the Z pass                      */
+  int32_t zplan;    /* radix plan of the Z pass's transforms: 0 the padded
+                       length's default, 1 its alternative (another radix
+                       order or radices with the same threads per pencil:
+                       L = 32, 48, 80, 96, 128, 192, 256, 384, 512, 1024; at
+                       L = 1024 it is 16 x 8 x 8, the complex128 default
+                       there); 1 is invalid at the other lengths              */
 } ori_layout;
 
 /* Layout in use for precision ORI_FP64 (complex128 FFTs) or ORI_MIXED

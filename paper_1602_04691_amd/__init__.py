@@ -73,7 +73,7 @@ class SolveInfo(ctypes.Structure):
 
 class Layout(ctypes.Structure):
     _fields_ = [("blk_lg", ctypes.c_int32), ("narrow", ctypes.c_int32), ("prefetch", ctypes.c_int32),
-                ("znarrow", ctypes.c_int32)]
+                ("znarrow", ctypes.c_int32), ("zplan", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -423,8 +423,8 @@ def ori_get_layout(ctx, precision=ORI_FP64):
     return out.as_dict()
 
 
-def ori_set_layout(ctx, precision=ORI_FP64, blk_lg=4, narrow=0, prefetch=0, znarrow=0):
-    lay = Layout(int(blk_lg), int(narrow), int(prefetch), int(znarrow))
+def ori_set_layout(ctx, precision=ORI_FP64, blk_lg=4, narrow=0, prefetch=0, znarrow=0, zplan=0):
+    lay = Layout(int(blk_lg), int(narrow), int(prefetch), int(znarrow), int(zplan))
     _check(lib().ori_set_layout(ctx.handle, int(precision), ctypes.byref(lay)), ctx)
 
 

@@ -282,20 +282,33 @@ struct Regs {
 //  0: tw is the length-L table exp(-2 pi i m / L); the powers w, w^2, w^4,
 //     w^8 are read, the other powers are products of two of them;
 //  1: tw is the stage-major table (stage_table): every power w^r of every
-//     k is read, no products (fewer vector instructions, more table).
+//     k is read, no products (fewer vector instructions, more table);
+//  2: tw is the stage-major table of the powers of two only: w, w^2, w^4,
+//     w^8 are read, the others are products as in 0.  The lanes of a
+//     wavefront read adjacent entries (in the length-L table a stage with
+//     few butterflies reads entries TS apart, which share LDS banks), and
+//     the table holds only what the stages read.
 template <typename T, int L, bool INV, int TP = threads_per_pencil(L), int PV = 0, int TWM = 0>
 struct Engine {
   using St = Stages<L, INV, TP, PV>;
   static constexpr int NS = St::NS;
   static constexpr int TPP = St::TPP;
 
-  // Stage-major twiddle table: stage s >= 1 holds w^(r k TS) for r = 1..R-1
-  // and k < ns(s) (TS = L / (ns(s) R)) at stage_offset(s) + (r - 1) ns(s) + k,
-  // forward sign (the inverse conjugates on use).  Consecutive k of one r are
-  // adjacent, so the lanes of a wavefront read adjacent entries.
+  // Stage-major twiddle table: stage s >= 1 holds w^(r k TS) for the powers
+  // r it reads (TWM 1: r = 1..R-1; TWM 2: r = 1, 2, 4, 8 below R) and k <
+  // ns(s) (TS = L / (ns(s) R)), power by power: the q-th power read at
+  // stage_offset(s) + q ns(s) + k, forward sign (the inverse conjugates on
+  // use).  Consecutive k of one r are adjacent, so the lanes of a wavefront
+  // read adjacent entries.
+  static constexpr int powers_read(int R) {
+    if (TWM != 2) return R - 1;
+    int c = 0;
+    for (int r = 1; r < R; r *= 2) ++c;
+    return c;
+  }
   static constexpr int stage_offset(int s) {
     int o = 0;
-    for (int q = 1; q < s; ++q) o += (St::radix(q) - 1) * St::ns(q);
+    for (int q = 1; q < s; ++q) o += powers_read(St::radix(q)) * St::ns(q);
     return o;
   }
   static constexpr int stage_table_size() { return stage_offset(NS); }
@@ -308,8 +321,8 @@ struct Engine {
       constexpr int q = decltype(Q)::value;
       if constexpr (q >= 1) {
         constexpr int nsq = St::ns(q), R = St::radix(q), TS = L / (nsq * R);
-        for (int idx = tid; idx < (R - 1) * nsq; idx += nthreads) {
-          const int r = idx / nsq + 1, k = idx % nsq;
+        for (int idx = tid; idx < powers_read(R) * nsq; idx += nthreads) {
+          const int r = TWM == 2 ? 1 << (idx / nsq) : idx / nsq + 1, k = idx % nsq;
           dst[stage_offset(q) + idx] = tw_full[r * k * TS];
         }
       }
@@ -353,6 +366,18 @@ struct Engine {
         if constexpr (TWM == 1) {
 #pragma unroll
           for (int r = 1; r < R; ++r) w[r] = tw[stage_offset(s) + (r - 1) * NSs + k];
+        } else if constexpr (TWM == 2) {
+#pragma unroll
+          for (int r = 1, q = 0; r < R; ++r) {
+            if ((r & (r - 1)) == 0) {
+              w[r] = tw[stage_offset(s) + q * NSs + k];
+              ++q;
+            } else {
+              const int low = r & -r;
+              const cx<T> a = w[r - low], c = w[low];
+              w[r] = cx<T>{a.re * c.re - a.im * c.im, a.re * c.im + a.im * c.re};
+            }
+          }
         } else {
           twiddles<R, TS>(w, k, tw);
         }

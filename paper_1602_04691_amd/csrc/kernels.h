@@ -109,9 +109,10 @@ struct StridedArgs {
 // i.e. i1 is split into blocks of 2^e_lg rows stored next to each other, so
 // that one pencil of the Z pass spans n / 2^e_lg far-apart regions instead
 // of n.  The spectrum is even along every axis and stored as its octant:
-// khat[(m1 * kp + m2) * kp + m3], kp = n + 1, m = min(k, L - k) per axis, so
-// a tile of consecutive k3 reads one run, ascending below n and descending
-// above.
+// khat[(m1 * kp + m2) * kp + m3], kp = L / 2 + 1, m = min(k, L - k) per axis,
+// so a tile of consecutive k3 reads one run, ascending below L / 2 and
+// descending above.  plan: the radix plan of the transforms (0 the length's
+// default, 1 its alternative where plan.h defines one).
 struct ZArgs {
   void* buf;
   int64_t n;
@@ -120,9 +121,10 @@ struct ZArgs {
   int64_t nrhs, batch_stride;
   int32_t prefetch;    // 1: load the next tile while transforming the current one
   int32_t rhs_slices;  // workgroups per (m2, k3 tile), each taking a contiguous share of the right-hand sides
-  const void* khat;     // spectrum (T), octant [n+1][n+1][n+1]
+  const void* khat;     // spectrum (T), octant [kp][kp][kp]
   int64_t kp;
   const void* tw;
+  int32_t plan;
 };
 
 // Kernel spectrum: passes 1 and 2 in place on an octant scratch

@@ -85,8 +85,9 @@ struct Knobs {
   int np_sel = 0;  // strided tile width: 0 wide, 1 narrow
   int zpf = 0;     // Z pass: prefetch the next tile
   int z_np = 0;    // Z tile width: 0 wide, 1 narrow
+  int zplan = 0;   // Z radix plan: 0 the length's default, 1 its alternative (plan.h)
   bool operator==(const Knobs& o) const {
-    return blk_lg == o.blk_lg && np_sel == o.np_sel && zpf == o.zpf && z_np == o.z_np;
+    return blk_lg == o.blk_lg && np_sel == o.np_sel && zpf == o.zpf && z_np == o.z_np && zplan == o.zplan;
   }
 };
 
@@ -423,7 +424,8 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   const int64_t zbase = c->K->zpass_blocks(fprec, kn.z_np);
   int64_t rs = std::min<int64_t>(R, (kZMinWorkgroups + zbase - 1) / zbase);
   if (rs > 1) rs = (R + (R + rs - 1) / rs - 1) / ((R + rs - 1) / rs);
-  ZArgs z{B, n, lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, static_cast<int32_t>(rs), kh, L / 2 + 1, tw};
+  ZArgs z{B,  n,  lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, static_cast<int32_t>(rs),
+          kh, L / 2 + 1, tw, kn.zplan};
   ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, z, c->stream); }));
 
   StridedArgs i2{B, A, R * n, L, n, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};
@@ -727,20 +729,27 @@ ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel)
 // Layout knobs: the i1 blocking of the B work array (ZArgs), the tile widths
 // of the strided and of the Z passes and the Z-pass prefetch.  Start from the
 // measured defaults, or from the tuned layout of this (device, n, nrhs);
-// ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF / ORI_TUNE_ZNP override both
+// ORI_TUNE_BLK_LG / ORI_TUNE_NP / ORI_TUNE_ZPF / ORI_TUNE_ZNP / ORI_TUNE_ZPLAN override both
 // for tuning runs.  Narrow Z tiles by default where they measured faster:
 // complex64 at every length (at L = 512 its wide workgroup of 16 wavefronts
 // fits once per CU, the narrow one three times) and complex128 from L = 512
 // on (0.57 vs 0.65 ms at n = 256, while wide tiles win at L = 256).
-bool valid_knobs(int64_t n, const Knobs& k) {
+bool valid_knobs(int64_t n, int64_t L, const Knobs& k) {
   return k.blk_lg >= 0 && k.blk_lg <= 6 && n % (int64_t{1} << k.blk_lg) == 0 && (k.np_sel == 0 || k.np_sel == 1) &&
-         (k.zpf == 0 || k.zpf == 1) && (k.z_np == 0 || k.z_np == 1);
+         (k.zpf == 0 || k.zpf == 1) && (k.z_np == 0 || k.z_np == 1) &&
+         (k.zplan == 0 || (k.zplan == 1 && has_plan_variant(static_cast<int>(L))));
 }
+
+// The Z pass's radix plan by default: the alternative (16 x 8 x 8) for the
+// complex128 pass at L = 1024, where it measured faster, else the length's
+// default.
+int default_zplan(int64_t L, int f) { return (L == 1024 && f == 0) ? 1 : 0; }
 
 void choose_layout(ori_ctx c) {
   for (int f = 0; f < 2; ++f) {
     Knobs k;
     k.z_np = (f == 1 || c->L >= 512) ? 1 : 0;
+    k.zplan = default_zplan(c->L, f);
     while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
     c->knob[f] = k;
   }
@@ -757,6 +766,7 @@ void choose_layout(ori_ctx c) {
     if (const char* e = std::getenv("ORI_TUNE_NP")) k.np_sel = std::atoi(e) ? 1 : 0;
     if (const char* e = std::getenv("ORI_TUNE_ZPF")) k.zpf = std::atoi(e) ? 1 : 0;
     if (const char* e = std::getenv("ORI_TUNE_ZNP")) k.z_np = std::atoi(e) ? 1 : 0;
+    if (const char* e = std::getenv("ORI_TUNE_ZPLAN")) k.zplan = std::atoi(e) && has_plan_variant(c->L) ? 1 : 0;
     if (k.blk_lg < 0) k.blk_lg = 0;
     if (k.blk_lg > 6) k.blk_lg = 6;
     while (k.blk_lg > 0 && (c->n % (int64_t{1} << k.blk_lg)) != 0) --k.blk_lg;
@@ -1573,7 +1583,7 @@ ori_status ori_get_layout(ori_ctx c, int32_t precision, ori_layout* out) {
   if (!out) return set_err(c, ORI_ERR_INVALID_ARG, "out is NULL");
   if (precision != ORI_FP64 && precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
   const Knobs& k = c->knob[precision == ORI_MIXED ? 1 : 0];
-  *out = ori_layout{k.blk_lg, k.np_sel, k.zpf, k.z_np};
+  *out = ori_layout{k.blk_lg, k.np_sel, k.zpf, k.z_np, k.zplan};
   return ORI_OK;
 }
 
@@ -1581,11 +1591,13 @@ ori_status ori_set_layout(ori_ctx c, int32_t precision, const ori_layout* in) {
   ORI_TRY(guard(c));
   if (!in) return set_err(c, ORI_ERR_INVALID_ARG, "layout is NULL");
   if (precision != ORI_FP64 && precision != ORI_MIXED) return set_err(c, ORI_ERR_INVALID_ARG, "bad precision");
-  const Knobs k{in->blk_lg, in->narrow, in->prefetch, in->znarrow};
-  if (!valid_knobs(c->n, k))
+  const Knobs k{in->blk_lg, in->narrow, in->prefetch, in->znarrow, in->zplan};
+  if (!valid_knobs(c->n, c->L, k))
     return set_err(c, ORI_ERR_INVALID_ARG,
-                   "layout {blk_lg %d, narrow %d, prefetch %d, znarrow %d} is not valid for n = %lld", in->blk_lg,
-                   in->narrow, in->prefetch, in->znarrow, (long long)c->n);
+                   "layout {blk_lg %d, narrow %d, prefetch %d, znarrow %d, zplan %d} is not valid for n = %lld "
+                   "(padded length %lld%s)",
+                   in->blk_lg, in->narrow, in->prefetch, in->znarrow, in->zplan, (long long)c->n, (long long)c->L,
+                   has_plan_variant(static_cast<int>(c->L)) ? "" : ", one radix plan");
   ORI_HIP(c, hipStreamSynchronize(c->stream));
   ORI_TRY(drop_graphs(c));
   c->knob[precision == ORI_MIXED ? 1 : 0] = k;
@@ -1625,9 +1637,10 @@ ori_status ori_tune(ori_ctx c, int32_t reps, ori_layout* best, double* ms_per_pr
     for (int lg = 0; lg <= 6 && st == ORI_OK; ++lg)
       for (int np = 0; np <= 1 && st == ORI_OK; ++np)
         for (int pf = 0; pf <= 1 && st == ORI_OK; ++pf)
-          for (int znp = 0; znp <= 1 && st == ORI_OK; ++znp) {
-            const Knobs k{lg, np, pf, znp};
-            if (!valid_knobs(c->n, k)) continue;
+          for (int znp = 0; znp <= 1 && st == ORI_OK; ++znp)
+            for (int zp = 0; zp <= 1 && st == ORI_OK; ++zp) {
+            const Knobs k{lg, np, pf, znp, zp};
+            if (!valid_knobs(c->n, c->L, k)) continue;
             c->knob[f] = k;
             auto product = [&] {
               return matvec(c, fp, fp, plain_f1(x, S), epi(y, x, 1.0, nullptr, 0.0, S, 1.0, nullptr, 0), nullptr);
@@ -1649,11 +1662,12 @@ ori_status ori_tune(ori_ctx c, int32_t reps, ori_layout* best, double* ms_per_pr
     c->knob[f] = st == ORI_OK ? win : start;
     found.k[f] = win;
     found.have[f] = st == ORI_OK;
-    if (best) best[f] = ori_layout{win.blk_lg, win.np_sel, win.zpf, win.z_np};
+    if (best) best[f] = ori_layout{win.blk_lg, win.np_sel, win.zpf, win.z_np, win.zplan};
     if (ms_per_product) ms_per_product[f] = st == ORI_OK ? win_ms : -1.0;
   }
   if (!mixed) {
-    if (best) best[1] = ori_layout{c->knob[1].blk_lg, c->knob[1].np_sel, c->knob[1].zpf, c->knob[1].z_np};
+    if (best) best[1] = ori_layout{c->knob[1].blk_lg, c->knob[1].np_sel, c->knob[1].zpf, c->knob[1].z_np,
+                                   c->knob[1].zplan};
     if (ms_per_product) ms_per_product[1] = -1.0;
   }
   (void)hipEventDestroy(e0);

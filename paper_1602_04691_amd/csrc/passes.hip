@@ -88,23 +88,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, 
   return __builtin_amdgcn_make_buffer_rsrc(p, 0, bytes, 0x00020000);
 }
 
+// off: the lane's byte offset; soff: a byte offset the same for every lane
+// (a scalar register)
 template <typename T>
-__device__ __forceinline__ cx<T> buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+__device__ __forceinline__ cx<T> buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0) {
   if constexpr (sizeof(T) == 8) {
-    return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0));
+    return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off),
+                                                                             static_cast<int>(soff), 0));
   } else {
-    return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0));
+    return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off),
+                                                                            static_cast<int>(soff), 0));
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t off, cx<T> v) {
+__device__ __forceinline__ void buffer_store(__amdgpu_buffer_rsrc_t r, uint32_t off, cx<T> v, uint32_t soff = 0) {
   using V4 = __attribute__((ext_vector_type(4))) unsigned int;
   using V2 = __attribute__((ext_vector_type(2))) unsigned int;
   if constexpr (sizeof(T) == 8) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, static_cast<int>(off), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, static_cast<int>(off),
+                                           static_cast<int>(soff), 0);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, static_cast<int>(off), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, static_cast<int>(off),
+                                          static_cast<int>(soff), 0);
   }
 }
 
@@ -316,42 +322,71 @@ constexpr int z_tpp() {
 }
 
 // Waves per SIMD that the register allocation must allow.  At L = 512 the
-// complex64 pass on 512-thread workgroups fits three workgroups per CU
-// within 80 VGPRs: 0.366 vs 0.441 ms at n = 256 when it needed 81 (it now
-// needs 59, and four workgroups fit its LDS).
-template <typename T, int NP, bool PF>
+// complex64 pass on 512-thread workgroups (default plan) fits three
+// workgroups per CU within 80 VGPRs: 0.366 vs 0.441 ms at n = 256 when it
+// needed 81 (it now needs 61, and four workgroups fit its LDS).  The
+// alternative plan would spill under that bound and gets none.
+template <typename T, int NP, bool PF, int PV>
 constexpr int z_min_waves() {
-  if (L == 512 && sizeof(T) == 4 && !PF && NP * z_tpp<T>() == 512) return 6;
+  if (L == 512 && sizeof(T) == 4 && !PF && PV == 0 && NP * z_tpp<T>() == 512) return 6;
   return 1;
-}
-
-// plan variant of the Z pass (plan.h: radix_plan(L, variant))
-template <typename T>
-constexpr int z_plan() {
-  return sizeof(T) == 8 ? 1 : 0;
 }
 
 // Twiddle source of the Z pass (fft_engine.h, TWM): the complex64 pass is
 // bound by vector instructions, so up to L = 512 it reads every power of
 // each twiddle from a stage-major table in LDS instead of multiplying two
-// of them; the complex128 pass keeps the short table (its LDS is full).
+// of them; the complex128 pass reads the powers of two from a stage-major
+// table (its LDS is full: that table is smaller than the entries of the
+// length-L table below the largest index read, and its lanes read adjacent
+// entries where the length-L table has them TS apart, on shared banks).
 template <typename T>
 constexpr int z_twm() {
-  return (sizeof(T) == 4 && L <= 512) ? 1 : 0;
+  if (L > 512) return 0;
+  return sizeof(T) == 4 ? 1 : 2;
 }
 
-template <typename T>
-using ZRegs = typename Engine<T, L, false, z_tpp<T>(), z_plan<T>(), z_twm<T>()>::template RegsOf<
-    Stages<L, false, z_tpp<T>(), z_plan<T>()>::NS - 1>;
+template <typename T, int PV>
+using ZRegs = typename Engine<T, L, false, z_tpp<T>(), PV, z_twm<T>()>::template RegsOf<
+    Stages<L, false, z_tpp<T>(), PV>::NS - 1>;
 
-template <typename T, int NP, bool PF, bool EX>
-__global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k_zpass(ZArgs a) {
+// The Z pass's plan variants (plan.h) keep the threads per pencil of the
+// length's default plan, so that its workgroup shape does not depend on the
+// plan.
+static_assert(L >= 1024 || threads_per_pencil(L, 1) == threads_per_pencil(L), "Z plan variant changes the tile");
+
+// log2 of the largest power of two that divides every C of the elements
+// bt + C a thread reads in the first forward stage and writes in the last
+// inverse stage of the Z pass (the inverse ends with the radix the forward
+// transform starts with; only the lower half of either is touched).  With
+// the B layout's i1 block 2^e_lg no larger, element bt + C lies a fixed
+// (C >> e_lg) e_hi elements after element bt for every lane.
+template <typename T, int PV>
+constexpr int z_align_lg() {
+  using St = Stages<L, false, z_tpp<T>(), PV>;
+  constexpr int R = St::radix(0), STRIDE = L / R;
+  int lg = 30;
+  for (int i = 0; i < St::cnt(0); ++i)
+    for (int r = 0; r < (R % 2 == 0 ? R / 2 : R); ++r) {
+      const int c = i * St::TPP + r * STRIDE;
+      int z = 0;
+      while (c != 0 && ((c >> z) & 1) == 0) ++z;
+      if (c != 0 && z < lg) lg = z;
+    }
+  return lg;
+}
+
+// SOFF: every element of a tile is addressed as one per-lane 32-bit offset
+// plus a scalar one (L <= 512, e_lg <= z_align_lg); otherwise each thread
+// addresses its elements from its own base in 64 bits.  PV: the radix plan
+// (plan.h, radix_plan(L, PV)).
+template <typename T, int NP, bool PF, bool EX, bool SOFF, int PV>
+__global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF, PV>())) k_zpass(ZArgs a) {
   constexpr int half = L / 2;
   constexpr int ZT = z_tpp<T>();
   constexpr int TWM = z_twm<T>();
-  using EF = Engine<T, L, false, ZT, z_plan<T>(), TWM>;
-  using EI = Engine<T, L, true, ZT, z_plan<T>(), TWM>;
-  using St = Stages<L, false, ZT, z_plan<T>()>;
+  using EF = Engine<T, L, false, ZT, PV, TWM>;
+  using EI = Engine<T, L, true, ZT, PV, TWM>;
+  using St = Stages<L, false, ZT, PV>;
   using G0 = typename EF::template RegsOf<0>;
   constexpr int SL = St::NS - 1;
   constexpr int RL = St::radix(SL);
@@ -419,7 +454,7 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
   // has (L/2 + 1)^3 < 2^31 entries)
   constexpr uint32_t KP = L / 2 + 1;
   const uint32_t krow = static_cast<uint32_t>(m2) * KP + static_cast<uint32_t>(m3);
-  ZRegs<T> kv;
+  ZRegs<T, PV> kv;
 #pragma unroll
   for (int i = 0; i < St::cnt(SL); ++i) {
     const int b = bt + i * ZT;
@@ -440,10 +475,15 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
   // workgroup; each thread adds its column t and the offset of each element.
   // Up to L = 512 one right-hand side's work array is below 4 GB, so the
   // offset of each element within a tile is a 32-bit byte count, the same
-  // for every tile: computed once below, added to the tile's base (uniform
-  // over the workgroup) at each access.  Longer lengths address each element
-  // from the thread's own base (k3 included) in 64 bits.
-  constexpr bool A32 = L <= 512;
+  // for every tile.  The elements a thread reads and writes are bt + C with
+  // C a compile-time multiple of 2^e_lg (the host keeps e_lg within
+  // z_align_lg), so element bt + C sits (C >> e_lg) e_hi elements after
+  // element bt: one per-lane offset (that of bt, computed once) plus a
+  // part the same for every lane (a scalar register).  Longer lengths
+  // address each element from the thread's own base (k3 included) in 64
+  // bits.
+  constexpr bool A32 = SOFF;
+  static_assert(!SOFF || L <= 512, "32-bit tile offsets need L <= 512");
   int64_t nx_rhs = r_lo, nx_var = 0;
   auto next_base = [&]() -> int64_t {
     const int64_t k2 = nx_var ? L - m2 : m2;
@@ -463,23 +503,23 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
   auto addr = [&](int64_t base, int e) -> int64_t {
     return base + (e >> a.e_lg) * a.e_hi + (e & emask) * a.e_lo;
   };
-  constexpr int NIN = EF::St::cnt(0) * EF::St::radix(0);
-  constexpr int NOUT = EI::St::cnt(EI::NS - 1) * EI::St::radix(EI::NS - 1);
-  uint32_t off_in[NIN], off_out[NOUT];
-  if constexpr (A32) {
-    EF::template first_slots<true>(bt, [&](int slot, int e) { off_in[slot] = elem_off32(e) * sizeof(cx<T>); });
-    EI::template last_slots<KEEP_HALF>(bt, [&](int slot, int e) { off_out[slot] = elem_off32(e) * sizeof(cx<T>); });
-  }
+  const uint32_t off0 = A32 ? elem_off32(bt) * static_cast<uint32_t>(sizeof(cx<T>)) : 0;
+  // the part of element e's offset beyond element bt's (e - bt is a
+  // compile-time constant once the stage loops are unrolled)
+  auto uoff = [&](int e) -> uint32_t {
+    return (static_cast<uint32_t>(e - bt) >> a.e_lg) * static_cast<uint32_t>(a.e_hi) *
+           static_cast<uint32_t>(sizeof(cx<T>));
+  };
   // range of a tile's buffer resource: one right-hand side's work array
   const int32_t range = A32 ? static_cast<int32_t>(a.batch_stride * int64_t{sizeof(cx<T>)}) : 0;
   auto fetch = [&](G0& g, int64_t base) {
     if constexpr (A32) {
       const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(buf + base, range);
-      EF::template load_first_slots<true>(g, bt, [&](int slot, int e) -> cx<T> {
+      EF::template load_first<true>(g, bt, [&](int e) -> cx<T> {
         if constexpr (!EX) {
           if (e >= a.n) return cx<T>{};  // zero padding between n and L/2
         }
-        return act ? buffer_load<T>(rs, off_in[slot]) : cx<T>{};
+        return act ? buffer_load<T>(rs, off0, uoff(e)) : cx<T>{};
       });
     } else {
       EF::template load_first<true>(g, bt, [&](int e) -> cx<T> {
@@ -501,11 +541,11 @@ __global__ void __launch_bounds__(NP * z_tpp<T>(), (z_min_waves<T, NP, PF>())) k
       EI::template run<false>(gl, bt, lp, twi, [&](auto& gi) {
         if constexpr (A32) {
           const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(buf + base, range);
-          EI::template store_last_slots<KEEP_HALF>(gi, bt, [&](int slot, int e, cx<T> v) {
+          EI::template store_last<KEEP_HALF>(gi, bt, [&](int e, cx<T> v) {
             if constexpr (!EX) {
               if (e >= a.n) return;
             }
-            if (act) buffer_store<T>(rs, off_out[slot], v);
+            if (act) buffer_store<T>(rs, off0, v, uoff(e));
           });
         } else {
           EI::template store_last<KEEP_HALF>(gi, bt, [&](int e, cx<T> v) {
@@ -733,19 +773,33 @@ int64_t zpass_blocks(int fprec, int np_sel) {
   return (L / 2 + 1) * ((L + np - 1) / np);
 }
 
-template <typename T, int NP>
-hipError_t zpass_t(const ZArgs& a, hipStream_t st) {
-  hipError_t e = hipSuccess;
-  if (a.rhs_slices < 1 || a.rhs_slices > a.nrhs) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>((L / 2 + 1) * ((L + NP - 1) / NP) * a.rhs_slices)), block(NP * z_tpp<T>());
+template <typename T, int NP, bool SOFF, int PV>
+hipError_t zpass_s(const ZArgs& a, const dim3& grid, const dim3& block, hipStream_t st) {
   const bool ex = 2 * a.n == L;
   if (a.prefetch)
-    e = ex ? launch_kernel((k_zpass<T, NP, true, true>), grid, block, st, a)
-           : launch_kernel((k_zpass<T, NP, true, false>), grid, block, st, a);
-  else
-    e = ex ? launch_kernel((k_zpass<T, NP, false, true>), grid, block, st, a)
-           : launch_kernel((k_zpass<T, NP, false, false>), grid, block, st, a);
-  return e;
+    return ex ? launch_kernel((k_zpass<T, NP, true, true, SOFF, PV>), grid, block, st, a)
+              : launch_kernel((k_zpass<T, NP, true, false, SOFF, PV>), grid, block, st, a);
+  return ex ? launch_kernel((k_zpass<T, NP, false, true, SOFF, PV>), grid, block, st, a)
+            : launch_kernel((k_zpass<T, NP, false, false, SOFF, PV>), grid, block, st, a);
+}
+
+template <typename T, int NP, int PV>
+hipError_t zpass_p(const ZArgs& a, const dim3& grid, const dim3& block, hipStream_t st) {
+  if constexpr (L <= 512) {
+    if (a.e_lg <= z_align_lg<T, PV>()) return zpass_s<T, NP, true, PV>(a, grid, block, st);
+  }
+  return zpass_s<T, NP, false, PV>(a, grid, block, st);
+}
+
+template <typename T, int NP>
+hipError_t zpass_t(const ZArgs& a, hipStream_t st) {
+  if (a.rhs_slices < 1 || a.rhs_slices > a.nrhs) return hipErrorInvalidValue;
+  if (a.plan != 0 && (a.plan != 1 || !has_plan_variant(L))) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((L / 2 + 1) * ((L + NP - 1) / NP) * a.rhs_slices)), block(NP * z_tpp<T>());
+  if constexpr (has_plan_variant(L)) {
+    if (a.plan == 1) return zpass_p<T, NP, 1>(a, grid, block, st);
+  }
+  return zpass_p<T, NP, 0>(a, grid, block, st);
 }
 
 hipError_t spectrum(const SpectrumArgs& a, hipStream_t st) {

@@ -50,14 +50,40 @@ constexpr RadixPlan radix_plan(int L) {
   }
 }
 
-// Alternative plans for single kernels.  The complex128 Z pass at L = 1024
-// runs 16 x 8 x 8: two exchanges per transform instead of three with the
-// same 64 threads per pencil (6.04 vs 6.52 ms at n = 512); the other passes
-// keep 8 x 8 x 4 x 4, with which they measured faster.
+// Alternative plans of the fused Z pass (its radix-plan knob, `zplan`):
+// variant 1 factors L into another radix order, or other radices, with the
+// same threads per pencil (the smallest butterfly count of a stage), so
+// that the Z workgroup shape is unchanged; the first radix stays even.  At
+// L = 1024 variant 1 is 16 x 8 x 8: two exchanges per transform instead of
+// three with the same 64 threads per pencil (complex128 Z 6.04 vs 6.52 ms
+// at n = 512, its default there).  Lengths without an alternative (L = 64
+// and most short ones) have variant 1 equal to the default.
 constexpr RadixPlan radix_plan(int L, int variant) {
-  if (variant == 1 && L == 1024) return {3, {16, 8, 8, 0}};
+  if (variant == 1) switch (L) {
+      case 32: return {2, {4, 8, 0, 0}};
+      case 48: return {3, {8, 3, 2, 0}};
+      case 80: return {3, {8, 5, 2, 0}};
+      case 96: return {3, {4, 8, 3, 0}};
+      case 128: return {3, {4, 4, 8, 0}};
+      case 192: return {3, {8, 3, 8, 0}};
+      case 256: return {3, {4, 8, 8, 0}};
+      case 384: return {4, {8, 3, 4, 4}};
+      case 512: return {4, {8, 4, 4, 4}};
+      case 1024: return {3, {16, 8, 8, 0}};
+      default: break;
+    }
   return radix_plan(L);
 }
+
+constexpr bool same_plan(const RadixPlan& a, const RadixPlan& b) {
+  if (a.n != b.n) return false;
+  for (int s = 0; s < a.n; ++s)
+    if (a.r[s] != b.r[s]) return false;
+  return true;
+}
+
+// whether the Z pass has a second plan at L
+constexpr bool has_plan_variant(int L) { return !same_plan(radix_plan(L, 1), radix_plan(L)); }
 
 constexpr bool supported_length(int L) { return radix_plan(L).n > 0; }
 
@@ -65,8 +91,8 @@ constexpr bool supported_length(int L) { return radix_plan(L).n > 0; }
 // no stage leaves threads idle in its widest configuration, capped at two
 // wavefronts (L = 1024: one radix-8 butterfly per thread keeps a complex128
 // thread within 128 registers).
-constexpr int threads_per_pencil(int L) {
-  RadixPlan p = radix_plan(L);
+constexpr int threads_per_pencil(int L, int variant = 0) {
+  RadixPlan p = radix_plan(L, variant);
   int t = L;
   for (int s = 0; s < p.n; ++s) {
     int b = L / p.r[s];

@@ -2,7 +2,8 @@
 
 Every layout computes the same product: the row blocking and the prefetch
 only move data, so they must be bitwise neutral; narrow tiles regroup the
-butterflies over threads and may differ at rounding level.
+butterflies over threads and the radix plan of the Z pass factors its
+transforms differently, so both may differ at rounding level.
 """
 
 import ctypes
@@ -29,10 +30,21 @@ def gpu(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+# the padded lengths (the smallest L >= 2n - 1 of these) and those with a
+# second radix plan for the Z pass, as the header states them
+LENGTHS = (2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 192, 256, 384, 512, 1024)
+ZPLAN_LENGTHS = (32, 48, 80, 96, 128, 192, 256, 384, 512, 1024)
+
+
+def padded(n):
+    return min(L for L in LENGTHS if L >= 2 * n - 1)
+
+
 def layouts(n):
-    for lg, nar, pf, znar in itertools.product(range(7), (0, 1), (0, 1), (0, 1)):
+    plans = (0, 1) if padded(n) in ZPLAN_LENGTHS else (0,)
+    for lg, nar, pf, znar, zp in itertools.product(range(7), (0, 1), (0, 1), (0, 1), plans):
         if n % (1 << lg) == 0:
-            yield dict(blk_lg=lg, narrow=nar, prefetch=pf, znarrow=znar)
+            yield dict(blk_lg=lg, narrow=nar, prefetch=pf, znarrow=znar, zplan=zp)
 
 
 @pytest.mark.parametrize("n,R", [(24, 1), (16, 3), (14, 2)])
@@ -52,14 +64,15 @@ def test_every_layout_same_product(n, R):
                 y = torch.empty_like(x)
                 ori.ori_matvec(ctx, x, y, op=ori.ORI_OP_SYMMETRIC, precision=prec)
                 y = y.cpu().numpy()
-                tiles = (lay["narrow"], lay["znarrow"])
+                tiles = (lay["narrow"], lay["znarrow"], lay["zplan"])
                 if ref is None:
-                    ref = {(0, 0): y}
+                    ref = {(0, 0, 0): y}
                 if tiles not in ref:
                     ref[tiles] = y
-                # blocking and prefetch: bitwise; narrow vs wide tiles: rounding
+                # blocking and prefetch: bitwise; narrow vs wide tiles and the
+                # radix plan: rounding
                 assert np.array_equal(y, ref[tiles]), lay
-                d = np.linalg.norm(y - ref[(0, 0)]) / np.linalg.norm(ref[(0, 0)])
+                d = np.linalg.norm(y - ref[(0, 0, 0)]) / np.linalg.norm(ref[(0, 0, 0)])
                 assert d <= (1e-14 if prec == ori.ORI_FP64 else 1e-6), (lay, d)
 
 
@@ -68,13 +81,15 @@ def test_invalid_layout_rejected():
     case = workloads.make_case(n, 2.0, seed=1)
     with ori.ori_setup(n, 2.0, gpu(case["h"]), gpu(case["N"]), gpu(case["u0"])) as ctx:
         before = ori.ori_get_layout(ctx)
+        # n = 12 pads to L = 24, which has one radix plan
         for bad in (dict(blk_lg=3), dict(blk_lg=-1), dict(blk_lg=7), dict(narrow=2), dict(prefetch=-1),
-                    dict(znarrow=2)):
-            lay = ori.Layout(bad.get("blk_lg", 0), bad.get("narrow", 0), bad.get("prefetch", 0), bad.get("znarrow", 0))
+                    dict(znarrow=2), dict(zplan=1), dict(zplan=2), dict(zplan=-1)):
+            lay = ori.Layout(bad.get("blk_lg", 0), bad.get("narrow", 0), bad.get("prefetch", 0), bad.get("znarrow", 0),
+                             bad.get("zplan", 0))
             st = ori.lib().ori_set_layout(ctx.handle, ori.ORI_FP64, ctypes.byref(lay))
             assert st == ori.ORI_ERR_INVALID_ARG, bad
             assert ori.ori_get_layout(ctx) == before
-        assert ori.lib().ori_set_layout(ctx.handle, 7, ctypes.byref(ori.Layout(0, 0, 0, 0))) == ori.ORI_ERR_INVALID_ARG
+        assert ori.lib().ori_set_layout(ctx.handle, 7, ctypes.byref(ori.Layout(0, 0, 0, 0, 0))) == ori.ORI_ERR_INVALID_ARG
 
 
 def test_tune_picks_layout_and_records_it():
@@ -128,10 +143,39 @@ def test_tune_fp64_only_provision():
         assert res["fp64"][1] > 0 and res["c64"][1] == -1.0
 
 
-@pytest.mark.parametrize("n,z128,z64", [(16, 0, 1), (128, 0, 1), (256, 1, 1), (512, 1, 1)])
-def test_default_z_tile_width(n, z128, z64):
+@pytest.mark.parametrize("n,z128,z64,p128", [(16, 0, 1, 0), (128, 0, 1, 0), (256, 1, 1, 0), (512, 1, 1, 1)])
+def test_default_z_tile_width(n, z128, z64, p128):
     # narrow Z tiles by default where they measured faster: complex64 at every
-    # length, complex128 from L = 512 on
+    # length, complex128 from L = 512 on; the alternative radix plan only for
+    # the complex128 Z pass at L = 1024
     with ori.ori_create(n) as ctx:
         assert ori.ori_get_layout(ctx, ori.ORI_FP64)["znarrow"] == z128
         assert ori.ori_get_layout(ctx, ori.ORI_MIXED)["znarrow"] == z64
+        assert ori.ori_get_layout(ctx, ori.ORI_FP64)["zplan"] == p128
+        assert ori.ori_get_layout(ctx, ori.ORI_MIXED)["zplan"] == 0
+
+
+@pytest.mark.parametrize("n", [40, 48, 64, 96, 128, 192, 256, 512])
+def test_zplan_variants_agree(n):
+    # the two radix plans of the Z pass (L = 80, 96, 128, 192, 256, 384, 512,
+    # 1024 here) give the same product to rounding, in both precisions; the
+    # default plans are held to the oracle by the parity tests
+    say(f"[zplan] n={n} L={padded(n)}")
+    assert padded(n) in ZPLAN_LENGTHS
+    k = 5.0
+    case = workloads.make_case(n, k, seed=45)
+    rng = np.random.default_rng(46)
+    x = gpu(rng.standard_normal(n ** 3) + 1j * rng.standard_normal(n ** 3))
+    with ori.ori_create(n) as ctx:
+        ori.ori_load(ctx, k, gpu(case["h"]), gpu(case["N"]), gpu(case["u0"]))
+        for prec, bar in ((ori.ORI_FP64, 1e-13), (ori.ORI_MIXED, 2e-6)):
+            base = ori.ori_get_layout(ctx, prec)
+            ys = []
+            for zp in (0, 1):
+                ori.ori_set_layout(ctx, prec, **dict(base, zplan=zp))
+                y = torch.empty_like(x)
+                ori.ori_matvec(ctx, x, y, op=ori.ORI_OP_SYMMETRIC, precision=prec)
+                ys.append(y)
+            d = (torch.linalg.vector_norm(ys[1] - ys[0]) / torch.linalg.vector_norm(ys[0])).item()
+            say(f"   precision {prec}: plans differ by {d:.2e}")
+            assert 0 < d <= bar, (prec, d)  # 0 would mean the knob changed nothing
