@@ -258,17 +258,18 @@ def next_workload(a):
         grp = ori.ori_group_create([p["n"] for p in probs])
         us = [torch.empty(p["n"] ** 3, dtype=torch.complex128, device=dev) for p in probs]
 
+        ks, hs, Ns, u0s = ([p[f] for p in probs] for f in ("k", "h", "N", "u0"))
+
         def step():
-            for i, p in enumerate(probs):
-                ori.ori_group_load(grp, i, p["k"], p["h"], p["N"], p["u0"])
-            _, infos = ori.ori_group_solve(grp, us, tol=a.tol, precision=ori.ORI_MIXED)
+            ori.ori_group_load_all(grp, ks, hs, Ns, u0s)
+            _, infos = ori.ori_group_solve(grp, us, tol=a.tol, precision=ori.ORI_MIXED, check_every=a.check_every)
             return {"matvecs": sum(i["matvecs"] for i in infos), "solves": len(infos),
                     "iterations": [i["iterations"] for i in infos]}
 
         unit, count = "solves/s", lambda info: info["solves"]
         metric = "uneven batch: problems solved/sec, n in {32,48,64,96}, mixed precision"
         desc = {"workload": "ori_red_uneven_n32_48_64_96_k5", "n": [32, 48, 64, 96], "k": k,
-                "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23],
+                "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23], "check_every": a.check_every,
                 "solver": "ori_group: a stream per problem for eager work, one graph replay per iteration "
                           "block holding every running problem's chain"}
     elif a.workload == "gradient":
@@ -374,9 +375,8 @@ def next_workload(a):
         t0 = time.perf_counter()
         for _ in range(a.steps):
             g2 = ori.ori_group_create([p["n"] for p in probs])
-            for i, p in enumerate(probs):
-                ori.ori_group_load(g2, i, p["k"], p["h"], p["N"], p["u0"])
-            ori.ori_group_solve(g2, us, tol=a.tol, precision=ori.ORI_MIXED)
+            ori.ori_group_load_all(g2, ks, hs, Ns, u0s)
+            ori.ori_group_solve(g2, us, tol=a.tol, precision=ori.ORI_MIXED, check_every=a.check_every)
             g2.close()
         torch.cuda.synchronize()
         extra["solves_per_s_with_group_created_each_step"] = round(len(probs) * a.steps / (time.perf_counter() - t0), 1)
@@ -412,6 +412,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--matvecs", type=int, default=50, help="plain operator applications timed")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle rows for cpu_baseline")
+    ap.add_argument("--check-every", type=int, default=1,
+                    help="uneven workload: COCG iterations between convergence checks (each later block one "
+                         "graph replay); results are the same for any value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--layout", default="2,0,0,1,0/3,0,0,1,0",

@@ -97,12 +97,12 @@ typedef struct {
                             reduction still needed for tol is reached            */
   int32_t max_outer;     /* mixed: refinement cycles (0: 10)                         */
   int32_t true_residual; /* 1: also compute ||u0 - A u|| / ||u0|| (one extra matvec) */
-  int32_t graph;         /* 1: after the first check_every iterations, run each block
-                            of check_every COCG iterations as one replay of a HIP
-                            graph built once per context and precision, node by
-                            node from the same kernels and arguments (no stream
-                            capture), so results are bitwise those of 0: one
-                            launch per kernel.  Safe while other threads use
+  int32_t graph;         /* 1: run each block of check_every COCG iterations as one
+                            replay of a HIP graph, built node by node from the
+                            same kernels and arguments (no stream capture) and
+                            cached per context and precision (the first block,
+                            later blocks; up to 8), so results are bitwise those
+                            of 0: one launch per kernel.  Safe while other threads use
                             other contexts or the device.  Ignored while
                             per-kernel profiling is enabled.                       */
 } ori_solve_opts;
@@ -244,10 +244,19 @@ ori_status ori_group_create(const ori_grid* grids, int32_t nprob, int32_t provis
  * (device arrays of that problem's size, as for ori_load). */
 ori_status ori_group_load(ori_group g, int32_t i, double k, const void* h, const double* N, const void* u0);
 
+/* ori_group_load of every problem in one call: k[i], h[i], N[i] (N NULL:
+ * all N_i NULL, or N[i] NULL for one problem) and u0[i] for i < nprob, host
+ * arrays of device pointers.  Every problem's work is enqueued before the
+ * call waits for any of them, so the problems load side by side.  Each
+ * problem ends loaded as by ori_group_load; on an error the problems after
+ * the failing one are left as they were before the call, or not loaded. */
+ori_status ori_group_load_all(ori_group g, const double* k, const void* const* h, const double* const* N,
+                              const void* const* u0);
+
 /* Solve every problem (eq. 2.19 by COCG on its complex-symmetric form, as
- * ori_solve).  The problems run in lockstep: after the first iteration,
- * each block of check_every COCG iterations of the problems still running is
- * one replay of a HIP graph in which every problem is an independent chain
+ * ori_solve).  The problems run in lockstep: each block of check_every
+ * COCG iterations of the problems still running is one replay of a HIP
+ * graph in which every problem is an independent chain
  * of its own kernels (built node by node, as in ori_solve), so the GPU runs
  * the problems side by side; a problem leaves once it has converged.  Every
  * problem runs exactly the kernels of its own ori_solve, in the same order,

@@ -25,7 +25,7 @@ __all__ = [
     "ORI_ERR_BREAKDOWN", "ORI_ERR_NOT_CONVERGED", "ORI_ERR_UNSUPPORTED",
     "ORI_FP64", "ORI_MIXED", "ORI_OP_SYSTEM", "ORI_OP_SYMMETRIC", "ORI_OP_GREEN",
     "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve", "solve_many",
-    "Group", "ori_group_create", "ori_group_load", "ori_group_solve", "ori_group_destroy",
+    "Group", "ori_group_create", "ori_group_load", "ori_group_load_all", "ori_group_solve", "ori_group_destroy",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libori.so")
@@ -98,6 +98,8 @@ def lib():
             "ori_batch_info": (ctypes.c_int, [P, I32, ctypes.POINTER(SolveInfo)]),
             "ori_group_create": (ctypes.c_int, [ctypes.POINTER(Grid), I32, I32, P, ctypes.POINTER(P)]),
             "ori_group_load": (ctypes.c_int, [P, I32, D, P, P, P]),
+            "ori_group_load_all": (ctypes.c_int, [P, ctypes.POINTER(D), ctypes.POINTER(P), ctypes.POINTER(P),
+                                                  ctypes.POINTER(P)]),
             "ori_group_solve": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(P),
                                                ctypes.POINTER(SolveInfo)]),
             "ori_group_destroy": (None, [P]),
@@ -574,6 +576,23 @@ def ori_group_load(group, i, k, h, N, u0):
                                 _dev(N, torch.float64, P, "N"), _dev(u0, torch.complex128, P, "u0")))
 
 
+def ori_group_load_all(group, ks, hs, Ns, u0s):
+    """ori_group_load of every problem in one call (their loads run side by
+    side); Ns may be None or hold None entries."""
+    import torch
+    M = len(group.ns)
+    Ns = [None] * M if Ns is None else list(Ns)
+    if not (len(ks) == len(hs) == len(Ns) == len(u0s) == M):
+        raise ValueError(f"expected {M} entries per argument")
+    ptr = lambda t, dt, i, what: _dev(t, dt, group.ns[i] ** 3, f"{what}[{i}]")
+    k_arr = (ctypes.c_double * M)(*[float(k) for k in ks])
+    h_arr = (ctypes.c_void_p * M)(*[ptr(h, torch.complex128, i, "h").value for i, h in enumerate(hs)])
+    N_arr = (ctypes.c_void_p * M)(*[(ptr(N, torch.float64, i, "N") or ctypes.c_void_p()).value
+                                    for i, N in enumerate(Ns)])
+    u_arr = (ctypes.c_void_p * M)(*[ptr(u, torch.complex128, i, "u0").value for i, u in enumerate(u0s)])
+    _check(lib().ori_group_load_all(group.handle, k_arr, h_arr, N_arr, u_arr))
+
+
 def ori_group_solve(group, us, raise_on_error=True, **opts):
     """Solve every problem of the group into us[i] (complex128 CUDA tensors).
     Returns (status, [info dict per problem])."""
@@ -593,17 +612,17 @@ def ori_group_solve(group, us, raise_on_error=True, **opts):
 
 
 def solve_many(problems, **opts):
-    """Independent problems of any sizes solved together as one group (one
-    stream; each iteration block of all problems is one graph replay, the
-    problems side by side on the GPU).  problems: dicts with n, k, h, N, u0
-    (CUDA tensors) and optionally side.  Returns a list of (u, info) in
+    """Independent problems of any sizes solved together as one group (a
+    stream per problem; each later iteration block of all running problems
+    is one graph replay, the problems side by side on the GPU).  problems:
+    dicts with n, k, h, N, u0 (CUDA tensors) and optionally side.  Returns a list of (u, info) in
     order; each result equals that problem's ori_solve bit for bit."""
     import torch
     grids = [{"n": int(p["n"]), "side": float(p.get("side", 1.0))} for p in problems]
     dev = problems[0]["h"].device
     with ori_group_create(grids) as g:
-        for i, p in enumerate(problems):
-            ori_group_load(g, i, p["k"], p["h"], p.get("N"), p["u0"])
+        ori_group_load_all(g, [p["k"] for p in problems], [p["h"] for p in problems],
+                           [p.get("N") for p in problems], [p["u0"] for p in problems])
         us = [torch.empty(int(p["n"]) ** 3, dtype=torch.complex128, device=dev) for p in problems]
         _, infos = ori_group_solve(g, us, **opts)
     return list(zip(us, infos))

@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize_coeff(const double* __
     sh[1] = fmin(sh[1], sh[3 * i + 1]);
     sh[2] = fmax(sh[2], sh[3 * i + 2]);
   }
-  sc->flags = sh[0] > 0.0 ? FLAG_BAD_INPUT : 0;
+  sc->flags = sh[0] > 0.0 ? FLAG_BAD_COEFF : 0;
   sc->s2_min = sh[1];
   sc->s2_max = sh[2];
 }
@@ -199,7 +199,9 @@ __global__ void __launch_bounds__(kFinThreads)
     case FIN_SETUP:
       sc->bb = s0;
       sc->aux = s1;
-      sc->flags = s2 > 0.0 ? FLAG_BAD_INPUT : 0;
+      // keeps the coefficient check of sc[0] (k_finalize_coeff, earlier on
+      // the stream), so that one copy to the host brings both
+      sc->flags = (sc->flags & FLAG_BAD_COEFF) | (s2 > 0.0 ? FLAG_BAD_INPUT : 0);
       break;
     case FIN_INIT: {
       sc->rho_re = s0;

@@ -36,7 +36,8 @@ enum : int32_t {
   FLAG_BREAKDOWN_RHO = 1,  // r^T r ~ 0 while r != 0
   FLAG_BREAKDOWN_MU = 2,   // p^T A p ~ 0 while p != 0
   FLAG_ZERO_RESIDUAL = 4,  // r == 0 exactly
-  FLAG_BAD_INPUT = 8,      // NaN / Inf / negative N met in ori_load
+  FLAG_BAD_INPUT = 8,      // NaN / Inf in a right-hand side u0, met in ori_load
+  FLAG_BAD_COEFF = 32,     // NaN / Inf in h or N, or N < 0, met in ori_load (sc[0])
   FLAG_CONVERGED = 16,     // rr <= rr_target: alpha = 0 from now on
 };
 constexpr int32_t FLAG_DONE = FLAG_BREAKDOWN_RHO | FLAG_BREAKDOWN_MU | FLAG_ZERO_RESIDUAL | FLAG_CONVERGED;

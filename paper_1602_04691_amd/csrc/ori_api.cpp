@@ -108,14 +108,30 @@ std::mutex g_tune_mu;
 
 std::map<TuneKey, Tuned> g_tuned;
 
-// A cached HIP graph of COCG iteration blocks: `iters` iterations of each
-// context in `members`, one independent chain per context.
+// Cached HIP graphs of COCG iteration blocks, the most recently used last.
+// An entry holds `iters` iterations (the first of them the first COCG
+// iteration when `first`) of every context in `members`, one independent
+// chain per context.  A few entries are kept, so that every block shape of
+// a solve stays cached across solves: the first block, full blocks, and the
+// blocks of the members left running once others are done.
 struct IterGraph {
-  hipGraphExec_t exec = nullptr;
-  int iters = 0;
-  std::vector<ori_ctx> members;
+  struct Entry {
+    hipGraphExec_t exec = nullptr;
+    int iters = 0;
+    bool first = false;
+    std::vector<ori_ctx> members;
+  };
+  std::vector<Entry> entries;
   hipEvent_t done = nullptr;  // recorded after a replay, waited on by each member's stream
+  void release() {
+    for (auto& e : entries)
+      if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    entries.clear();
+    if (done) (void)hipEventDestroy(done);
+    done = nullptr;
+  }
 };
+constexpr size_t kGraphCacheEntries = 8;
 
 struct ProfPending {
   int slot;  // kind * 2 + (fprec == F32)
@@ -562,43 +578,48 @@ using Members = std::vector<ori_ctx>;
 // exactly the kernels and arguments of its eager launches, in order; the
 // chains of different contexts are independent, so the GPU runs them side
 // by side.  No stream is put into capture mode.
-ori_status iteration_graph(const Members& active, int prec, int iters, IterGraph& cache, hipGraphExec_t* out) {
+ori_status iteration_graph(const Members& active, int prec, int iters, bool first, IterGraph& cache,
+                           hipGraphExec_t* out) {
   *out = nullptr;
   ori_ctx c0 = active.front();
-  if (cache.exec && cache.iters == iters && cache.members == active) {
-    *out = cache.exec;
-    return ORI_OK;
-  }
-  if (cache.exec) {
-    ORI_HIP(c0, hipGraphExecDestroy(cache.exec));
-    cache.exec = nullptr;
+  auto& ents = cache.entries;
+  for (size_t i = 0; i < ents.size(); ++i) {
+    if (ents[i].iters == iters && ents[i].first == first && ents[i].members == active) {
+      std::rotate(ents.begin() + i, ents.begin() + i + 1, ents.end());
+      *out = ents.back().exec;
+      return ORI_OK;
+    }
   }
   if (!cache.done) ORI_HIP(c0, hipEventCreateWithFlags(&cache.done, hipEventDisableTiming));
+  if (ents.size() >= kGraphCacheEntries) {
+    ORI_HIP(c0, hipGraphExecDestroy(ents.front().exec));
+    ents.erase(ents.begin());
+  }
   GraphBuild gb;
   ORI_HIP(c0, hipGraphCreate(&gb.graph, 0));
   t_graph = &gb;
   ori_status st = ORI_OK;
   for (ori_ctx c : active) {
     gb.last = nullptr;  // a chain of its own
-    for (int it = 0; it < iters && st == ORI_OK; ++it) st = iteration(c, prec, false);
+    for (int it = 0; it < iters && st == ORI_OK; ++it) st = iteration(c, prec, first && it == 0);
     if (st != ORI_OK) {
       if (c != c0) set_err(c0, st, "%s", c->err.c_str());
       break;
     }
   }
   t_graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   if (st == ORI_OK) {
-    const hipError_t e = hipGraphInstantiateWithFlags(&cache.exec, gb.graph, 0);
+    const hipError_t e = hipGraphInstantiateWithFlags(&exec, gb.graph, 0);
     if (e != hipSuccess) {
-      cache.exec = nullptr;
+      exec = nullptr;
       st = set_err(c0, ORI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
   }
   (void)hipGraphDestroy(gb.graph);
   if (st != ORI_OK) return st;
-  cache.iters = iters;
-  cache.members = active;
-  *out = cache.exec;
+  ents.push_back(IterGraph::Entry{exec, iters, first, active});
+  *out = exec;
   return ORI_OK;
 }
 
@@ -637,9 +658,10 @@ ori_status sync_members(const Members& ms) {
 // at most budget[i] iterations and leaves when all its right-hand sides are
 // done (a right-hand side that converges or breaks down is frozen on the
 // device, alpha = 0, while the others of its context go on); ran[i]
-// receives the iterations it ran.  The first block runs eagerly (it holds
-// the first iteration); later full blocks of check_every iterations replay
-// one graph over the members still running.  Each member runs exactly the
+// receives the iterations it ran.  Every full block of check_every
+// iterations (the first one starting with the first COCG iteration) is one
+// replay of a graph over the members still running; a shorter block (an
+// iteration budget running out) runs eagerly.  Each member runs exactly the
 // kernels of its own solve, so results do not depend on the other members.
 ori_status group_cocg(const Members& ms, int prec, const std::vector<int>& budget, int check_every, bool use_graph,
                       IterGraph& cache, std::vector<int>* ran) {
@@ -659,7 +681,7 @@ ori_status group_cocg(const Members& ms, int prec, const std::vector<int>& budge
     Members active;
     for (size_t i : act) active.push_back(ms[i]);
     hipGraphExec_t exec = nullptr;
-    if (use_graph && it > 0 && blk == check_every) ORI_TRY(iteration_graph(active, prec, blk, cache, &exec));
+    if (use_graph && blk == check_every) ORI_TRY(iteration_graph(active, prec, blk, it == 0, cache, &exec));
     if (exec) {
       // the replay runs every member's chain on the first member's stream;
       // the other members' streams wait for it before their next work
@@ -712,18 +734,21 @@ ori_status recover(ori_ctx c, const cxd* w, cxd* u, int* products) {
 }
 
 // ||u0 - u - G0 D u|| / ||u0|| per right-hand side
-ori_status true_residual_orig(ori_ctx c, const cxd* u, std::vector<double>* rel) {
+// (launched; true_residual_orig_read reads it once the scalars are on the host)
+ori_status true_residual_orig(ori_ctx c, const cxd* u) {
   int64_t nblk = 0;
   ORI_TRY(matvec(c, PREC_F64, PREC_F64, plain_f1(u, c->D),
                  epi(c->q, c->u0, 1.0, u, -1.0, nullptr, -1.0, c->partials, 1), &nblk));
-  ORI_TRY(finalize(c, nblk, FIN_NORM));
-  ORI_TRY(sync_scalars(c));
-  rel->resize(c->nrhs);
+  return finalize(c, nblk, FIN_NORM);
+}
+
+std::vector<double> true_residual_orig_read(ori_ctx c) {
+  std::vector<double> rel(c->nrhs);
   for (int64_t i = 0; i < c->nrhs; ++i) {
     const double a = c->sc_host[i].aux;
-    (*rel)[i] = c->u0norm2[i] > 0 ? std::sqrt(a / c->u0norm2[i]) : std::sqrt(a);
+    rel[i] = c->u0norm2[i] > 0 ? std::sqrt(a / c->u0norm2[i]) : std::sqrt(a);
   }
-  return ORI_OK;
+  return rel;
 }
 
 // Layout knobs: the i1 blocking of the B work array (ZArgs), the tile widths
@@ -776,14 +801,7 @@ void choose_layout(ori_ctx c) {
 
 // Captured graphs bake the layout into their kernel arguments.
 ori_status drop_graphs(ori_ctx c) {
-  for (auto& g : c->graphs) {
-    if (g.exec) ORI_HIP(c, hipGraphExecDestroy(g.exec));
-    if (g.done) ORI_HIP(c, hipEventDestroy(g.done));
-    g.exec = nullptr;
-    g.done = nullptr;
-    g.iters = 0;
-    g.members.clear();
-  }
+  for (auto& g : c->graphs) g.release();
   return ORI_OK;
 }
 
@@ -1010,6 +1028,8 @@ ori_status forward_solve_group(const Members& ms, const ori_solve_opts& o, const
     jobs.push_back(SymJob{c, c->b, c->bnorm2, oc});
   }
   ORI_TRY(solve_sym_group(jobs, o, cache));
+  // every member's recovery and true residual launched, then one wait per
+  // stream
   for (size_t m = 0; m < ms.size(); ++m) {
     ori_ctx c = ms[m];
     Outcome* oc = &(*ocs)[m];
@@ -1019,13 +1039,16 @@ ori_status forward_solve_group(const Members& ms, const ori_solve_opts& o, const
       i.matvecs += rec;
       i.rel_res_true = -1.0;
     }
-    if (o.true_residual) {
-      std::vector<double> rel;
-      ORI_TRY(true_residual_orig(c, u[m], &rel));
-      for (int64_t i = 0; i < c->nrhs; ++i) {
-        oc->info[i].matvecs++;
-        oc->info[i].rel_res_true = rel[i];
-      }
+    if (o.true_residual) ORI_TRY(true_residual_orig(c, u[m]));
+  }
+  if (!o.true_residual) return ORI_OK;
+  ORI_TRY(sync_members(ms));
+  for (size_t m = 0; m < ms.size(); ++m) {
+    ori_ctx c = ms[m];
+    const std::vector<double> rel = true_residual_orig_read(c);
+    for (int64_t i = 0; i < c->nrhs; ++i) {
+      (*ocs)[m].info[i].matvecs++;
+      (*ocs)[m].info[i].rel_res_true = rel[i];
     }
   }
   return ORI_OK;
@@ -1376,8 +1399,12 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
   return ORI_OK;
 }
 
-ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const void* u0) {
-  ORI_TRY(guard(c));
+namespace {
+// ori_load in two halves: the checks of the arguments and every launch
+// (load_launch), then one wait for the context's stream and the checks of
+// the data (load_finish).  Several contexts can be loaded with their waits
+// overlapping (ori_group_load_all).
+ori_status load_launch(ori_ctx c, double k, const void* h, const double* N, const void* u0) {
   if (!(k > 0.0) || !std::isfinite(k)) return set_err(c, ORI_ERR_INVALID_ARG, "k must be finite and > 0");
   const int64_t P = c->P, R = c->nrhs;
   ORI_TRY(check_dev_ptr(c, h, P * 16, "h"));
@@ -1399,15 +1426,20 @@ ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const v
   ORI_HIP(c, hipMemsetAsync(c->sc, 0, R * sizeof(ScalarBlock), c->stream));
   ORI_TRY(launch(c, K_FINALIZE, PREC_F64,
                  [&] { return launch_finalize_coeff(c->partials, rblocks(c), c->sc, c->stream); }));
+  // right-hand sides b = S u0 and their norms; the coefficient check stays
+  // in sc[0] (FLAG_BAD_COEFF, |S|^2 range), so one wait covers both
+  ORI_TRY(launch(c, K_COEFF, PREC_F64, [&] { return launch_rhs(u0, c->S, P, R, c->b, c->u0, c->partials, c->stream); }));
+  return finalize(c, rblocks(c), FIN_SETUP);
+}
+
+ori_status load_finish(ori_ctx c) {
+  const int64_t R = c->nrhs;
   ORI_TRY(sync_scalars(c));
-  if (c->sc_host[0].flags & FLAG_BAD_INPUT) return set_err(c, ORI_ERR_INVALID_ARG, "h or N holds NaN/Inf, or N < 0");
+  if (c->sc_host[0].flags & FLAG_BAD_COEFF) return set_err(c, ORI_ERR_INVALID_ARG, "h or N holds NaN/Inf, or N < 0");
   // u = w / S is exact and free when no S_p vanishes; with |S| spread over
   // more than 1e3 the division would amplify the error of w in small-S
   // cells, so the recovery u = u0 - G0 S w (one product) is used instead
   c->recover_by_division = c->sc_host[0].s2_min > 0.0 && c->sc_host[0].s2_min >= 1e-6 * c->sc_host[0].s2_max;
-  ORI_TRY(launch(c, K_COEFF, PREC_F64, [&] { return launch_rhs(u0, c->S, P, R, c->b, c->u0, c->partials, c->stream); }));
-  ORI_TRY(finalize(c, rblocks(c), FIN_SETUP));
-  ORI_TRY(sync_scalars(c));
   for (int64_t i = 0; i < R; ++i) {
     if (c->sc_host[i].flags & FLAG_BAD_INPUT)
       return set_err(c, ORI_ERR_INVALID_ARG, "u0 (right-hand side %lld) holds NaN/Inf", (long long)i);
@@ -1416,6 +1448,13 @@ ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const v
   }
   c->loaded = true;
   return ORI_OK;
+}
+}  // namespace
+
+ori_status ori_load(ori_ctx c, double k, const void* h, const double* N, const void* u0) {
+  ORI_TRY(guard(c));
+  ORI_TRY(load_launch(c, k, h, N, u0));
+  return load_finish(c);
 }
 
 ori_status ori_spectrum_cache(ori_ctx c, int32_t enable) {
@@ -1748,6 +1787,28 @@ ori_status ori_group_load(ori_group g, int32_t i, double k, const void* h, const
   return st;
 }
 
+ori_status ori_group_load_all(ori_group g, const double* k, const void* const* h, const double* const* N,
+                              const void* const* u0) {
+  if (!g) return set_err(nullptr, ORI_ERR_INVALID_ARG, "group is NULL");
+  if (!k || !h || !u0) return set_err(nullptr, ORI_ERR_INVALID_ARG, "k, h and u0 must not be NULL");
+  const size_t M = g->members.size();
+  // every problem's launches first, then the waits: the problems' loads run
+  // side by side on their streams
+  for (size_t m = 0; m < M; ++m) {
+    ori_ctx c = g->members[m];
+    ori_status st = guard(c);
+    if (st == ORI_OK) st = group_wait_caller(g, m);
+    if (st == ORI_OK) st = load_launch(c, k[m], h[m], N ? N[m] : nullptr, u0[m]);
+    if (st != ORI_OK) return set_err(nullptr, st, "problem %zu: %s", m, c->err.c_str());
+  }
+  for (size_t m = 0; m < M; ++m) {
+    ori_ctx c = g->members[m];
+    const ori_status st = load_finish(c);
+    if (st != ORI_OK) return set_err(nullptr, st, "problem %zu: %s", m, c->err.c_str());
+  }
+  return ORI_OK;
+}
+
 ori_status ori_group_solve(ori_group g, const ori_solve_opts* opts_in, void* const* u, ori_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!g) return set_err(nullptr, ORI_ERR_INVALID_ARG, "group is NULL");
@@ -1796,10 +1857,7 @@ ori_status ori_group_solve(ori_group g, const ori_solve_opts* opts_in, void* con
 
 void ori_group_destroy(ori_group g) {
   if (!g) return;
-  for (auto& gr : g->graphs) {
-    if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
-    if (gr.done) (void)hipEventDestroy(gr.done);
-  }
+  for (auto& gr : g->graphs) gr.release();
   for (ori_ctx c : g->members) ori_destroy(c);  // waits for each member's stream
   for (hipStream_t sm : g->streams) (void)hipStreamDestroy(sm);
   if (g->ready) (void)hipEventDestroy(g->ready);
@@ -1947,10 +2005,7 @@ void ori_destroy(ori_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);  // all of the context's work is on its stream
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-  for (auto& g : c->graphs) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.done) (void)hipEventDestroy(g.done);
-  }
+  for (auto& g : c->graphs) g.release();
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   if (c->outer_m_host) (void)hipHostFree(c->outer_m_host);

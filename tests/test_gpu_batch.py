@@ -169,8 +169,12 @@ def test_group_reloaded_and_both_precisions_bitwise():
     with ori.ori_group_create(ns) as g:
         for rnd in range(2):
             cases = [workloads.make_case(n, 3.0 + j, seed=40 + 10 * rnd + j) for j, n in enumerate(ns)]
-            for j, (n, c) in enumerate(zip(ns, cases)):
-                ori.ori_group_load(g, j, 3.0 + j, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]))
+            if rnd == 0:  # one problem at a time, then all in one call
+                for j, (n, c) in enumerate(zip(ns, cases)):
+                    ori.ori_group_load(g, j, 3.0 + j, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]))
+            else:
+                ori.ori_group_load_all(g, [3.0 + j for j in range(len(ns))], [gpu(c["h"]) for c in cases],
+                                       [gpu(c["N"]) for c in cases], [gpu(c["u0"]) for c in cases])
             for prec, graph in ((ori.ORI_FP64, True), (ori.ORI_MIXED, True), (ori.ORI_FP64, False)):
                 us = [torch.empty(n ** 3, dtype=torch.complex128, device="cuda") for n in ns]
                 _, infos = ori.ori_group_solve(g, us, tol=1e-10, precision=prec, graph=graph)
@@ -196,3 +200,23 @@ def test_group_reports_nonconvergence_of_one_problem():
         assert all(i["iterations"] == 3 for i in infos)
         assert all(torch.isfinite(torch.view_as_real(u)).all() for u in us)
         assert "problem 0" in ori.ori_last_error()
+
+
+def test_group_load_all_reports_bad_input():
+    # a NaN in one problem's h: the call fails naming that problem, and the
+    # group is still usable once that problem is loaded with good data
+    ns = (8, 12, 10)
+    cases = [workloads.make_case(n, 4.0, seed=80 + n) for n in ns]
+    with ori.ori_group_create(ns) as g:
+        hs = [gpu(c["h"]) for c in cases]
+        bad = hs[1].clone()
+        bad[5] = complex("nan")
+        with pytest.raises(ori.OriError, match="problem 1"):
+            ori.ori_group_load_all(g, [4.0] * 3, [hs[0], bad, hs[2]], [gpu(c["N"]) for c in cases],
+                                   [gpu(c["u0"]) for c in cases])
+        ori.ori_group_load_all(g, [4.0] * 3, hs, [gpu(c["N"]) for c in cases], [gpu(c["u0"]) for c in cases])
+        us = [torch.empty(n ** 3, dtype=torch.complex128, device="cuda") for n in ns]
+        _, infos = ori.ori_group_solve(g, us, tol=1e-10)
+        for j, (n, c) in enumerate(zip(ns, cases)):
+            u1, _ = ori.solve(n, 4.0, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]), tol=1e-10)
+            assert torch.equal(us[j], u1), n
