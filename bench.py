@@ -70,7 +70,7 @@ def kernel_sources_sha():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1602_04691_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h", ".inc")):
             text = open(os.path.join(d, f), encoding="utf-8").read()
             text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
             text = re.sub(r"//[^\n]*", " ", text)

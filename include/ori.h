@@ -105,6 +105,13 @@ typedef struct {
                             of 0: one launch per kernel.  Safe while other threads use
                             other contexts or the device.  Ignored while
                             per-kernel profiling is enabled.                       */
+  int32_t multi;         /* ori_group_solve: 1 runs the COCG iterations of the
+                            problems still running in one launch per kernel when
+                            every one of them has a padded length in 8..256
+                            other than 16 and the default layout (otherwise, and
+                            with 0, each problem launches its own kernels).  The
+                            results are bitwise the same either way.  Other
+                            calls ignore it.                                    */
 } ori_solve_opts;
 
 typedef struct {
@@ -267,6 +274,11 @@ ori_status ori_group_load_all(ori_group g, const double* k, const void* const* h
  * Returns ORI_OK, or the status of the first problem that did not converge
  * (every u[i] is filled either way). */
 ori_status ori_group_solve(ori_group g, const ori_solve_opts* opts, void* const* u, ori_solve_info* info);
+
+/* COCG iterations the group's solves have run in one launch per kernel for
+ * all of their problems still running (ori_solve_opts.multi), counted once
+ * per iteration of the set, since the group was created. */
+ori_status ori_group_multi_iterations(ori_group g, int64_t* iterations);
 
 /* Release the group and its problems' workspaces (NULL is ignored). */
 void ori_group_destroy(ori_group g);

@@ -26,6 +26,7 @@ __all__ = [
     "ORI_FP64", "ORI_MIXED", "ORI_OP_SYSTEM", "ORI_OP_SYMMETRIC", "ORI_OP_GREEN",
     "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve", "solve_many",
     "Group", "ori_group_create", "ori_group_load", "ori_group_load_all", "ori_group_solve", "ori_group_destroy",
+    "ori_group_multi_iterations",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libori.so")
@@ -58,7 +59,8 @@ class Grid(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_x0", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("max_outer", ctypes.c_int32), ("true_residual", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("true_residual", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("multi", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -103,6 +105,7 @@ def lib():
             "ori_group_solve": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(P),
                                                ctypes.POINTER(SolveInfo)]),
             "ori_group_destroy": (None, [P]),
+            "ori_group_multi_iterations": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
             "ori_load": (ctypes.c_int, [P, D, P, P, P]),
             "ori_spectrum_cache": (ctypes.c_int, [P, I32]),
             "ori_setup": (ctypes.c_int, [ctypes.POINTER(Grid), D, P, P, P, P, ctypes.POINTER(P)]),
@@ -262,9 +265,9 @@ def ori_setup(n, k, h, N, u0, side=1.0, origin=(0.0, 0.0, 0.0), cell_offset=0.5,
 
 
 def _opts(tol=1e-10, max_iter=1000, precision=ORI_FP64, check_every=1, use_x0=False, inner_tol=1e-5,
-          max_outer=10, true_residual=True, graph=True):
+          max_outer=10, true_residual=True, graph=True, multi=True):
     return SolveOpts(float(tol), int(max_iter), int(precision), int(check_every), int(bool(use_x0)),
-                     float(inner_tol), int(max_outer), int(bool(true_residual)), int(bool(graph)))
+                     float(inner_tol), int(max_outer), int(bool(true_residual)), int(bool(graph)), int(bool(multi)))
 
 
 def ori_solve(ctx, u, tol=1e-10, max_iter=1000, precision=ORI_FP64, check_every=1, use_x0=False,
@@ -591,6 +594,13 @@ def ori_group_load_all(group, ks, hs, Ns, u0s):
                                     for i, N in enumerate(Ns)])
     u_arr = (ctypes.c_void_p * M)(*[ptr(u, torch.complex128, i, "u0").value for i, u in enumerate(u0s)])
     _check(lib().ori_group_load_all(group.handle, k_arr, h_arr, N_arr, u_arr))
+
+
+def ori_group_multi_iterations(group):
+    """COCG iterations run in one launch per kernel for all running problems."""
+    out = ctypes.c_int64()
+    _check(lib().ori_group_multi_iterations(group.handle, ctypes.byref(out)))
+    return out.value
 
 
 def ori_group_solve(group, us, raise_on_error=True, **opts):

@@ -3,7 +3,8 @@
     python -m paper_1602_04691_amd.build [--jobs N] [--incremental]
 
 Compiles the FFT pass kernels once per supported padded length L
-(``csrc/passes.hip`` with ``-DORI_L=<L>``), the auxiliary kernels and the
+(``csrc/passes.hip`` with ``-DORI_L=<L>``), the multi-problem passes of the
+short lengths (``csrc/multi_passes.hip``), the auxiliary kernels and the
 host runtime, and links ``paper_1602_04691_amd/libori.so``.
 """
 
@@ -27,6 +28,9 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no automatic a * b + c contraction: the fused operations are written
+    # out (cx.h), so a body rounds the same in every kernel that runs it
+    "-ffp-contract=off",
     "-I", INCLUDE, "-I", CSRC,
 ]
 
@@ -40,22 +44,24 @@ def supported_lengths():
 def _sources():
     units = [(os.path.join(CSRC, "passes.hip"), f"passes_L{L}.o", [f"-DORI_L={L}"])
              for L in supported_lengths()]
+    units.append((os.path.join(CSRC, "multi_passes.hip"), "multi_passes.o", []))
     units.append((os.path.join(CSRC, "aux.hip"), "aux.o", []))
     units.append((os.path.join(CSRC, "physics.hip"), "physics.o", []))
     units.append((os.path.join(CSRC, "ori_api.cpp"), "ori_api.o", ["-x", "hip"]))
     return units
 
 
-def _deps_mtime():
-    return max(os.path.getmtime(os.path.join(d, f))
-               for d in (CSRC, INCLUDE) for f in os.listdir(d)
-               if f.endswith((".h", ".hip", ".cpp")))
+def _deps_mtime(src):
+    """Newest of the unit's source and every header it may include."""
+    return max([os.path.getmtime(src)] + [os.path.getmtime(os.path.join(d, f))
+                                          for d in (CSRC, INCLUDE) for f in os.listdir(d)
+                                          if f.endswith((".h", ".inc"))])
 
 
 def _compile(unit, incremental):
     src, obj, extra = unit
     out = os.path.join(BUILD, obj)
-    if incremental and os.path.exists(out) and os.path.getmtime(out) >= _deps_mtime():
+    if incremental and os.path.exists(out) and os.path.getmtime(out) >= _deps_mtime(src):
         return out, ""
     cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", out]
     p = subprocess.run(cmd, capture_output=True, text=True)

@@ -180,11 +180,11 @@ __global__ void __launch_bounds__(kRedThreads)
 // fixed order and update its scalars.  1024 threads: after the I1 pass there
 // is one quadruple per I1 workgroup (16 384 at n = 256).
 constexpr int kFinThreads = 1024;
-__global__ void __launch_bounds__(kFinThreads)
-    k_finalize(const double* __restrict__ partials, int64_t nblk, ScalarBlock* scb, int32_t mode, double eps,
-               double tol2, int32_t tol2_of_bb, const double* __restrict__ tol2_rhs) {
-  const double* part = partials + 4 * nblk * blockIdx.x;
-  ScalarBlock* sc = scb + blockIdx.x;
+__device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int64_t nblk, ScalarBlock* scb,
+                                              int64_t rhs, int32_t mode, double eps, double tol2, int32_t tol2_of_bb,
+                                              const double* __restrict__ tol2_rhs) {
+  const double* part = partials + 4 * nblk * rhs;
+  ScalarBlock* sc = scb + rhs;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t i = threadIdx.x; i < nblk; i += kFinThreads) {
 #pragma unroll
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(kFinThreads)
       sc->alpha_re = 0.0;
       sc->alpha_im = 0.0;
       sc->iters = 0;
-      sc->rr_target = (tol2_rhs ? tol2_rhs[blockIdx.x] : tol2) * (tol2_of_bb ? sc->bb : s2);
+      sc->rr_target = (tol2_rhs ? tol2_rhs[rhs] : tol2) * (tol2_of_bb ? sc->bb : s2);
       int f = 0;
       if (s2 == 0.0) f |= FLAG_ZERO_RESIDUAL;
       else if (s2 <= sc->rr_target) f |= FLAG_CONVERGED;
@@ -275,21 +275,28 @@ __global__ void __launch_bounds__(kFinThreads)
   }
 }
 
+__global__ void __launch_bounds__(kFinThreads)
+    k_finalize(const double* __restrict__ partials, int64_t nblk, ScalarBlock* scb, int32_t mode, double eps,
+               double tol2, int32_t tol2_of_bb, const double* __restrict__ tol2_rhs) {
+  finalize_body(partials, nblk, scb, blockIdx.x, mode, eps, tol2, tol2_of_bb, tol2_rhs);
+}
+
+// workgroup bid of nb over right-hand side rhs
 template <typename V>
-__global__ void __launch_bounds__(kRedThreads)
-    k_update(cx<V>* __restrict__ x, const cx<V>* __restrict__ p, cx<V>* __restrict__ r,
-             const cx<V>* __restrict__ q, int64_t P, const ScalarBlock* __restrict__ scb,
-             double* __restrict__ partials) {
-  const ScalarBlock* sc = scb + blockIdx.y;
-  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+__device__ __forceinline__ void update_body(cx<V>* __restrict__ x, const cx<V>* __restrict__ p, cx<V>* __restrict__ r,
+                                            const cx<V>* __restrict__ q, int64_t P,
+                                            const ScalarBlock* __restrict__ scb, double* __restrict__ partials,
+                                            int64_t bid, int64_t nb, int64_t rhs) {
+  const ScalarBlock* sc = scb + rhs;
+  const int64_t off = rhs * P;
   const cxd al = {sc->alpha_re, sc->alpha_im};
   const bool moving = al.re != 0.0 || al.im != 0.0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  ORI_RHS_LOOP(i) {
+  for (int64_t i = bid * blockDim.x + threadIdx.x; i < P; i += nb * blockDim.x) {
     cxd rd;
     if (moving) {
-      if (x) x[off + i] = cvt<V>(cvt<double>(x[off + i]) + al * cvt<double>(p[off + i]));
-      const cx<V> rs = cvt<V>(cvt<double>(r[off + i]) - al * cvt<double>(q[off + i]));
+      if (x) x[off + i] = cvt<V>(cfma(al, cvt<double>(p[off + i]), cvt<double>(x[off + i])));
+      const cx<V> rs = cvt<V>(cfms(al, cvt<double>(q[off + i]), cvt<double>(r[off + i])));
       r[off + i] = rs;
       rd = cvt<double>(rs);  // reduce what was stored
     } else {
@@ -300,7 +307,38 @@ __global__ void __launch_bounds__(kRedThreads)
     acc[1] += rr.im;
     acc[2] += norm2(rd);
   }
-  block_sum4(acc, partials + 4 * (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x));
+  block_sum4(acc, partials + 4 * (rhs * nb + bid));
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kRedThreads)
+    k_update(cx<V>* __restrict__ x, const cx<V>* __restrict__ p, cx<V>* __restrict__ r,
+             const cx<V>* __restrict__ q, int64_t P, const ScalarBlock* __restrict__ scb,
+             double* __restrict__ partials) {
+  update_body<V>(x, p, r, q, P, scb, partials, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+// The finalisation and the update of several problems in one launch
+// (MultiFin, MultiUpd): workgroup b belongs to the problem whose range of
+// workgroups holds it, and runs that problem's workgroup b - first_block.
+template <typename E>
+__device__ __forceinline__ int find_problem(const E* __restrict__ tab, int32_t np, int64_t b) {
+  int p = 0;
+  while (p + 1 < np && tab[p + 1].first_block <= b) ++p;
+  return p;
+}
+
+__global__ void __launch_bounds__(kFinThreads)
+    k_multi_finalize(const MultiFin* __restrict__ tab, int32_t np, int32_t mode, double eps) {
+  const MultiFin& m = tab[find_problem(tab, np, blockIdx.x)];
+  finalize_body(m.partials, m.nblk, m.sc, blockIdx.x - m.first_block, mode, eps, 0.0, 0, nullptr);
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kRedThreads) k_multi_update(const MultiUpd* __restrict__ tab, int32_t np) {
+  const MultiUpd& m = tab[find_problem(tab, np, blockIdx.x)];
+  update_body<V>(nullptr, static_cast<const cx<V>*>(m.p), static_cast<cx<V>*>(m.r), static_cast<const cx<V>*>(m.q),
+                 m.P, m.sc, m.partials, blockIdx.x - m.first_block, m.nblocks, 0);
 }
 
 template <typename V>
@@ -310,7 +348,7 @@ __global__ void __launch_bounds__(256)
   const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
   const cxd al = {sc->alpha_re, sc->alpha_im};
   if (al.re == 0.0 && al.im == 0.0) return;
-  ORI_RHS_LOOP(i) x[off + i] = cvt<V>(cvt<double>(x[off + i]) + al * cvt<double>(p[off + i]));
+  ORI_RHS_LOOP(i) x[off + i] = cvt<V>(cfma(al, cvt<double>(p[off + i]), cvt<double>(x[off + i])));
 }
 
 template <typename V>
@@ -449,6 +487,20 @@ hipError_t launch_update(int prec, void* x, const void* p, void* r, const void* 
     e = launch_kernel(k_update<float>, red_grid(P, nrhs, kUpdateBlocksMaxF32), dim3(kRedThreads), st, static_cast<cxf*>(x),
                        static_cast<const cxf*>(p), static_cast<cxf*>(r), static_cast<const cxf*>(q), P, sc, partials);
   return e;
+}
+
+hipError_t launch_multi_finalize(const MultiFin* tab, int32_t np, int64_t blocks, int32_t mode, double eps,
+                                 hipStream_t st) {
+  if (np < 1 || blocks < 1) return hipErrorInvalidValue;
+  return launch_kernel(k_multi_finalize, dim3(static_cast<unsigned>(blocks)), dim3(kFinThreads), st, tab, np, mode,
+                       eps);
+}
+
+hipError_t launch_multi_update(int prec, const MultiUpd* tab, int32_t np, int64_t blocks, hipStream_t st) {
+  if (np < 1 || blocks < 1) return hipErrorInvalidValue;
+  if (prec == PREC_F64)
+    return launch_kernel(k_multi_update<double>, dim3(static_cast<unsigned>(blocks)), dim3(kRedThreads), st, tab, np);
+  return launch_kernel(k_multi_update<float>, dim3(static_cast<unsigned>(blocks)), dim3(kRedThreads), st, tab, np);
 }
 
 hipError_t launch_x_flush(int prec, void* x, const void* p, int64_t P, int64_t nrhs, const ScalarBlock* sc,

@@ -50,7 +50,7 @@ __device__ __forceinline__ cx<T> mul_w16(cx<T> a) {
   if constexpr (M == 4) return mul_w4<INV>(a);
   const T c = static_cast<T>(cs[M]);
   const T s = INV ? static_cast<T>(sn[M]) : static_cast<T>(-sn[M]);
-  return {a.re * c - a.im * s, a.re * s + a.im * c};
+  return {fmadd(a.re, c, -(a.im * s)), fmadd(a.re, s, a.im * c)};
 }
 
 template <bool INV, int R, typename T>
@@ -157,7 +157,7 @@ struct Dft<INV, 3, T> {
     constexpr double S = 0.86602540378443864676;  // sin(2 pi / 3)
     const T sg = INV ? static_cast<T>(S) : static_cast<T>(-S);
     cx<T> s = v[1] + v[2], d = v[1] - v[2];
-    cx<T> m = {v[0].re + static_cast<T>(C) * s.re, v[0].im + static_cast<T>(C) * s.im};
+    cx<T> m = {fmadd(static_cast<T>(C), s.re, v[0].re), fmadd(static_cast<T>(C), s.im, v[0].im)};
     cx<T> id = {-sg * d.im, sg * d.re};  // i * sg * d
     v[0] = v[0] + s;
     v[1] = m + id;
@@ -177,11 +177,11 @@ struct Dft<INV, 5, T> {
     const T c1 = static_cast<T>(C1), c2 = static_cast<T>(C2);
     cx<T> b1 = v[1] + v[4], b2 = v[2] + v[3];
     cx<T> d1 = v[1] - v[4], d2 = v[2] - v[3];
-    cx<T> m1 = {v[0].re + c1 * b1.re + c2 * b2.re, v[0].im + c1 * b1.im + c2 * b2.im};
-    cx<T> m2 = {v[0].re + c2 * b1.re + c1 * b2.re, v[0].im + c2 * b1.im + c1 * b2.im};
+    cx<T> m1 = {fmadd(c2, b2.re, fmadd(c1, b1.re, v[0].re)), fmadd(c2, b2.im, fmadd(c1, b1.im, v[0].im))};
+    cx<T> m2 = {fmadd(c1, b2.re, fmadd(c2, b1.re, v[0].re)), fmadd(c1, b2.im, fmadd(c2, b1.im, v[0].im))};
     // i * (s1 d1 + s2 d2) and i * (s2 d1 - s1 d2)
-    cx<T> n1 = {-(s1 * d1.im + s2 * d2.im), s1 * d1.re + s2 * d2.re};
-    cx<T> n2 = {-(s2 * d1.im - s1 * d2.im), s2 * d1.re - s1 * d2.re};
+    cx<T> n1 = {-fmadd(s1, d1.im, s2 * d2.im), fmadd(s1, d1.re, s2 * d2.re)};
+    cx<T> n2 = {-fmadd(s2, d1.im, -(s1 * d2.im)), fmadd(s2, d1.re, -(s1 * d2.re))};
     v[0] = v[0] + b1 + b2;
     v[1] = m1 + n1;
     v[4] = m1 - n1;
@@ -344,8 +344,7 @@ struct Engine {
         w[r] = tw[r * k * TS];
       } else {
         const int low = r & -r;
-        const cx<T> a = w[r - low], c = w[low];
-        w[r] = cx<T>{a.re * c.re - a.im * c.im, a.re * c.im + a.im * c.re};
+        w[r] = w[r - low] * w[low];
       }
     }
   }
@@ -374,8 +373,7 @@ struct Engine {
               ++q;
             } else {
               const int low = r & -r;
-              const cx<T> a = w[r - low], c = w[low];
-              w[r] = cx<T>{a.re * c.re - a.im * c.im, a.re * c.im + a.im * c.re};
+              w[r] = w[r - low] * w[low];
             }
           }
         } else {

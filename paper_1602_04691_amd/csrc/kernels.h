@@ -11,6 +11,8 @@
 
 #include <cstdint>
 
+#include "plan.h"
+
 namespace ori {
 
 // COCG scalars of one right-hand side, resident in device memory for the
@@ -161,6 +163,77 @@ struct LengthKernels {
 };
 
 const LengthKernels* kernels_for_length(int L);
+
+// ---------------------------------------------------------------------------
+// One pass of several problems of different padded lengths in one launch
+// (multi_passes.hip).  The problems' workgroup ranges follow each other:
+// launch workgroup b belongs to the problem p with first_block(p) <= b <
+// first_block(p + 1) and runs that problem's workgroup b - first_block(p),
+// with the pass body its length L compiles for the single-problem kernels,
+// on the tile shape below.  Lanes beyond that body's workgroup size (the
+// launch uses the largest of the problems') leave at once.  So every
+// problem computes exactly what its own launch computes.
+// ---------------------------------------------------------------------------
+struct MultiProblem {
+  int64_t first_block, nblocks;
+  int32_t L;
+  int32_t ex;    // n = L / 2 exactly (the EX bodies)
+  int32_t soff;  // Z: per-lane plus scalar tile offsets (blk_lg <= the length's alignment)
+  int32_t pad;
+  union {
+    ContigFwdArgs f1;
+    StridedArgs s;
+    ZArgs z;
+    ContigInvArgs i1;
+  } a;
+};
+enum MultiPass : int32_t { MP_F1 = 0, MP_F2 = 1, MP_Z = 2, MP_I2 = 3, MP_I1 = 4, MP_NPASS = 5 };
+// The padded lengths that have multi-problem bodies: 8 to 256 except 16,
+// whose single radix-16 stage holds 16 values per thread (a complex128 Z
+// body of 188 VGPRs would set the register budget of every problem's Z
+// workgroups in the launch).
+constexpr bool multi_length(int L) { return L >= 8 && L <= 256 && L != 16 && radix_plan(L).n > 0; }
+// Their tile shape: wide strided tiles, no Z prefetch, the default Z plan,
+// and Z tiles narrow for complex64 and wide for complex128 (the library's
+// default layout up to L = 256).  A problem whose layout differs runs its
+// own launches.
+constexpr int kMultiZNarrow[2] = {0, 1};  // [PREC_F64, PREC_F32]
+// Workgroup size of pass `pass` (MultiPass) at length L in precision prec,
+// or 0 if L has no multi-problem bodies.
+int multi_pass_threads(int L, int prec, int pass);
+// whether the Z pass of that length addresses its tiles with scalar offsets
+// at i1 block 2^e_lg (MultiProblem::soff, as the single-problem launch decides)
+bool multi_z_soff(int L, int prec, int e_lg);
+// LDS bytes of that pass and length
+int multi_pass_smem(int L, int prec, int pass);
+// tab: device array of np problems (first_block ascending), blocks = the
+// sum of their nblocks; threads and smem = the largest multi_pass_threads
+// and multi_pass_smem of them.
+hipError_t launch_multi_pass(int prec, int pass, const MultiProblem* tab, int32_t np, int64_t blocks, int threads,
+                             int smem, hipStream_t st);
+
+// finalisation of several problems: problem p's right-hand sides are
+// workgroups [first_block, first_block + nrhs) of the launch
+struct MultiFin {
+  const double* partials;
+  int64_t nblk;  // partial quadruples per right-hand side
+  ScalarBlock* sc;
+  int64_t first_block;
+};
+// COCG update (r -= alpha q, partials) of several problems, one right-hand
+// side each, on their own update_blocks(P, prec) workgroups
+struct MultiUpd {
+  const void* p;
+  void* r;
+  const void* q;
+  int64_t P;
+  const ScalarBlock* sc;
+  double* partials;
+  int64_t first_block, nblocks;
+};
+hipError_t launch_multi_finalize(const MultiFin* tab, int32_t np, int64_t blocks, int32_t mode, double eps,
+                                 hipStream_t st);
+hipError_t launch_multi_update(int prec, const MultiUpd* tab, int32_t np, int64_t blocks, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Elementwise / reduction kernels (aux.hip).  Batched kernels run a grid of

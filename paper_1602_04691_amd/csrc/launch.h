@@ -27,8 +27,8 @@ struct GraphBuild {
 GraphBuild* graph_being_built();
 
 template <class... P, class... A, size_t... I>
-hipError_t launch_kernel_impl(void (*k)(P...), dim3 grid, dim3 block, hipStream_t st, std::index_sequence<I...>,
-                              A&&... args) {
+hipError_t launch_kernel_impl(void (*k)(P...), dim3 grid, dim3 block, unsigned smem, hipStream_t st,
+                              std::index_sequence<I...>, A&&... args) {
   // the arguments converted to the kernel's parameter types, one address each
   std::tuple<std::decay_t<P>...> vals(std::forward<A>(args)...);
   void* params[sizeof...(P) + 1] = {static_cast<void*>(&std::get<I>(vals))..., nullptr};
@@ -37,7 +37,7 @@ hipError_t launch_kernel_impl(void (*k)(P...), dim3 grid, dim3 block, hipStream_
     kp.func = reinterpret_cast<void*>(k);
     kp.gridDim = grid;
     kp.blockDim = block;
-    kp.sharedMemBytes = 0;
+    kp.sharedMemBytes = smem;
     kp.kernelParams = params;
     kp.extra = nullptr;
     hipGraphNode_t node = nullptr;
@@ -46,14 +46,21 @@ hipError_t launch_kernel_impl(void (*k)(P...), dim3 grid, dim3 block, hipStream_
     if (e == hipSuccess) gb->last = node;
     return e;
   }
-  return hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, params, 0, st);
+  return hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, params, smem, st);
 }
 
 // k<<<grid, block, 0, st>>>(args...), or a node of the graph being built.
 template <class... P, class... A>
 hipError_t launch_kernel(void (*k)(P...), dim3 grid, dim3 block, hipStream_t st, A&&... args) {
   static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
-  return launch_kernel_impl(k, grid, block, st, std::index_sequence_for<P...>{}, std::forward<A>(args)...);
+  return launch_kernel_impl(k, grid, block, 0u, st, std::index_sequence_for<P...>{}, std::forward<A>(args)...);
+}
+
+// The same with smem bytes of dynamic LDS.
+template <class... P, class... A>
+hipError_t launch_kernel_smem(void (*k)(P...), dim3 grid, dim3 block, unsigned smem, hipStream_t st, A&&... args) {
+  static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+  return launch_kernel_impl(k, grid, block, smem, st, std::index_sequence_for<P...>{}, std::forward<A>(args)...);
 }
 
 }  // namespace ori

@@ -18,6 +18,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "cx.h"
@@ -120,6 +121,7 @@ struct IterGraph {
     int iters = 0;
     bool first = false;
     std::vector<ori_ctx> members;
+    const void* multi = nullptr;  // the MultiSet its launches serve, or NULL (one chain per member)
   };
   std::vector<Entry> entries;
   hipEvent_t done = nullptr;  // recorded after a replay, waited on by each member's stream
@@ -407,7 +409,21 @@ int64_t rblocks(ori_ctx c) { return red_blocks(c->P); }
 // the FFT product: F1 -> F2 -> Z -> I2 -> I1 (prologue / epilogue in f1, i1),
 // over all right-hand sides of the context at once
 // ---------------------------------------------------------------------------
-ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvArgs i1, int64_t* nblk_out) {
+
+// The arguments of the five passes of one product of context c with FFTs
+// of precision fprec, from the prologue f1 and the epilogue i1, and the
+// workgroups of each pass.
+struct PassArgs {
+  ContigFwdArgs f1;
+  StridedArgs f2;
+  ZArgs z;
+  StridedArgs i2;
+  ContigInvArgs i1;
+  int64_t blocks[MP_NPASS];
+  int64_t i1_blocks_per_rhs;
+};
+
+ori_status pass_args(ori_ctx c, int fprec, ContigFwdArgs f1, ContigInvArgs i1, PassArgs* out) {
   const int64_t n = c->n, L = c->L, R = c->nrhs;
   const int64_t elem = fprec == PREC_F64 ? 16 : 8;
   char* A = static_cast<char*>(c->arena);
@@ -423,7 +439,7 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   f1.in_pitch = n;
   f1.out_pitch = L;
   f1.tw = tw;
-  ORI_TRY(launch(c, K_F1, fprec, [&] { return c->K->contig_fwd(vprec, fprec, f1, c->stream); }));
+  out->f1 = f1;
 
   // B layout: i1 split into blocks of 2^lg rows (see ZArgs); the batch is
   // just more outer rows
@@ -431,8 +447,7 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   const int lg = kn.blk_lg;
   const int64_t Bk = int64_t{1} << lg;
   const int ns = kn.np_sel;
-  StridedArgs f2{A, B, R * n, L, n, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, ns, tw};
-  ORI_TRY(launch(c, K_F2, fprec, [&] { return c->K->strided(fprec, f2, c->stream); }));
+  out->f2 = StridedArgs{A, B, R * n, L, n, 0, lg, n * L, 0, L, L * L * Bk, L, Bk * L, 0, 1, 0, ns, tw};
 
   // Small grids (a batch at small n) are split over the right-hand sides,
   // so that the pass has enough workgroups to fill the chip; no slice is
@@ -440,12 +455,10 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   const int64_t zbase = c->K->zpass_blocks(fprec, kn.z_np);
   int64_t rs = std::min<int64_t>(R, (kZMinWorkgroups + zbase - 1) / zbase);
   if (rs > 1) rs = (R + (R + rs - 1) / rs - 1) / ((R + rs - 1) / rs);
-  ZArgs z{B,  n,  lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, static_cast<int32_t>(rs),
-          kh, L / 2 + 1, tw, kn.zplan};
-  ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, z, c->stream); }));
+  out->z = ZArgs{B,  n,  lg, kn.z_np, L * L * Bk, L, Bk * L, R, n * L * L, kn.zpf, static_cast<int32_t>(rs),
+                 kh, L / 2 + 1, tw, kn.zplan};
 
-  StridedArgs i2{B, A, R * n, L, n, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};
-  ORI_TRY(launch(c, K_I2, fprec, [&] { return c->K->strided(fprec, i2, c->stream); }));
+  out->i2 = StridedArgs{B, A, R * n, L, n, lg, 0, L * L * Bk, L, Bk * L, n * L, 0, L, 1, 0, 1, ns, tw};
 
   i1.in = A;
   i1.nrhs = R;
@@ -453,8 +466,27 @@ ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvAr
   i1.in_pitch = L;
   i1.out_pitch = n;
   i1.tw = tw;
-  if (nblk_out) *nblk_out = c->K->contig_blocks_per_rhs(n * n);
-  ORI_TRY(launch(c, K_I1, fprec, [&] { return c->K->contig_inv(vprec, fprec, i1, c->stream); }));
+  out->i1 = i1;
+
+  const int64_t cb = c->K->contig_blocks_per_rhs(n * n);
+  out->i1_blocks_per_rhs = cb;
+  out->blocks[MP_F1] = R * cb;
+  out->blocks[MP_F2] = c->K->strided_blocks(fprec, ns, R * n, L);
+  out->blocks[MP_Z] = zbase * rs;
+  out->blocks[MP_I2] = c->K->strided_blocks(fprec, ns, R * n, L);
+  out->blocks[MP_I1] = R * cb;
+  return ORI_OK;
+}
+
+ori_status matvec(ori_ctx c, int vprec, int fprec, ContigFwdArgs f1, ContigInvArgs i1, int64_t* nblk_out) {
+  PassArgs pa;
+  ORI_TRY(pass_args(c, fprec, f1, i1, &pa));
+  ORI_TRY(launch(c, K_F1, fprec, [&] { return c->K->contig_fwd(vprec, fprec, pa.f1, c->stream); }));
+  ORI_TRY(launch(c, K_F2, fprec, [&] { return c->K->strided(fprec, pa.f2, c->stream); }));
+  ORI_TRY(launch(c, K_Z, fprec, [&] { return c->K->zpass(fprec, pa.z, c->stream); }));
+  ORI_TRY(launch(c, K_I2, fprec, [&] { return c->K->strided(fprec, pa.i2, c->stream); }));
+  if (nblk_out) *nblk_out = pa.i1_blocks_per_rhs;
+  ORI_TRY(launch(c, K_I1, fprec, [&] { return c->K->contig_inv(vprec, fprec, pa.i1, c->stream); }));
   return ORI_OK;
 }
 
@@ -571,6 +603,168 @@ ori_status iteration(ori_ctx c, int prec, bool first) {
 // stream each), or a single context.
 using Members = std::vector<ori_ctx>;
 
+// ---------------------------------------------------------------------------
+// The COCG iteration of several problems in one launch per kernel
+// (kernels.h, MultiProblem; the uneven batch of an ori_group).  A MultiSet
+// holds the device tables of one set of members in one precision: the five
+// passes (F1 twice: the first iteration and the others), the finalisations
+// of the product and of the update, and the update.  The tables hold the
+// arguments each member's own launches take, so every member computes what
+// its own solve computes.
+// ---------------------------------------------------------------------------
+struct MultiSet {
+  Members members;
+  int prec = 0;
+  void* dev = nullptr;  // every table, one allocation
+  const MultiProblem* f1_first = nullptr;
+  const MultiProblem* pass[MP_NPASS] = {};
+  int64_t blocks[MP_NPASS] = {};
+  int threads[MP_NPASS] = {};
+  int smem[MP_NPASS] = {};
+  const MultiFin* fin_mu = nullptr;
+  const MultiFin* fin_rho = nullptr;
+  const MultiUpd* upd = nullptr;
+  int64_t fin_blocks = 0, upd_blocks = 0;
+};
+
+// The MultiSets of an ori_group, built on first use and kept (a later
+// solve of the same members reuses them).  Cached graphs of either
+// precision point into them, so they go together: release() drops the
+// group's graphs (graphs[2]) first.
+struct MultiCache {
+  std::vector<std::unique_ptr<MultiSet>> sets;
+  IterGraph* graphs = nullptr;  // the group's graph caches, [2]
+  int64_t iterations = 0;       // COCG iterations run this way (per member set, not per member)
+  void release() {
+    if (graphs) {
+      graphs[0].release();
+      graphs[1].release();
+    }
+    for (auto& m : sets)
+      if (m->dev) (void)hipFree(m->dev);
+    sets.clear();
+  }
+};
+constexpr size_t kMultiSetsMax = 32;
+
+// whether the members can run in one launch per kernel in precision prec:
+// lengths with multi-problem bodies, one right-hand side each, the tile
+// shape of those bodies, no per-kernel profiling or guard checks
+bool multi_ok(const Members& ms, int prec) {
+  if (ms.size() < 2) return false;
+  const int f = prec == PREC_F32 ? 1 : 0;
+  for (ori_ctx c : ms) {
+    const Knobs& k = c->knob[f];
+    if (!multi_length(static_cast<int>(c->L)) || c->nrhs != 1 || c->prof || c->check_guards || k.np_sel != 0 ||
+        k.zpf != 0 || k.zplan != 0 || k.z_np != kMultiZNarrow[f])
+      return false;
+  }
+  return true;
+}
+
+template <class E>
+size_t table_bytes(size_t n) {
+  return (n * sizeof(E) + 255) / 256 * 256;
+}
+
+ori_status multi_set(MultiCache& mc, const Members& act, int prec, const MultiSet** out) {
+  for (auto& m : mc.sets)
+    if (m->prec == prec && m->members == act) {
+      *out = m.get();
+      return ORI_OK;
+    }
+  ori_ctx c0 = act.front();
+  const size_t M = act.size();
+  auto ms = std::make_unique<MultiSet>();
+  ms->members = act;
+  ms->prec = prec;
+  std::vector<MultiProblem> tp[MP_NPASS + 1];  // [MP_NPASS]: F1 of the first iteration
+  std::vector<MultiFin> fmu(M), frho(M);
+  std::vector<MultiUpd> up(M);
+  int64_t first[MP_NPASS] = {};
+  for (size_t i = 0; i < M; ++i) {
+    ori_ctx c = act[i];
+    const PrecVecs v = vecs(c, prec);
+    ContigFwdArgs f1{};  // as cocg_iteration
+    f1.x = v.r;
+    f1.pvec = v.p;
+    f1.xvec = v.x;
+    f1.s_in = v.S;
+    f1.sc = c->sc;
+    f1.mode = 1;
+    PassArgs pa;
+    ORI_TRY(pass_args(c, prec, f1, epi(v.q, v.p, 1.0, nullptr, 0.0, v.S, 1.0, c->partials, 0), &pa));
+    const int L = static_cast<int>(c->L);
+    for (int p = 0; p < MP_NPASS; ++p) {
+      MultiProblem e{};
+      e.first_block = first[p];
+      e.nblocks = pa.blocks[p];
+      e.L = L;
+      e.ex = 2 * c->n == c->L;
+      e.soff = multi_z_soff(L, prec, pa.z.e_lg);
+      if (p == MP_F1) e.a.f1 = pa.f1;
+      if (p == MP_F2) e.a.s = pa.f2;
+      if (p == MP_Z) e.a.z = pa.z;
+      if (p == MP_I2) e.a.s = pa.i2;
+      if (p == MP_I1) e.a.i1 = pa.i1;
+      tp[p].push_back(e);
+      if (p == MP_F1) {
+        e.a.f1.first = 1;
+        tp[MP_NPASS].push_back(e);
+      }
+      first[p] += pa.blocks[p];
+      ms->threads[p] = std::max(ms->threads[p], multi_pass_threads(L, prec, p));
+      ms->smem[p] = std::max(ms->smem[p], multi_pass_smem(L, prec, p));
+      ms->blocks[p] = first[p];
+    }
+    const int64_t ub = update_blocks(c->P, prec);
+    fmu[i] = MultiFin{c->partials, pa.i1_blocks_per_rhs, c->sc, static_cast<int64_t>(i)};
+    frho[i] = MultiFin{c->partials, ub, c->sc, static_cast<int64_t>(i)};
+    up[i] = MultiUpd{v.p, v.r, v.q, c->P, c->sc, c->partials, ms->upd_blocks, ub};
+    ms->upd_blocks += ub;
+  }
+  ms->fin_blocks = static_cast<int64_t>(M);
+  // one host image of every table, copied once
+  const size_t bp = table_bytes<MultiProblem>(M), bf = table_bytes<MultiFin>(M), bu = table_bytes<MultiUpd>(M);
+  std::vector<unsigned char> img((MP_NPASS + 1) * bp + 2 * bf + bu, 0);
+  for (int p = 0; p <= MP_NPASS; ++p) std::memcpy(img.data() + p * bp, tp[p].data(), M * sizeof(MultiProblem));
+  unsigned char* tail = img.data() + (MP_NPASS + 1) * bp;
+  std::memcpy(tail, fmu.data(), M * sizeof(MultiFin));
+  std::memcpy(tail + bf, frho.data(), M * sizeof(MultiFin));
+  std::memcpy(tail + 2 * bf, up.data(), M * sizeof(MultiUpd));
+  ORI_HIP(c0, hipMalloc(&ms->dev, img.size()));
+  const hipError_t e = hipMemcpy(ms->dev, img.data(), img.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(ms->dev);
+    return set_err(c0, ORI_ERR_DEVICE, "copy of the multi-problem tables failed: %s", hipGetErrorString(e));
+  }
+  unsigned char* d = static_cast<unsigned char*>(ms->dev);
+  for (int p = 0; p < MP_NPASS; ++p) ms->pass[p] = reinterpret_cast<const MultiProblem*>(d + p * bp);
+  ms->f1_first = reinterpret_cast<const MultiProblem*>(d + MP_NPASS * bp);
+  d += (MP_NPASS + 1) * bp;
+  ms->fin_mu = reinterpret_cast<const MultiFin*>(d);
+  ms->fin_rho = reinterpret_cast<const MultiFin*>(d + bf);
+  ms->upd = reinterpret_cast<const MultiUpd*>(d + 2 * bf);
+  mc.sets.push_back(std::move(ms));
+  *out = mc.sets.back().get();
+  return ORI_OK;
+}
+
+// One COCG iteration of every member of m on stream st: the launches of
+// cocg_iteration, one for all members each.
+ori_status multi_iteration(const MultiSet& m, bool first, hipStream_t st) {
+  ori_ctx c0 = m.members.front();
+  const int32_t np = static_cast<int32_t>(m.members.size());
+  for (int p = 0; p < MP_NPASS; ++p) {
+    const MultiProblem* tab = (p == MP_F1 && first) ? m.f1_first : m.pass[p];
+    ORI_HIP(c0, launch_multi_pass(m.prec, p, tab, np, m.blocks[p], m.threads[p], m.smem[p], st));
+  }
+  ORI_HIP(c0, launch_multi_finalize(m.fin_mu, np, m.fin_blocks, FIN_MU, kBreakdownEps, st));
+  ORI_HIP(c0, launch_multi_update(m.prec, m.upd, np, m.upd_blocks, st));
+  ORI_HIP(c0, launch_multi_finalize(m.fin_rho, np, m.fin_blocks, FIN_RHO, kBreakdownEps, st));
+  return ORI_OK;
+}
+
 // The graph of `iters` non-first iterations of every context of `active`,
 // cached in `cache`.  It is built node by node: with graph_being_built()
 // set, every launch of an iteration appends a kernel node after the previous
@@ -578,13 +772,13 @@ using Members = std::vector<ori_ctx>;
 // exactly the kernels and arguments of its eager launches, in order; the
 // chains of different contexts are independent, so the GPU runs them side
 // by side.  No stream is put into capture mode.
-ori_status iteration_graph(const Members& active, int prec, int iters, bool first, IterGraph& cache,
-                           hipGraphExec_t* out) {
+ori_status iteration_graph(const Members& active, int prec, int iters, bool first, const MultiSet* multi,
+                           IterGraph& cache, hipGraphExec_t* out) {
   *out = nullptr;
   ori_ctx c0 = active.front();
   auto& ents = cache.entries;
   for (size_t i = 0; i < ents.size(); ++i) {
-    if (ents[i].iters == iters && ents[i].first == first && ents[i].members == active) {
+    if (ents[i].iters == iters && ents[i].first == first && ents[i].members == active && ents[i].multi == multi) {
       std::rotate(ents.begin() + i, ents.begin() + i + 1, ents.end());
       *out = ents.back().exec;
       return ORI_OK;
@@ -599,12 +793,17 @@ ori_status iteration_graph(const Members& active, int prec, int iters, bool firs
   ORI_HIP(c0, hipGraphCreate(&gb.graph, 0));
   t_graph = &gb;
   ori_status st = ORI_OK;
-  for (ori_ctx c : active) {
-    gb.last = nullptr;  // a chain of its own
-    for (int it = 0; it < iters && st == ORI_OK; ++it) st = iteration(c, prec, first && it == 0);
-    if (st != ORI_OK) {
-      if (c != c0) set_err(c0, st, "%s", c->err.c_str());
-      break;
+  if (multi) {
+    // one chain: the launches of every member together
+    for (int it = 0; it < iters && st == ORI_OK; ++it) st = multi_iteration(*multi, first && it == 0, c0->stream);
+  } else {
+    for (ori_ctx c : active) {
+      gb.last = nullptr;  // a chain of its own
+      for (int it = 0; it < iters && st == ORI_OK; ++it) st = iteration(c, prec, first && it == 0);
+      if (st != ORI_OK) {
+        if (c != c0) set_err(c0, st, "%s", c->err.c_str());
+        break;
+      }
     }
   }
   t_graph = nullptr;
@@ -618,7 +817,7 @@ ori_status iteration_graph(const Members& active, int prec, int iters, bool firs
   }
   (void)hipGraphDestroy(gb.graph);
   if (st != ORI_OK) return st;
-  ents.push_back(IterGraph::Entry{exec, iters, first, active});
+  ents.push_back(IterGraph::Entry{exec, iters, first, active, multi});
   *out = exec;
   return ORI_OK;
 }
@@ -664,7 +863,7 @@ ori_status sync_members(const Members& ms) {
 // iteration budget running out) runs eagerly.  Each member runs exactly the
 // kernels of its own solve, so results do not depend on the other members.
 ori_status group_cocg(const Members& ms, int prec, const std::vector<int>& budget, int check_every, bool use_graph,
-                      IterGraph& cache, std::vector<int>* ran) {
+                      IterGraph& cache, MultiCache* mc, std::vector<int>* ran) {
   ran->assign(ms.size(), 0);
   ORI_TRY(sync_members(ms));
   for (ori_ctx c : ms) {
@@ -680,19 +879,32 @@ ori_status group_cocg(const Members& ms, int prec, const std::vector<int>& budge
     for (size_t i : act) blk = std::min(blk, budget[i] - (*ran)[i]);
     Members active;
     for (size_t i : act) active.push_back(ms[i]);
+    // members that fit run in one launch per kernel (multi_ok)
+    const MultiSet* mset = nullptr;
+    if (mc && multi_ok(active, prec)) {
+      if (mc->sets.size() >= kMultiSetsMax) mc->release();  // with every graph that points into them
+      ORI_TRY(multi_set(*mc, active, prec, &mset));
+    }
     hipGraphExec_t exec = nullptr;
-    if (use_graph && blk == check_every) ORI_TRY(iteration_graph(active, prec, blk, it == 0, cache, &exec));
+    if (use_graph && blk == check_every) ORI_TRY(iteration_graph(active, prec, blk, it == 0, mset, cache, &exec));
+    ori_ctx c0 = active.front();
+    if (mset) mc->iterations += blk;
     if (exec) {
-      // the replay runs every member's chain on the first member's stream;
-      // the other members' streams wait for it before their next work
-      ori_ctx c0 = active.front();
       ORI_HIP(c0, hipGraphLaunch(exec, c0->stream));
-      ORI_HIP(c0, hipEventRecord(cache.done, c0->stream));
-      for (ori_ctx c : active)
-        if (c->stream != c0->stream) ORI_HIP(c, hipStreamWaitEvent(c->stream, cache.done, 0));
+    } else if (mset) {
+      for (int j = 0; j < blk; ++j) ORI_TRY(multi_iteration(*mset, it + j == 0, c0->stream));
     } else {
       for (int j = 0; j < blk; ++j)
         for (ori_ctx c : active) ORI_TRY(iteration(c, prec, it + j == 0));
+    }
+    if (exec || mset) {
+      // a replay, or the multi-problem launches, ran every member's work on
+      // the first member's stream; the other members' streams wait for it
+      // before their next work
+      if (!cache.done) ORI_HIP(c0, hipEventCreateWithFlags(&cache.done, hipEventDisableTiming));
+      ORI_HIP(c0, hipEventRecord(cache.done, c0->stream));
+      for (ori_ctx c : active)
+        if (c->stream != c0->stream) ORI_HIP(c, hipStreamWaitEvent(c->stream, cache.done, 0));
     }
     it += blk;
     for (size_t i : act) (*ran)[i] += blk;
@@ -881,7 +1093,8 @@ struct SymJob {
 // targets for the refinement loop.  Counts go to each member's outcome
 // (added).  Every member runs the kernels of its own solve in the same
 // order as alone, so its results do not depend on the others.
-ori_status solve_sym_group(std::vector<SymJob>& jobs, const ori_solve_opts& o, IterGraph* cache) {
+ori_status solve_sym_group(std::vector<SymJob>& jobs, const ori_solve_opts& o, IterGraph* cache,
+                           MultiCache* mc = nullptr) {
   const size_t M = jobs.size();
   Members ms;
   for (auto& j : jobs) ms.push_back(j.c);
@@ -892,7 +1105,8 @@ ori_status solve_sym_group(std::vector<SymJob>& jobs, const ori_solve_opts& o, I
   }
   std::vector<int> ran;
   if (o.precision == ORI_FP64) {
-    ORI_TRY(group_cocg(ms, PREC_F64, std::vector<int>(M, o.max_iter), o.check_every, o.graph != 0, cache[0], &ran));
+    ORI_TRY(
+        group_cocg(ms, PREC_F64, std::vector<int>(M, o.max_iter), o.check_every, o.graph != 0, cache[0], mc, &ran));
     for (auto& j : jobs) {
       for (int64_t i = 0; i < j.c->nrhs; ++i) {
         const ScalarBlock& s = j.c->sc_host[i];
@@ -961,7 +1175,7 @@ ori_status solve_sym_group(std::vector<SymJob>& jobs, const ori_solve_opts& o, I
       am.push_back(c);
       budget.push_back(inner_left[m]);
     }
-    ORI_TRY(group_cocg(am, PREC_F32, budget, o.check_every, o.graph != 0, cache[1], &ran));
+    ORI_TRY(group_cocg(am, PREC_F32, budget, o.check_every, o.graph != 0, cache[1], mc, &ran));
     for (size_t a = 0; a < act.size(); ++a) {
       const size_t m = act[a];
       ori_ctx c = jobs[m].c;
@@ -1005,7 +1219,7 @@ ori_status solve_sym(ori_ctx c, const ori_solve_opts& o, const cxd* rhs, const s
 // (guess) or 0, solve (in lockstep), recover u (recover: w / S, or
 // u0 - G0 S w), true residual.
 ori_status forward_solve_group(const Members& ms, const ori_solve_opts& o, const std::vector<cxd*>& u,
-                               std::vector<Outcome>* ocs, IterGraph* cache) {
+                               std::vector<Outcome>* ocs, IterGraph* cache, MultiCache* mc = nullptr) {
   const double tol2 = o.tol * o.tol;
   ocs->resize(ms.size());
   std::vector<SymJob> jobs;
@@ -1027,7 +1241,7 @@ ori_status forward_solve_group(const Members& ms, const ori_solve_opts& o, const
     }
     jobs.push_back(SymJob{c, c->b, c->bnorm2, oc});
   }
-  ORI_TRY(solve_sym_group(jobs, o, cache));
+  ORI_TRY(solve_sym_group(jobs, o, cache, mc));
   // every member's recovery and true residual launched, then one wait per
   // stream
   for (size_t m = 0; m < ms.size(); ++m) {
@@ -1242,6 +1456,7 @@ struct ori_group_s {
   hipStream_t caller = nullptr;
   hipEvent_t ready = nullptr;
   IterGraph graphs[2];  // per vector precision
+  MultiCache multi;     // tables of the one-launch-per-kernel iterations
 };
 
 namespace {
@@ -1270,6 +1485,7 @@ void ori_default_opts(ori_solve_opts* o) {
   o->max_outer = 10;
   o->true_residual = 1;
   o->graph = 1;
+  o->multi = 1;
 }
 
 const char* ori_version(void) { return "ori 0.2 (gfx950)"; }
@@ -1747,6 +1963,7 @@ ori_status ori_group_create(const ori_grid* grids, int32_t nprob, int32_t provis
   if (!grids) return set_err(nullptr, ORI_ERR_INVALID_ARG, "grids is NULL");
   if (nprob < 1 || nprob > 64) return set_err(nullptr, ORI_ERR_INVALID_ARG, "nprob = %d out of [1, 64]", nprob);
   ori_group g = new ori_group_s();
+  g->multi.graphs = g->graphs;
   g->caller = static_cast<hipStream_t>(stream);
   if (hipEventCreateWithFlags(&g->ready, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
@@ -1826,7 +2043,7 @@ ori_status ori_group_solve(ori_group g, const ori_solve_opts* opts_in, void* con
     us[m] = static_cast<cxd*>(u[m]);
   }
   std::vector<Outcome> ocs;
-  ori_status st = forward_solve_group(g->members, o, us, &ocs, g->graphs);
+  ori_status st = forward_solve_group(g->members, o, us, &ocs, g->graphs, o.multi ? &g->multi : nullptr);
   for (size_t m = 0; m < M && st == ORI_OK; ++m) {
     ori_ctx c = g->members[m];
     if (hipStreamSynchronize(c->stream) != hipSuccess) st = set_err(c, ORI_ERR_DEVICE, "hipStreamSynchronize failed");
@@ -1855,10 +2072,18 @@ ori_status ori_group_solve(ori_group g, const ori_solve_opts* opts_in, void* con
   return worst;
 }
 
+ori_status ori_group_multi_iterations(ori_group g, int64_t* iterations) {
+  if (!g) return set_err(nullptr, ORI_ERR_INVALID_ARG, "group is NULL");
+  if (!iterations) return set_err(nullptr, ORI_ERR_INVALID_ARG, "iterations is NULL");
+  *iterations = g->multi.iterations;
+  return ORI_OK;
+}
+
 void ori_group_destroy(ori_group g) {
   if (!g) return;
-  for (auto& gr : g->graphs) gr.release();
-  for (ori_ctx c : g->members) ori_destroy(c);  // waits for each member's stream
+  for (ori_ctx c : g->members) (void)hipStreamSynchronize(c->stream);  // nothing of the group in flight
+  g->multi.release();  // the graphs, then the tables their nodes point into
+  for (ori_ctx c : g->members) ori_destroy(c);
   for (hipStream_t sm : g->streams) (void)hipStreamDestroy(sm);
   if (g->ready) (void)hipEventDestroy(g->ready);
   delete g;

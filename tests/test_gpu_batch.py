@@ -220,3 +220,38 @@ def test_group_load_all_reports_bad_input():
         for j, (n, c) in enumerate(zip(ns, cases)):
             u1, _ = ori.solve(n, 4.0, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]), tol=1e-10)
             assert torch.equal(us[j], u1), n
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_group_one_launch_per_kernel_bitwise(prec):
+    # problems of five padded lengths (n = 5, 9, 20, 33, 48: L = 10, 20, 40,
+    # 80, 96; n = 9 and 33 not L / 2) solved with the iterations of all
+    # running problems in one launch per kernel, with graph replay and
+    # eagerly: bitwise the group's own per-problem launches and each
+    # problem's ori_solve, and the multi-problem iterations did run
+    ns = (5, 9, 20, 33, 48)
+    say(f"[multi] n in {ns}, precision {prec}")
+    cases = [workloads.make_case(n, 2.0 + 0.5 * j, seed=90 + j) for j, n in enumerate(ns)]
+    with ori.ori_group_create(ns) as g:
+        ori.ori_group_load_all(g, [2.0 + 0.5 * j for j in range(len(ns))], [gpu(c["h"]) for c in cases],
+                               [gpu(c["N"]) for c in cases], [gpu(c["u0"]) for c in cases])
+        runs = {}
+        for multi, graph, ce in ((True, True, 2), (True, False, 1), (False, True, 2)):
+            before = ori.ori_group_multi_iterations(g)
+            us = [torch.empty(n ** 3, dtype=torch.complex128, device="cuda") for n in ns]
+            _, infos = ori.ori_group_solve(g, us, tol=1e-10, precision=prec, multi=multi, graph=graph,
+                                           check_every=ce)
+            ran = ori.ori_group_multi_iterations(g) - before
+            say(f"   multi={multi} graph={graph}: {ran} multi-problem iterations, "
+                f"iterations {[i['iterations'] for i in infos]}")
+            assert (ran > 0) == multi
+            runs[(multi, graph)] = (us, infos)
+        ref_us, ref_infos = runs[(False, True)]
+        for key, (us, infos) in runs.items():
+            for j in range(len(ns)):
+                assert torch.equal(us[j], ref_us[j]), (key, ns[j])
+                assert infos[j]["iterations"] == ref_infos[j]["iterations"]
+        for j, (n, c) in enumerate(zip(ns, cases)):
+            u1, i1 = ori.solve(n, 2.0 + 0.5 * j, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]), tol=1e-10, precision=prec)
+            assert torch.equal(ref_us[j], u1), n
+            assert i1["iterations"] == ref_infos[j]["iterations"]
