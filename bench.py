@@ -199,9 +199,9 @@ def next_workload(a):
     batch   n = 64, k = 5, 32 incident directions on a Fibonacci sphere in
             one context (one launch per pass over the whole block), mixed
             precision to tol; value = right-hand-side products per second
-    uneven  four independent problems, n = 32, 48, 64, 96, solved side by
-            side (solve_many, contexts kept between steps); value = problems
-            per second
+    uneven  four independent problems, n = 32, 48, 64, 96, solved as one
+            group (made once, loaded each step; the iterations of all running
+            problems in one launch per kernel); value = problems per second
     gradient  n = 128, k = 5: J = sum |u - t|^2 with t the solution at 1.2 h,
             and dJ/dh by one adjoint solve (ori_gradient, complex128);
             value = gradients per second
@@ -270,8 +270,8 @@ def next_workload(a):
         metric = "uneven batch: problems solved/sec, n in {32,48,64,96}, mixed precision"
         desc = {"workload": "ori_red_uneven_n32_48_64_96_k5", "n": [32, 48, 64, 96], "k": k,
                 "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23], "check_every": a.check_every,
-                "solver": "ori_group: a stream per problem for eager work, one graph replay per iteration "
-                          "block holding every running problem's chain"}
+                "solver": "ori_group: the COCG iterations of all running problems in one launch per kernel, "
+                          "each block of check_every iterations one graph replay"}
     elif a.workload == "gradient":
         n, k = 128, 5.0
         case = workloads.make_case(n, k, seed=3)
@@ -380,6 +380,23 @@ def next_workload(a):
             g2.close()
         torch.cuda.synchronize()
         extra["solves_per_s_with_group_created_each_step"] = round(len(probs) * a.steps / (time.perf_counter() - t0), 1)
+        # the same timed steps checking convergence after every iteration
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            ori.ori_group_load_all(grp, ks, hs, Ns, u0s)
+            ori.ori_group_solve(grp, us, tol=a.tol, precision=ori.ORI_MIXED, check_every=1)
+        torch.cuda.synchronize()
+        extra["solves_per_s_check_every_1"] = round(len(probs) * a.steps / (time.perf_counter() - t0), 1)
+        # and the per-problem launches of the group (ori_solve_opts.multi = 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            ori.ori_group_load_all(grp, ks, hs, Ns, u0s)
+            ori.ori_group_solve(grp, us, tol=a.tol, precision=ori.ORI_MIXED, check_every=a.check_every, multi=False)
+        torch.cuda.synchronize()
+        extra["solves_per_s_per_problem_launches"] = round(len(probs) * a.steps / (time.perf_counter() - t0), 1)
+        extra["multi_problem_iterations"] = ori.ori_group_multi_iterations(grp)
         # and every solution against the oracle: sampled rows of eq. 2.19
         res = []
         for p, uu in zip(probs, us):
@@ -387,7 +404,8 @@ def next_workload(a):
             res.append(oracle_residual(c, uu.cpu().numpy(), sample_rows(p["n"], 6, seed=p["n"])))
         extra["oracle_rows_rel_residual"] = res
         log(f"[bench] with the group made each step: {extra['solves_per_s_with_group_created_each_step']} solves/s; "
-            f"oracle rows {res}")
+            f"check_every 1: {extra['solves_per_s_check_every_1']}; per-problem launches: "
+            f"{extra['solves_per_s_per_problem_launches']}; oracle rows {res}")
         grp.close()
     if ctx is not None:
         ctx.close()
@@ -412,9 +430,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--matvecs", type=int, default=50, help="plain operator applications timed")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle rows for cpu_baseline")
-    ap.add_argument("--check-every", type=int, default=1,
-                    help="uneven workload: COCG iterations between convergence checks (each later block one "
-                         "graph replay); results are the same for any value")
+    ap.add_argument("--check-every", type=int, default=2,
+                    help="uneven workload: COCG iterations between convergence checks (each block one graph "
+                         "replay); results are bitwise the same for any value (a problem that converges inside "
+                         "a block is frozen on the device), the line also states the rate at 1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--layout", default="2,0,0,1,0/3,0,0,1,0",
