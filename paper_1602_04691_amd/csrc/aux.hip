@@ -334,6 +334,18 @@ __global__ void __launch_bounds__(kFinThreads)
   finalize_body(m.partials, m.nblk, m.sc, blockIdx.x - m.first_block, mode, eps, 0.0, 0, nullptr);
 }
 
+// The scalar blocks of several problems (one right-hand side each, the sc
+// of each MultiFin entry) copied into out[0..np), host memory the device
+// writes, so that one wait brings every problem's scalars to the host.
+static_assert(sizeof(ScalarBlock) % sizeof(double) == 0, "scalar blocks are whole doubles");
+__global__ void __launch_bounds__(64) k_gather_scalars(const MultiFin* __restrict__ tab, int32_t np, ScalarBlock* out) {
+  constexpr int W = static_cast<int>(sizeof(ScalarBlock) / sizeof(double));
+  for (int i = threadIdx.x; i < np * W; i += blockDim.x) {
+    const int p = i / W, w = i - p * W;
+    reinterpret_cast<double*>(out + p)[w] = reinterpret_cast<const double*>(tab[p].sc)[w];
+  }
+}
+
 template <typename V>
 __global__ void __launch_bounds__(kRedThreads) k_multi_update(const MultiUpd* __restrict__ tab, int32_t np) {
   const MultiUpd& m = tab[find_problem(tab, np, blockIdx.x)];
@@ -494,6 +506,11 @@ hipError_t launch_multi_finalize(const MultiFin* tab, int32_t np, int64_t blocks
   if (np < 1 || blocks < 1) return hipErrorInvalidValue;
   return launch_kernel(k_multi_finalize, dim3(static_cast<unsigned>(blocks)), dim3(kFinThreads), st, tab, np, mode,
                        eps);
+}
+
+hipError_t launch_gather_scalars(const MultiFin* tab, int32_t np, ScalarBlock* out, hipStream_t st) {
+  if (np < 1) return hipErrorInvalidValue;
+  return launch_kernel(k_gather_scalars, dim3(1), dim3(64), st, tab, np, out);
 }
 
 hipError_t launch_multi_update(int prec, const MultiUpd* tab, int32_t np, int64_t blocks, hipStream_t st) {

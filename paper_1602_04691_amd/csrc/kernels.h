@@ -234,6 +234,8 @@ struct MultiUpd {
 hipError_t launch_multi_finalize(const MultiFin* tab, int32_t np, int64_t blocks, int32_t mode, double eps,
                                  hipStream_t st);
 hipError_t launch_multi_update(int prec, const MultiUpd* tab, int32_t np, int64_t blocks, hipStream_t st);
+// out[p] = *tab[p].sc for p < np; out is host memory the device can write
+hipError_t launch_gather_scalars(const MultiFin* tab, int32_t np, ScalarBlock* out, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Elementwise / reduction kernels (aux.hip).  Batched kernels run a grid of

@@ -635,6 +635,8 @@ struct MultiCache {
   std::vector<std::unique_ptr<MultiSet>> sets;
   IterGraph* graphs = nullptr;  // the group's graph caches, [2]
   int64_t iterations = 0;       // COCG iterations run this way (per member set, not per member)
+  ScalarBlock* gathered = nullptr;      // pinned, one block per member: the scalars after a block of iterations
+  ScalarBlock* gathered_dev = nullptr;  // its device address
   void release() {
     if (graphs) {
       graphs[0].release();
@@ -747,6 +749,31 @@ ori_status multi_set(MultiCache& mc, const Members& act, int prec, const MultiSe
   ms->upd = reinterpret_cast<const MultiUpd*>(d + 2 * bf);
   mc.sets.push_back(std::move(ms));
   *out = mc.sets.back().get();
+  return ORI_OK;
+}
+
+// The scalar blocks of every member of m on the host after work that ran
+// on the first member's stream: one gather into pinned memory, one wait,
+// then each member's mirror.
+ori_status multi_sync_scalars(MultiCache& mc, const MultiSet& m) {
+  ori_ctx c0 = m.members.front();
+  const int32_t np = static_cast<int32_t>(m.members.size());
+  if (!mc.gathered) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&mc.gathered), 64 * sizeof(ScalarBlock), hipHostMallocDefault) !=
+        hipSuccess) {
+      mc.gathered = nullptr;
+      return set_err(c0, ORI_ERR_OUT_OF_MEMORY, "hipHostMalloc of the gathered scalars failed");
+    }
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&mc.gathered_dev), mc.gathered, 0) != hipSuccess) {
+      (void)hipHostFree(mc.gathered);
+      mc.gathered = nullptr;
+      mc.gathered_dev = nullptr;
+      return set_err(c0, ORI_ERR_DEVICE, "hipHostGetDevicePointer of the gathered scalars failed");
+    }
+  }
+  ORI_HIP(c0, launch_gather_scalars(m.fin_mu, np, mc.gathered_dev, c0->stream));
+  ORI_HIP(c0, hipStreamSynchronize(c0->stream));
+  for (int32_t i = 0; i < np; ++i) m.members[i]->sc_host[0] = mc.gathered[i];
   return ORI_OK;
 }
 
@@ -908,7 +935,10 @@ ori_status group_cocg(const Members& ms, int prec, const std::vector<int>& budge
     }
     it += blk;
     for (size_t i : act) (*ran)[i] += blk;
-    ORI_TRY(sync_members(active));
+    if (mset)
+      ORI_TRY(multi_sync_scalars(*mc, *mset));  // the block ran on the first member's stream
+    else
+      ORI_TRY(sync_members(active));
     std::vector<size_t> next;
     for (size_t i : act) {
       trace_cocg(ms[i], prec);
@@ -2083,6 +2113,7 @@ void ori_group_destroy(ori_group g) {
   if (!g) return;
   for (ori_ctx c : g->members) (void)hipStreamSynchronize(c->stream);  // nothing of the group in flight
   g->multi.release();  // the graphs, then the tables their nodes point into
+  if (g->multi.gathered) (void)hipHostFree(g->multi.gathered);
   for (ori_ctx c : g->members) ori_destroy(c);
   for (hipStream_t sm : g->streams) (void)hipStreamDestroy(sm);
   if (g->ready) (void)hipEventDestroy(g->ready);
