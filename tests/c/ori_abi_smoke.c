@@ -1,5 +1,5 @@
 /* Standalone use of the C ABI (include/ori.h), no Python: the two-per-side
- * closed form of eq. 2.19 and the error paths.
+ * closed form of eq. 2.19, the error paths, and a group of two problems.
  *
  * With n = 2 and constant h, N, u0 = 1, cube symmetry makes all eight
  * unknowns equal, and eq. 2.19 reduces to
@@ -96,10 +96,76 @@ int main(void) {
   CHECK(info.rel_res_true >= 0.0 && info.rel_res_true < 1e-12, "true residual %.3e", info.rel_res_true);
 
   ori_destroy(ctx);
+
+  /* a group of two problems (n = 4 and 5: padded lengths 8 and 10) solved
+   * in one launch per kernel, bitwise each problem's own ori_solve */
+  {
+    const int64_t ns[2] = {4, 5};
+    ori_grid gg[2] = {{4, side, {0.0, 0.0, 0.0}, 0.5}, {5, side, {0.0, 0.0, 0.0}, 0.5}};
+    static cplx hb[125], ub[125], out_g[125], out_s[125];
+    static double Nb[125];
+    for (int i = 0; i < 125; ++i) {
+      hb[i] = (cplx){hc.re * (1.0 + 0.01 * (i % 7)), hc.im};
+      ub[i] = (cplx){cos(0.3 * i), sin(0.3 * i)};
+      Nb[i] = Nc;
+    }
+    void *hg[2], *u0g[2], *ug[2], *us = NULL;
+    double* Ng[2];
+    double kk[2] = {k, 0.5 * k};
+    for (int j = 0; j < 2; ++j) {
+      const size_t P3 = (size_t)(ns[j] * ns[j] * ns[j]);
+      CHECK(hipMalloc(&hg[j], P3 * sizeof(cplx)) == hipSuccess && hipMalloc(&u0g[j], P3 * sizeof(cplx)) == hipSuccess &&
+                hipMalloc(&ug[j], P3 * sizeof(cplx)) == hipSuccess &&
+                hipMalloc((void**)&Ng[j], P3 * sizeof(double)) == hipSuccess,
+            "hipMalloc (group)");
+      CHECK(hipMemcpy(hg[j], hb, P3 * sizeof(cplx), hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(u0g[j], ub, P3 * sizeof(cplx), hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(Ng[j], Nb, P3 * sizeof(double), hipMemcpyHostToDevice) == hipSuccess,
+            "hipMemcpy (group)");
+    }
+    CHECK(hipMalloc(&us, 125 * sizeof(cplx)) == hipSuccess, "hipMalloc (single)");
+    ori_group grp = NULL;
+    st = ori_group_create(gg, 2, ORI_PROVISION_FP64, NULL, &grp);
+    CHECK(st == ORI_OK, "ori_group_create: %s", ori_last_error(NULL));
+    st = ori_group_load_all(grp, kk, (const void* const*)hg, (const double* const*)Ng, (const void* const*)u0g);
+    CHECK(st == ORI_OK, "ori_group_load_all: %s", ori_last_error(NULL));
+    ori_solve_info ginfo[2];
+    st = ori_group_solve(grp, &o, ug, ginfo);
+    CHECK(st == ORI_OK, "ori_group_solve: %s", ori_last_error(NULL));
+    int64_t multi_iters = 0;
+    CHECK(ori_group_multi_iterations(grp, &multi_iters) == ORI_OK && multi_iters > 0,
+          "no multi-problem iterations (%lld)", (long long)multi_iters);
+    for (int j = 0; j < 2; ++j) {
+      const size_t P3 = (size_t)(ns[j] * ns[j] * ns[j]);
+      ori_ctx c1 = NULL;
+      st = ori_setup(&gg[j], kk[j], hg[j], Ng[j], u0g[j], NULL, &c1);
+      CHECK(st == ORI_OK, "ori_setup (n=%lld): %s", (long long)ns[j], ori_last_error(NULL));
+      ori_solve_info i1;
+      st = ori_solve(c1, &o, us, &i1);
+      CHECK(st == ORI_OK, "ori_solve (n=%lld): %s", (long long)ns[j], ori_last_error(c1));
+      CHECK(hipMemcpy(out_g, ug[j], P3 * sizeof(cplx), hipMemcpyDeviceToHost) == hipSuccess &&
+                hipMemcpy(out_s, us, P3 * sizeof(cplx), hipMemcpyDeviceToHost) == hipSuccess,
+            "copy back (group)");
+      CHECK(memcmp(out_g, out_s, P3 * sizeof(cplx)) == 0, "group result of n=%lld differs from its own solve",
+            (long long)ns[j]);
+      CHECK(ginfo[j].iterations == i1.iterations, "iterations differ (n=%lld)", (long long)ns[j]);
+      ori_destroy(c1);
+    }
+    ori_group_destroy(grp);
+    for (int j = 0; j < 2; ++j) {
+      hipFree(hg[j]);
+      hipFree(u0g[j]);
+      hipFree(ug[j]);
+      hipFree(Ng[j]);
+    }
+    hipFree(us);
+  }
+
   hipFree(h);
   hipFree(u0);
   hipFree(u);
   hipFree(N);
-  printf("OK %s n=2 closed form max_err=%.3e iterations=%d\n", ori_version(), err, info.iterations);
+  printf("OK %s n=2 closed form max_err=%.3e iterations=%d; group n=4,5 bitwise\n", ori_version(), err,
+         info.iterations);
   return 0;
 }

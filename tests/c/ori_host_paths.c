@@ -16,7 +16,7 @@ int main(void) {
     int64_t b = 0;
     if (ori_workspace_bytes(&gg, 1, 3, &b) != ORI_OK || b <= 0) bad++;
   }
-  ori_grid g = {7, 1.0, {0, 0, 0}, 0.5};
+  ori_grid g = {513, 1.0, {0, 0, 0}, 0.5};  /* beyond the largest planned length */
   ori_ctx c = NULL;
   if (ori_create(&g, 1, 3, 0, NULL, &c) == ORI_OK) bad++;
   if (strlen(ori_last_error(NULL)) == 0) bad++;

@@ -1,7 +1,8 @@
 """The C ABI used from a C program, without Python (tests/c/ori_abi_smoke.c,
 built next to the library by paper_1602_04691_amd/build.py): the
-two-per-side closed form of eq. 2.19 and the refusal of host pointers and
-unsupported sizes."""
+two-per-side closed form of eq. 2.19, the refusal of host pointers and
+unsupported sizes, and a group of two problems solved in one launch per
+kernel, bitwise each problem's own solve."""
 
 import os
 import subprocess
