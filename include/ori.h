@@ -244,7 +244,9 @@ typedef struct ori_group_s* ori_group; /* opaque; owns its problems' workspaces 
  * and a stream per problem (so the problems' launches run side by side).
  * stream: the caller's stream (hipStream_t or NULL); every group call starts
  * after the work already queued on it and returns after all of its own work
- * has completed.  Errors of the ori_group_* calls: ori_last_error(NULL). */
+ * has completed.  Like a context, a group is used by one thread at a time;
+ * distinct groups and contexts are independent.  Errors of the ori_group_*
+ * calls: ori_last_error(NULL). */
 ori_status ori_group_create(const ori_grid* grids, int32_t nprob, int32_t provision, void* stream, ori_group* out);
 
 /* ori_load of problem i (0 <= i < nprob): wave number, h, N, incident field
