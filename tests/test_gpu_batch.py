@@ -255,3 +255,26 @@ def test_group_one_launch_per_kernel_bitwise(prec):
             u1, i1 = ori.solve(n, 2.0 + 0.5 * j, gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]), tol=1e-10, precision=prec)
             assert torch.equal(ref_us[j], u1), n
             assert i1["iterations"] == ref_infos[j]["iterations"]
+
+
+def test_group_of_sixteen_lengths_one_launch_per_kernel():
+    # sixteen problems over eleven padded lengths (8 to 128), some with n =
+    # L / 2 and some not, in one launch per kernel: each result bitwise its
+    # own ori_solve, and the iterations ran in common launches
+    ns = (4, 5, 6, 9, 10, 12, 13, 17, 20, 24, 25, 33, 40, 48, 49, 64)
+    say(f"[multi16] n in {ns}")
+    cases = [workloads.make_case(n, 1.0 + 0.25 * (j % 5), seed=200 + j) for j, n in enumerate(ns)]
+    ks = [1.0 + 0.25 * (j % 5) for j in range(len(ns))]
+    with ori.ori_group_create(ns) as g:
+        ori.ori_group_load_all(g, ks, [gpu(c["h"]) for c in cases], [gpu(c["N"]) for c in cases],
+                               [gpu(c["u0"]) for c in cases])
+        us = [torch.empty(n ** 3, dtype=torch.complex128, device="cuda") for n in ns]
+        _, infos = ori.ori_group_solve(g, us, tol=1e-10)
+        ran = ori.ori_group_multi_iterations(g)
+        say(f"   {ran} multi-problem iterations, iterations {[i['iterations'] for i in infos]}")
+        assert ran > 0
+        for j, (n, c) in enumerate(zip(ns, cases)):
+            u1, i1 = ori.solve(n, ks[j], gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]), tol=1e-10)
+            assert torch.equal(us[j], u1), n
+            assert infos[j]["iterations"] == i1["iterations"]
+            assert infos[j]["rel_res_true"] <= 2e-10
