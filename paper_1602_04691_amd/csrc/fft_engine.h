@@ -53,6 +53,16 @@ __device__ __forceinline__ cx<T> mul_w16(cx<T> a) {
   return {fmadd(a.re, c, -(a.im * s)), fmadd(a.re, s, a.im * c)};
 }
 
+// (a, b) <- (a + t b, a - t b) in six fused multiply-adds: a - t b is formed
+// as 2a - (a + t b), so the product t b is never rounded on its own.
+template <typename T>
+__device__ __forceinline__ void bfly_tw(cx<T>& a, cx<T>& b, cx<T> t) {
+  const T pr = fmadd(-t.im, b.im, fmadd(t.re, b.re, a.re));
+  const T pi = fmadd(t.im, b.re, fmadd(t.re, b.im, a.im));
+  b = {fmadd(static_cast<T>(2), a.re, -pr), fmadd(static_cast<T>(2), a.im, -pi)};
+  a = {pr, pi};
+}
+
 template <bool INV, int R, typename T>
 struct Dft;
 
@@ -86,31 +96,106 @@ struct Dft<INV, 4, T> {
   }
 };
 
+// (a, b) <- (a + t b, a - t b) for t = exp(-+2 pi i M/8), M = 0..3: one
+// addition per component (M even), or for M odd (t = c (+-1 +- i), c =
+// cos(pi/4)) two additions and four fused multiply-adds.
+template <bool INV, int M, typename T>
+__device__ __forceinline__ void bfly_w8(cx<T>& a, cx<T>& b) {
+  if constexpr (M % 2 == 0) {
+    const cx<T> tb = M == 0 ? b : mul_w4<INV>(b);
+    b = a - tb;
+    a = a + tb;
+  } else {
+    const T c = static_cast<T>(0.70710678118654752440);
+    // t / c = sr + i si
+    constexpr T sr = M == 1 ? 1 : -1;
+    constexpr T si = INV ? 1 : -1;
+    const T u = sr * b.re - si * b.im;  // re(t b) / c
+    const T v = sr * b.im + si * b.re;  // im(t b) / c
+    b = {fmadd(-c, u, a.re), fmadd(-c, v, a.im)};
+    a = {fmadd(c, u, a.re), fmadd(c, v, a.im)};
+  }
+}
+
 template <bool INV, typename T>
 struct Dft<INV, 8, T> {
-  __device__ __forceinline__ static void combine(cx<T>* v, cx<T>* e, cx<T>* o) {
-    o[1] = mul_w16<INV, 2>(o[1]);
-    o[2] = mul_w16<INV, 4>(o[2]);
-    o[3] = mul_w16<INV, 6>(o[3]);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[k] = e[k] + o[k];
-      v[k + 4] = e[k] - o[k];
-    }
+  // Radix 8 as three layers of radix-2 butterflies, splitting the input
+  // index by its top bit first: (v_m, v_(m+4)), then (v_m, v_(m+2)) with
+  // the factors 1 and W^2, then neighbours with 1, W^2, W, W^3 (W =
+  // exp(-+2 pi i/8)).  The outputs y0..y7 come out in bit-reversed slots.
+  __device__ __forceinline__ static void layers23(cx<T>* v) {
+    bfly_w8<INV, 0>(v[0], v[2]);
+    bfly_w8<INV, 0>(v[1], v[3]);
+    bfly_w8<INV, 2>(v[4], v[6]);
+    bfly_w8<INV, 2>(v[5], v[7]);
+    bfly_w8<INV, 0>(v[0], v[1]);
+    bfly_w8<INV, 2>(v[2], v[3]);
+    bfly_w8<INV, 1>(v[4], v[5]);
+    bfly_w8<INV, 3>(v[6], v[7]);
+  }
+  __device__ __forceinline__ static void natural(cx<T>* v) {
+    const cx<T> y1 = v[4], y3 = v[6], y4 = v[1], y6 = v[3];
+    v[1] = y1;
+    v[3] = y3;
+    v[4] = y4;
+    v[6] = y6;
   }
   __device__ __forceinline__ static void run(cx<T>* v) {
-    cx<T> e[4] = {v[0], v[2], v[4], v[6]};
-    cx<T> o[4] = {v[1], v[3], v[5], v[7]};
-    Dft<INV, 4, T>::run(e);
-    Dft<INV, 4, T>::run(o);
-    combine(v, e, o);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) bfly_w8<INV, 0>(v[m], v[m + 4]);
+    layers23(v);
+    natural(v);
   }
+  // inputs 4..7 are zero
   __device__ __forceinline__ static void run_half(cx<T>* v) {
-    cx<T> e[4] = {v[0], v[2], {}, {}};
-    cx<T> o[4] = {v[1], v[3], {}, {}};
-    Dft<INV, 4, T>::run_half(e);
-    Dft<INV, 4, T>::run_half(o);
-    combine(v, e, o);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m + 4] = v[m];
+    layers23(v);
+    natural(v);
+  }
+  // the DFT of (s_m v_m): the products with the first four factors, then
+  // the first layer as bfly_tw with the other four
+  __device__ __forceinline__ static void run_scaled(cx<T>* v, const cx<T>* sc) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      v[m] = v[m] * sc[m];
+      bfly_tw(v[m], v[m + 4], sc[m + 4]);
+    }
+    layers23(v);
+    natural(v);
+  }
+  // y_j = sum_m v_m w^m W^(jm) (W = exp(-+2 pi i/8)): the twiddled butterfly
+  // of a Stockham stage as three layers of bfly_tw.  Splitting m by its top
+  // bit gives y_(2j') from A_m = v_m + w^4 v_(m+4) and y_(2j'+1) from B_m =
+  // v_m - w^4 v_(m+4), two twiddled 4-point DFTs with twiddle bases w and
+  // wW; splitting again gives 2-point DFTs with twiddles w^2, w^2 W^2, w,
+  // wW^2, wW and wW^3.  W^2 = -+i costs nothing, so the stage needs w, w^2,
+  // w^4 and wW (forward sign; the inverse conjugates them) and 12 butterflies
+  // of 6 operations, against 7 complex products and the plain butterfly.
+  __device__ __forceinline__ static void run_tw(cx<T>* v, cx<T> w1, cx<T> w2, cx<T> w4, cx<T> w1w) {
+    if constexpr (INV) {
+      w1 = conj(w1);
+      w2 = conj(w2);
+      w4 = conj(w4);
+      w1w = conj(w1w);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) bfly_tw(v[m], v[m + 4], w4);
+    const cx<T> w2v = mul_w4<INV>(w2);
+    bfly_tw(v[0], v[2], w2);
+    bfly_tw(v[1], v[3], w2);
+    bfly_tw(v[4], v[6], w2v);
+    bfly_tw(v[5], v[7], w2v);
+    bfly_tw(v[0], v[1], w1);
+    bfly_tw(v[2], v[3], mul_w4<INV>(w1));
+    bfly_tw(v[4], v[5], w1w);
+    bfly_tw(v[6], v[7], mul_w4<INV>(w1w));
+    natural(v);
+  }
+  // w exp(-2 pi i/8), w given with the forward sign
+  __device__ __forceinline__ static cx<T> times_w8(cx<T> w) {
+    const T c = static_cast<T>(0.70710678118654752440);
+    return {(w.re + w.im) * c, (w.im - w.re) * c};
   }
 };
 
@@ -281,13 +366,16 @@ struct Regs {
 // TWM selects where the twiddles of a stage come from:
 //  0: tw is the length-L table exp(-2 pi i m / L); the powers w, w^2, w^4,
 //     w^8 are read, the other powers are products of two of them;
-//  1: tw is the stage-major table (stage_table): every power w^r of every
-//     k is read, no products (fewer vector instructions, more table);
+//  1: tw is the stage-major table (stage_table): every twiddle a stage
+//     uses is read, no products (fewer vector instructions, more table);
 //  2: tw is the stage-major table of the powers of two only: w, w^2, w^4,
 //     w^8 are read, the others are products as in 0.  The lanes of a
 //     wavefront read adjacent entries (in the length-L table a stage with
 //     few butterflies reads entries TS apart, which share LDS banks), and
 //     the table holds only what the stages read.
+// A radix-8 stage with twiddles runs Dft<8>::run_tw, which uses w, w^2, w^4
+// and w exp(-2 pi i/8): the last is a table entry in mode 1 (entry
+// k TS + L/8 of the length-L table) and a product by a constant otherwise.
 template <typename T, int L, bool INV, int TP = threads_per_pencil(L), int PV = 0, int TWM = 0>
 struct Engine {
   using St = Stages<L, INV, TP, PV>;
@@ -295,13 +383,14 @@ struct Engine {
   static constexpr int TPP = St::TPP;
 
   // Stage-major twiddle table: stage s >= 1 holds w^(r k TS) for the powers
-  // r it reads (TWM 1: r = 1..R-1; TWM 2: r = 1, 2, 4, 8 below R) and k <
-  // ns(s) (TS = L / (ns(s) R)), power by power: the q-th power read at
-  // stage_offset(s) + q ns(s) + k, forward sign (the inverse conjugates on
-  // use).  Consecutive k of one r are adjacent, so the lanes of a wavefront
-  // read adjacent entries.
+  // r it reads (TWM 1: r = 1..R-1, or for R = 8 the powers 1, 2, 4 and then
+  // w exp(-2 pi i/8); TWM 2: r = 1, 2, 4, 8 below R) and k < ns(s) (TS = L /
+  // (ns(s) R)), power by power: the q-th power read at stage_offset(s) +
+  // q ns(s) + k, forward sign (the inverse conjugates on use).  Consecutive
+  // k of one r are adjacent, so the lanes of a wavefront read adjacent
+  // entries.
   static constexpr int powers_read(int R) {
-    if (TWM != 2) return R - 1;
+    if (TWM == 1) return R == 8 ? 4 : R - 1;
     int c = 0;
     for (int r = 1; r < R; r *= 2) ++c;
     return c;
@@ -322,8 +411,13 @@ struct Engine {
       if constexpr (q >= 1) {
         constexpr int nsq = St::ns(q), R = St::radix(q), TS = L / (nsq * R);
         for (int idx = tid; idx < powers_read(R) * nsq; idx += nthreads) {
-          const int r = TWM == 2 ? 1 << (idx / nsq) : idx / nsq + 1, k = idx % nsq;
-          dst[stage_offset(q) + idx] = tw_full[r * k * TS];
+          const int p = idx / nsq, k = idx % nsq;
+          int e;
+          if (TWM == 1 && R == 8)
+            e = p < 3 ? (k * TS) << p : k * TS + L / 8;
+          else
+            e = (TWM == 2 ? 1 << p : p + 1) * k * TS;
+          dst[stage_offset(q) + idx] = tw_full[e];
         }
       }
     });
@@ -359,6 +453,24 @@ struct Engine {
     for (int i = 0; i < St::cnt(s); ++i) {
       const int b = bt + i * TPP;
       if (St::nbf(s) % TPP != 0 && b >= St::nbf(s)) continue;
+      if constexpr (NSs > 1 && R == 8) {
+        const int k = b % NSs;
+        cx<T> w1, w2, w4, w1w;
+        if constexpr (TWM == 1 || TWM == 2) {
+          constexpr int o = stage_offset(s);
+          w1 = tw[o + k];
+          w2 = tw[o + NSs + k];
+          w4 = tw[o + 2 * NSs + k];
+          if constexpr (TWM == 1) w1w = tw[o + 3 * NSs + k];
+        } else {
+          w1 = tw[k * TS];
+          w2 = tw[2 * k * TS];
+          w4 = tw[4 * k * TS];
+        }
+        if constexpr (TWM != 1) w1w = Dft<INV, 8, T>::times_w8(w1);
+        Dft<INV, 8, T>::run_tw(g.v[i], w1, w2, w4, w1w);
+        continue;
+      }
       if constexpr (NSs > 1) {
         const int k = b % NSs;
         cx<T> w[R];
@@ -574,6 +686,34 @@ struct Engine {
       run_from_lds<s + 1>(bt, p, tw, fin);
     } else {
       fin(g);
+    }
+  }
+
+  // The whole transform of the elementwise product of g0 and sc (both laid
+  // out as stage 0's registers): for radix 8 the products are folded into
+  // the first butterfly layer (Dft<8>::run_scaled).  fin as in run.
+  template <class Fin>
+  __device__ __forceinline__ static void run_scaled(RegsOf<0>& g0, const RegsOf<0>& sc, int bt, LdsPencil<T> p,
+                                                    const cx<T>* __restrict__ tw, Fin&& fin) {
+    constexpr int R = St::radix(0);
+#pragma unroll
+    for (int i = 0; i < St::cnt(0); ++i) {
+      const int b = bt + i * TPP;
+      if (St::nbf(0) % TPP != 0 && b >= St::nbf(0)) continue;
+      if constexpr (R == 8) {
+        Dft<INV, 8, T>::run_scaled(g0.v[i], sc.v[i]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) g0.v[i][r] = g0.v[i][r] * sc.v[i][r];
+        Dft<INV, R, T>::run(g0.v[i]);
+      }
+    }
+    if constexpr (NS > 1) {
+      write_lds<0>(g0, bt, p);
+      __syncthreads();
+      run_from_lds<1>(bt, p, tw, fin);
+    } else {
+      fin(g0);
     }
   }
 
