@@ -194,6 +194,37 @@ def cpu_baseline(case, budget_s, x):
     return rows, vals, dt, rate, used, model
 
 
+def same_method_baseline(case, x, gpu_products, timed=2):
+    """The paper's own product on the CPU: G0 (D x) as the (2n)^3 cyclic
+    convolution of Section 3 (eq. 3.3.8) with scipy.fft on all host cores,
+    after one untimed product.  Also the GPU products' relative error
+    against it over the whole vector (gpu_products: {tag: G0 D x})."""
+    import numpy as np
+    import oracle as O
+    n, k = case["n"], case["k"]
+    D = O.coupling(case["h"], case["N"], n)
+    model, workers = host_cpu()
+    t0 = time.perf_counter()
+    conv = O.GreenConvolution(n, k, workers=workers)
+    setup = time.perf_counter() - t0
+    Dx = D * x
+    y = conv(Dx)
+    times = []
+    for _ in range(timed):
+        t0 = time.perf_counter()
+        y = conv(Dx)
+        times.append(time.perf_counter() - t0)
+    del conv
+    errs = {tag: float(np.linalg.norm(yg - y) / np.linalg.norm(y)) for tag, yg in gpu_products.items()}
+    mean = sum(times) / len(times)
+    return {"value": 1.0 / mean, "unit": "matvecs/s", "cores": workers, "kind": "same-method CPU baseline",
+            "sample": f"{timed} products G0 D x at n={n} as (2n)^3 cyclic convolutions (full complex128 3-D "
+                      f"FFTs, scipy.fft on {workers} threads, {model}) after one untimed; the Green's table "
+                      f"and its FFT took {setup:.1f}s before them",
+            "seconds_per_product": [round(t, 3) for t in times], "setup_s": round(setup, 2),
+            "gpu_vs_cpu_fft_rel_err_whole_vector": errs}
+
+
 def next_workload(a):
     """The extension workloads, one JSON line each:
     batch   n = 64, k = 5, 32 incident directions on a Fibonacci sphere in
@@ -657,6 +688,15 @@ def main():
                "gpu_vs_oracle_rel_err_on_sample": {"c128": err, "c64": errm}}
         log(f"[bench] cpu oracle: {len(rows)} rows in {dt:.1f}s on {used} cores -> {rate:.3e} matvecs/s; "
             f"GPU product err c128 {err:.2e} c64 {errm:.2e}")
+        # the same method on the host, apart from the oracle: the convolution
+        # product of Section 3 with scipy.fft on all cores
+        # (up to n = 256: at n = 512 one 1024^3 transform takes about a minute)
+        cpu["same_method"] = same_method_baseline(case, xs, {"c128": yg, "c64": ygm}) if n <= 256 else None
+        sm = cpu["same_method"]
+        if sm:
+            log(f"[bench] cpu same-method product: {sm['seconds_per_product']} s on {sm['cores']} threads "
+                f"(setup {sm['setup_s']} s) -> {sm['value']:.3f} matvecs/s; GPU product vs it over the whole "
+                f"vector: {sm['gpu_vs_cpu_fft_rel_err_whole_vector']}")
         # every solution of the timed step against the oracle: sampled rows
         # of eq. 2.19 (corners, edges, faces, random cells)
         rrows = sample_rows(n, 6, seed=7)

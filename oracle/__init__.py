@@ -11,7 +11,10 @@ Everything is complex128 / float64 NumPy, with LAPACK (``numpy.linalg.solve``,
 the singular values and the ``zgecon`` condition estimate) as the only library
 primitive beyond ``numpy.fft`` in the Section 3 route.  ``rows.py`` spreads
 independent sampled rows of eq. 2.19 over forked worker processes; each row's
-arithmetic is the single-process function's.
+arithmetic is the single-process function's.  ``fft_baseline.py`` is not
+part of the definition: it runs the paper's own method (the convolution
+product of Section 3, with ``scipy.fft`` on all host cores) as the
+same-method CPU baseline of ``bench.py``, pinned against the dense sum.
 
 Parity pins: every function is pinned by a CPU test in
 ``tests/test_oracle_pins.py`` or ``tests/test_physics_pins.py`` (no function
@@ -48,6 +51,12 @@ from .section3 import (  # noqa: F401
     scatter_section3,
 )
 from .rows import sample_rows_parallel  # noqa: F401
+from .fft_baseline import (  # noqa: F401
+    green_spectrum,
+    GreenConvolution,
+    scatter_fft,
+    solve_symmetrized_fft,
+)
 from .physics import (  # noqa: F401
     sqrt_branch_0_2pi,
     refraction_from_h,

@@ -405,6 +405,33 @@ def test_large_matvec_sampled_rows(name, nrows, bench_layout):
     assert rel(gotm, s) <= 2e-6
 
 
+@pytest.mark.parametrize("name,n_odd", [("n128_k5", None), (None, 100)])
+def test_matvec_whole_vector_vs_cpu_convolution(name, n_odd):
+    # every element of the GPU product against the same method on the host
+    # (the (2n)^3 cyclic convolution of Section 3 with scipy.fft, itself
+    # pinned against the dense sums on the CPU): n = 128, and n = 100
+    # (padded to L = 256 on the GPU, to 200 here)
+    case = workloads.named_case(name) if name else workloads.make_case(n_odd, 5.0, seed=100)
+    n, k = case["n"], case["k"]
+    say(f"[whole vector] n={n}")
+    P = n ** 3
+    x = case["u0"] * (1.0 + 0.25 * np.cos(np.arange(P) * 0.001))
+    with context(n, k, case["h"], case["N"], case["u0"]) as ctx:
+        xg = gpu(x)
+        yg = torch.empty_like(xg)
+        ori.ori_matvec(ctx, xg, yg, ori.ORI_OP_SYSTEM, ori.ORI_FP64)
+        y = cpu(yg) - x
+        ori.ori_matvec(ctx, xg, yg, ori.ORI_OP_SYSTEM, ori.ORI_MIXED)
+        ym = cpu(yg) - x
+    D = O.coupling(case["h"], case["N"], n)
+    ref = O.scatter_fft(n, k, D, x)
+    e64, em = rel(y, ref), rel(ym, ref)
+    worst = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+    say(f"   err64={e64:.2e} (largest element error / largest element {worst:.2e}) err_mixed={em:.2e}")
+    assert e64 <= 1e-14 and worst <= 1e-14
+    assert em <= 1e-6
+
+
 def test_solve_n100_padded_to_256_sampled_true_residual():
     # n = 100 has no plan of length 200: it is padded to L = 256 (zeros
     # between 100 and 128 on every axis); complex128 and mixed to 1e-8, 32

@@ -236,6 +236,33 @@ def test_section3_route_equals_dense_sum(n, k, side):
         assert _rel(y_fft, y_dense) <= 1e-13
 
 
+@pytest.mark.parametrize("n,k,side", [(1, 1.0, 1.0), (2, 3.0, 1.0), (3, 5.0, 0.7), (5, 2.0, 1.0), (8, 9.0, 2.0)])
+def test_same_method_baseline_equals_dense_sum(n, k, side):
+    # the (2n)^3 cyclic convolution of the CPU baseline (eq. 3.3.8) gives the
+    # dense sums of eq. 2.19: a table with g(0) kept, or with the negative
+    # offsets of the upper half taken as positive, fails
+    pts, h, N, v = _varied_case(n, k, seed=10 + n, side=side)
+    D = O.coupling(h, N, n, side)
+    y_dense = O.scatter_dense(pts, k, D, v)
+    y = O.scatter_fft(n, k, D, v, side=side, workers=2)
+    if n == 1:
+        assert np.all(y == 0) and np.all(y_dense == 0)
+    else:
+        assert _rel(y, y_dense) <= 1e-13
+
+
+def test_same_method_baseline_solve_matches_lu():
+    # COCG with the convolution product on the symmetrised system reaches the
+    # LU solution of eq. 2.19 (varied h, so the symmetrisation matters)
+    n, k = 6, 5.0
+    pts, h, N, u0 = _varied_case(n, k, seed=61)
+    D = O.coupling(h, N, n)
+    u_lu = O.solve_direct(O.system_matrix(pts, k, D), u0)
+    u, hist = O.solve_symmetrized_fft(n, k, D, u0, tol=1e-12, workers=2)
+    assert hist[-1] < 1e-12 and len(hist) < 60
+    assert _rel(u, u_lu) <= 1e-10
+
+
 def test_row_sampler_equals_dense_rows():
     n, k = 6, 4.0
     pts, h, N, v = _varied_case(n, k, seed=2)
