@@ -648,6 +648,8 @@ struct MultiCache {
   }
 };
 constexpr size_t kMultiSetsMax = 32;
+// problems in one ori_group (and scalar blocks in MultiCache::gathered)
+constexpr int32_t kGroupMaxProblems = 64;
 
 // whether the members can run in one launch per kernel in precision prec:
 // lengths with multi-problem bodies, one right-hand side each, the tile
@@ -758,8 +760,10 @@ ori_status multi_set(MultiCache& mc, const Members& act, int prec, const MultiSe
 ori_status multi_sync_scalars(MultiCache& mc, const MultiSet& m) {
   ori_ctx c0 = m.members.front();
   const int32_t np = static_cast<int32_t>(m.members.size());
+  if (np > kGroupMaxProblems) return set_err(c0, ORI_ERR_INVALID_ARG, "%d problems in one group", np);
   if (!mc.gathered) {
-    if (hipHostMalloc(reinterpret_cast<void**>(&mc.gathered), 64 * sizeof(ScalarBlock), hipHostMallocDefault) !=
+    if (hipHostMalloc(reinterpret_cast<void**>(&mc.gathered), kGroupMaxProblems * sizeof(ScalarBlock),
+                      hipHostMallocDefault) !=
         hipSuccess) {
       mc.gathered = nullptr;
       return set_err(c0, ORI_ERR_OUT_OF_MEMORY, "hipHostMalloc of the gathered scalars failed");
@@ -1991,7 +1995,8 @@ ori_status ori_group_create(const ori_grid* grids, int32_t nprob, int32_t provis
   if (!out) return set_err(nullptr, ORI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!grids) return set_err(nullptr, ORI_ERR_INVALID_ARG, "grids is NULL");
-  if (nprob < 1 || nprob > 64) return set_err(nullptr, ORI_ERR_INVALID_ARG, "nprob = %d out of [1, 64]", nprob);
+  if (nprob < 1 || nprob > kGroupMaxProblems)
+    return set_err(nullptr, ORI_ERR_INVALID_ARG, "nprob = %d out of [1, %d]", nprob, kGroupMaxProblems);
   ori_group g = new ori_group_s();
   g->multi.graphs = g->graphs;
   g->caller = static_cast<hipStream_t>(stream);
