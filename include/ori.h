@@ -282,7 +282,9 @@ ori_status ori_group_solve(ori_group g, const ori_solve_opts* opts, void* const*
  * per iteration of the set, since the group was created. */
 ori_status ori_group_multi_iterations(ori_group g, int64_t* iterations);
 
-/* Release the group and its problems' workspaces (NULL is ignored). */
+/* Release the group and its problems' workspaces (NULL is ignored).  Waits
+ * for the group's streams; the workspaces and the streams go to the
+ * process-wide cache of ori_destroy. */
 void ori_group_destroy(ori_group g);
 
 /* ---- what the solution is used for (Section 2, Section 4) ---------------- */
@@ -400,8 +402,21 @@ ori_status ori_profile_kinds(ori_ctx ctx, const char* kinds);
 ori_status ori_profile_read(ori_ctx ctx, int32_t max, const char** names, double* avg_ms,
                             int64_t* launches, int32_t* count);
 
-/* Release every device allocation of ctx (NULL is ignored). */
+/* Release every device allocation of ctx (NULL is ignored).  Waits for the
+ * context's stream.  The workspace (one device block) and the pinned host
+ * mirrors (one pinned block) are kept in a process-wide cache, up to 4 GiB
+ * of each kind, and a later ori_create or ori_group_create on the same
+ * device that needs a block of exactly that size takes it instead of
+ * allocating (creating and destroying contexts in a loop then costs no
+ * hipMalloc/hipFree); larger blocks are freed at once.  A block taken from
+ * the cache holds what its last owner left: nothing in this library reads a
+ * workspace before writing it. */
 void ori_destroy(ori_ctx ctx);
+
+/* Free every block and stream the process-wide cache holds (ori_destroy,
+ * ori_group_destroy), on their devices.  Contexts and groups still alive
+ * are not touched.  Safe to call at any time from any thread. */
+void ori_release_cached_memory(void);
 
 /* Text of the last error on ctx, or of the last failed ori_create/ori_setup
  * in this thread when ctx is NULL.  Never NULL. */

@@ -26,7 +26,7 @@ __all__ = [
     "ORI_FP64", "ORI_MIXED", "ORI_OP_SYSTEM", "ORI_OP_SYMMETRIC", "ORI_OP_GREEN",
     "ORI_PROVISION_FP64", "ORI_PROVISION_MIXED", "LIB_PATH", "solve", "solve_many",
     "Group", "ori_group_create", "ori_group_load", "ori_group_load_all", "ori_group_solve", "ori_group_destroy",
-    "ori_group_multi_iterations",
+    "ori_group_multi_iterations", "ori_release_cached_memory",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libori.so")
@@ -130,6 +130,7 @@ def lib():
             "ori_tune": (ctypes.c_int, [P, I32, ctypes.POINTER(Layout), ctypes.POINTER(D)]),
             "ori_check_guards": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64)]),
             "ori_destroy": (None, [P]),
+            "ori_release_cached_memory": (None, []),
             "ori_last_error": (ctypes.c_char_p, [P]),
         }
         for name, (res, args) in sig.items():
@@ -343,6 +344,12 @@ def ori_destroy(ctx):
 
 def ori_group_destroy(group):
     group.close()
+
+
+def ori_release_cached_memory():
+    """Free the device blocks, pinned blocks and streams that destroyed
+    contexts and groups left in the library's process-wide cache."""
+    lib().ori_release_cached_memory()
 
 
 def ori_charges(ctx, u, q=None):

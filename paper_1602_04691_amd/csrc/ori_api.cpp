@@ -18,6 +18,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <memory>
 #include <vector>
 
@@ -79,6 +80,139 @@ thread_local std::string g_last_error = "no error";
 
 constexpr int64_t kGuardBytes = 4096;
 constexpr unsigned char kGuardByte = 0xA5;
+
+// Blocks of destroyed contexts and groups, kept for the next ones of the
+// same size: device workspaces, pinned host mirrors and group streams.
+// Contexts made and destroyed in a loop (a group per batch of problems) then
+// skip hipMalloc, hipFree (which waits for the device), hipHostMalloc and
+// stream creation and destruction.  A block is reused only on its own device
+// and at its exact size.  At most kPoolBytes of memory per kind are kept;
+// larger blocks, and blocks beyond that, are freed at once.  A block comes
+// back only after its owner's work has finished (ori_destroy and
+// ori_group_destroy wait for their streams first), and a block taken again
+// holds whatever its last owner left: every workspace is initialised by the
+// code that uses it.  ori_release_cached_memory frees every kept block.
+constexpr size_t kPoolBytes = size_t{4} << 30;
+constexpr size_t kPoolStreams = 64;
+
+class BlockPool {
+ public:
+  enum Kind { DEVICE, HOST };
+  explicit BlockPool(Kind kind) : kind_(kind) {}
+  // a kept block of exactly `bytes` on `device`, or NULL
+  void* take(int device, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.find({device, bytes});
+    if (it == free_.end() || it->second.empty()) return nullptr;
+    void* p = it->second.back();
+    it->second.pop_back();
+    kept_ -= bytes;
+    return p;
+  }
+  // keeps p for a later take, or frees it
+  void give(int device, size_t bytes, void* p) {
+    if (!p) return;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (kept_ + bytes <= kPoolBytes) {
+        free_[{device, bytes}].push_back(p);
+        kept_ += bytes;
+        return;
+      }
+    }
+    free_block(device, p);
+  }
+  void release_all() {
+    std::map<std::pair<int, size_t>, std::vector<void*>> all;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      all.swap(free_);
+      kept_ = 0;
+    }
+    for (auto& kv : all)
+      for (void* p : kv.second) free_block(kv.first.first, p);
+  }
+
+ private:
+  void free_block(int device, void* p) {
+    if (kind_ == HOST) {
+      (void)hipHostFree(p);
+      return;
+    }
+    int cur = 0;
+    const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != device;
+    if (switch_dev) (void)hipSetDevice(device);
+    (void)hipFree(p);
+    if (switch_dev) (void)hipSetDevice(cur);
+  }
+  Kind kind_;
+  std::mutex mu_;
+  std::map<std::pair<int, size_t>, std::vector<void*>> free_;
+  size_t kept_ = 0;
+};
+
+// process-wide pools (never destroyed: blocks still kept at exit go with the
+// process)
+BlockPool& device_pool() {
+  static BlockPool* p = new BlockPool(BlockPool::DEVICE);
+  return *p;
+}
+BlockPool& host_pool() {
+  static BlockPool* p = new BlockPool(BlockPool::HOST);
+  return *p;
+}
+
+// device memory of `bytes` on the current device `device`: a kept block, or
+// hipMalloc
+hipError_t pool_malloc(int device, size_t bytes, void** p) {
+  *p = device_pool().take(device, bytes);
+  if (*p) return hipSuccess;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) *p = nullptr;
+  return e;
+}
+// pinned host memory of `bytes`: a kept block, or hipHostMalloc
+hipError_t pool_host_malloc(size_t bytes, void** p) {
+  *p = host_pool().take(-1, bytes);
+  if (*p) return hipSuccess;
+  const hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) *p = nullptr;
+  return e;
+}
+
+// Non-blocking streams for group members, kept per device.
+struct StreamPool {
+  std::mutex mu;
+  std::map<int, std::vector<hipStream_t>> free;
+};
+StreamPool& stream_pool() {
+  static StreamPool* p = new StreamPool();
+  return *p;
+}
+hipError_t pool_stream(int device, hipStream_t* s) {
+  {
+    std::lock_guard<std::mutex> lk(stream_pool().mu);
+    auto& v = stream_pool().free[device];
+    if (!v.empty()) {
+      *s = v.back();
+      v.pop_back();
+      return hipSuccess;
+    }
+  }
+  return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+// s has no work left (the caller waited for it)
+void pool_stream_give(int device, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(stream_pool().mu);
+    auto& v = stream_pool().free[device];
+    if (v.size() < kPoolStreams) {
+      v.push_back(s);
+      return;
+    }
+  }
+  (void)hipStreamDestroy(s);
+}
 
 // Layout knobs of the FFT passes (performance only)
 struct Knobs {
@@ -181,7 +315,12 @@ struct ori_ctx_s {
   ScalarBlock* sc_host = nullptr;  // pinned mirror
   double* outer_m = nullptr;       // [2 nrhs]: refinement multipliers, then inner tolerances^2
   double* outer_m_host = nullptr;  // pinned
-  std::vector<void*> allocs;
+  // every device workspace is carved from one block (device_pool), the two
+  // pinned mirrors from one pinned block (host_pool)
+  void* ws_block = nullptr;
+  size_t ws_bytes = 0;
+  void* pin_block = nullptr;
+  size_t pin_bytes = 0;
   // guard band after every workspace: kGuardBytes of kGuardByte, checked by
   // ori_check_guards and, with ORI_CHECK_GUARDS=1 in the environment at
   // create, after every kernel launch
@@ -615,7 +754,9 @@ using Members = std::vector<ori_ctx>;
 struct MultiSet {
   Members members;
   int prec = 0;
-  void* dev = nullptr;  // every table, one allocation
+  void* dev = nullptr;  // every table, one block (device_pool)
+  size_t dev_bytes = 0;
+  int device = 0;
   const MultiProblem* f1_first = nullptr;
   const MultiProblem* pass[MP_NPASS] = {};
   int64_t blocks[MP_NPASS] = {};
@@ -642,8 +783,7 @@ struct MultiCache {
       graphs[0].release();
       graphs[1].release();
     }
-    for (auto& m : sets)
-      if (m->dev) (void)hipFree(m->dev);
+    for (auto& m : sets) device_pool().give(m->device, m->dev_bytes, m->dev);
     sets.clear();
   }
 };
@@ -736,10 +876,12 @@ ori_status multi_set(MultiCache& mc, const Members& act, int prec, const MultiSe
   std::memcpy(tail, fmu.data(), M * sizeof(MultiFin));
   std::memcpy(tail + bf, frho.data(), M * sizeof(MultiFin));
   std::memcpy(tail + 2 * bf, up.data(), M * sizeof(MultiUpd));
-  ORI_HIP(c0, hipMalloc(&ms->dev, img.size()));
+  ms->device = c0->device;
+  ORI_HIP(c0, pool_malloc(ms->device, img.size(), &ms->dev));
+  ms->dev_bytes = img.size();
   const hipError_t e = hipMemcpy(ms->dev, img.data(), img.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    (void)hipFree(ms->dev);
+    device_pool().give(ms->device, ms->dev_bytes, ms->dev);
     return set_err(c0, ORI_ERR_DEVICE, "copy of the multi-problem tables failed: %s", hipGetErrorString(e));
   }
   unsigned char* d = static_cast<unsigned char*>(ms->dev);
@@ -762,14 +904,13 @@ ori_status multi_sync_scalars(MultiCache& mc, const MultiSet& m) {
   const int32_t np = static_cast<int32_t>(m.members.size());
   if (np > kGroupMaxProblems) return set_err(c0, ORI_ERR_INVALID_ARG, "%d problems in one group", np);
   if (!mc.gathered) {
-    if (hipHostMalloc(reinterpret_cast<void**>(&mc.gathered), kGroupMaxProblems * sizeof(ScalarBlock),
-                      hipHostMallocDefault) !=
+    if (pool_host_malloc(kGroupMaxProblems * sizeof(ScalarBlock), reinterpret_cast<void**>(&mc.gathered)) !=
         hipSuccess) {
       mc.gathered = nullptr;
       return set_err(c0, ORI_ERR_OUT_OF_MEMORY, "hipHostMalloc of the gathered scalars failed");
     }
     if (hipHostGetDevicePointer(reinterpret_cast<void**>(&mc.gathered_dev), mc.gathered, 0) != hipSuccess) {
-      (void)hipHostFree(mc.gathered);
+      host_pool().give(-1, kGroupMaxProblems * sizeof(ScalarBlock), mc.gathered);
       mc.gathered = nullptr;
       mc.gathered_dev = nullptr;
       return set_err(c0, ORI_ERR_DEVICE, "hipHostGetDevicePointer of the gathered scalars failed");
@@ -1485,8 +1626,9 @@ ori_status static_workspace(int dev, void** out) {
 // per member.  Group calls start after the work already queued on the
 // caller's stream (an event) and return after all of theirs is done.
 struct ori_group_s {
+  int device = 0;
   std::vector<ori_ctx> members;
-  std::vector<hipStream_t> streams;  // one per member, owned by the group
+  std::vector<hipStream_t> streams;  // one per member, owned by the group (stream_pool)
   hipStream_t caller = nullptr;
   hipEvent_t ready = nullptr;
   IterGraph graphs[2];  // per vector precision
@@ -1573,68 +1715,80 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
     set_err(c, ORI_ERR_DEVICE, "hipGetDevice failed (no GPU?)");
     return fail(ORI_ERR_DEVICE);
   }
-  auto alloc = [&](int64_t bytes, void** p) -> ori_status {
-    if (bytes <= 0) {
-      *p = nullptr;
-      return ORI_OK;
-    }
-    hipError_t e = hipMalloc(p, static_cast<size_t>(bytes + kGuardBytes));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      *p = nullptr;
-      return set_err(c, ORI_ERR_OUT_OF_MEMORY, "hipMalloc(%lld) failed: %s", (long long)bytes, hipGetErrorString(e));
-    }
-    c->allocs.push_back(*p);
-    unsigned char* guard = static_cast<unsigned char*>(*p) + bytes;
-    if (hipMemset(guard, kGuardByte, kGuardBytes) != hipSuccess)
-      return set_err(c, ORI_ERR_DEVICE, "hipMemset of a guard band failed");
-    c->guards.push_back(guard);
-    return ORI_OK;
-  };
-  ori_status st = ORI_OK;
-  void* v = nullptr;
   const bool mixed = provision & ORI_PROVISION_MIXED;
   const int64_t R = nrhs;
-#define ORI_ALLOC(bytes, dst, type)    \
-  do {                                 \
-    st = alloc((bytes), &v);           \
-    if (st != ORI_OK) return fail(st); \
-    dst = static_cast<type>(v);        \
-  } while (0)
-  ORI_ALLOC(lay.arena, c->arena, void*);
-  ORI_ALLOC(lay.vec_d, c->D, cxd*);
-  ORI_ALLOC(lay.vec_d, c->S, cxd*);
-  ORI_ALLOC(lay.vec_f, c->cN, double*);
-  ORI_ALLOC(lay.vec_d, c->t1, cxd*);
-  ORI_ALLOC(lay.vec_d, c->t2, cxd*);
-  ORI_ALLOC(R * lay.vec_d, c->b, cxd*);
-  ORI_ALLOC(R * lay.vec_d, c->u0, cxd*);
-  ORI_ALLOC(R * lay.vec_d, c->x, cxd*);
-  ORI_ALLOC(R * lay.vec_d, c->r, cxd*);
-  ORI_ALLOC(R * lay.vec_d, c->p, cxd*);
-  ORI_ALLOC(R * lay.vec_d, c->q, cxd*);
-  if (mixed) {
-    ORI_ALLOC(lay.vec_f, c->Sf, cxf*);
-    ORI_ALLOC(R * lay.vec_f, c->xf, cxf*);
-    ORI_ALLOC(R * lay.vec_f, c->rf, cxf*);
-    ORI_ALLOC(R * lay.vec_f, c->pf, cxf*);
-    ORI_ALLOC(R * lay.vec_f, c->qf, cxf*);
-    ORI_ALLOC(lay.khf, c->khf, cxf*);
+  // The workspaces, in order, carved from one block: each starts on a
+  // 256-byte boundary and is followed by its guard band.  carve(take) calls
+  // take(bytes, pointer) for every workspace; a first pass sums the sizes.
+  auto carve = [&](auto&& take) {
+    take(lay.arena, c->arena);
+    take(lay.vec_d, c->D);
+    take(lay.vec_d, c->S);
+    take(lay.vec_f, c->cN);
+    take(lay.vec_d, c->t1);
+    take(lay.vec_d, c->t2);
+    take(R * lay.vec_d, c->b);
+    take(R * lay.vec_d, c->u0);
+    take(R * lay.vec_d, c->x);
+    take(R * lay.vec_d, c->r);
+    take(R * lay.vec_d, c->p);
+    take(R * lay.vec_d, c->q);
+    if (mixed) {
+      take(lay.vec_f, c->Sf);
+      take(R * lay.vec_f, c->xf);
+      take(R * lay.vec_f, c->rf);
+      take(R * lay.vec_f, c->pf);
+      take(R * lay.vec_f, c->qf);
+      take(lay.khf, c->khf);
+    }
+    take(lay.kh, c->kh);
+    take(align_up(L * 16), c->twd);
+    take(align_up(L * 8), c->twf);
+    take(align_up(lay.npart * 4 * 8), c->partials);
+    take(align_up(R * (int64_t)sizeof(ScalarBlock)), c->sc);
+    take(align_up(2 * R * 8), c->outer_m);
+  };
+  int64_t total = 0;
+  carve([&](int64_t bytes, auto&) {
+    if (bytes > 0) total = align_up(total + bytes + kGuardBytes);
+  });
+  {
+    const hipError_t e = pool_malloc(c->device, static_cast<size_t>(total), &c->ws_block);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_err(c, ORI_ERR_OUT_OF_MEMORY, "hipMalloc(%lld) failed: %s", (long long)total, hipGetErrorString(e));
+      return fail(ORI_ERR_OUT_OF_MEMORY);
+    }
+    c->ws_bytes = static_cast<size_t>(total);
   }
-  ORI_ALLOC(lay.kh, c->kh, cxd*);
-  ORI_ALLOC(align_up(L * 16), c->twd, cxd*);
-  ORI_ALLOC(align_up(L * 8), c->twf, cxf*);
-  ORI_ALLOC(align_up(lay.npart * 4 * 8), c->partials, double*);
-  ORI_ALLOC(align_up(R * (int64_t)sizeof(ScalarBlock)), c->sc, ScalarBlock*);
-  ORI_ALLOC(align_up(2 * R * 8), c->outer_m, double*);
-#undef ORI_ALLOC
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->sc_host), R * sizeof(ScalarBlock), hipHostMallocDefault) !=
-          hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->outer_m_host), 2 * R * sizeof(double), hipHostMallocDefault) !=
-          hipSuccess) {
+  int64_t at = 0;
+  unsigned char* base = static_cast<unsigned char*>(c->ws_block);
+  carve([&](int64_t bytes, auto& dst) {
+    using Ptr = std::remove_reference_t<decltype(dst)>;
+    if (bytes <= 0) {
+      dst = nullptr;
+      return;
+    }
+    dst = static_cast<Ptr>(static_cast<void*>(base + at));
+    c->guards.push_back(base + at + bytes);
+    at = align_up(at + bytes + kGuardBytes);
+  });
+  // the guard bands, on the context's stream (ori_check_guards waits for it)
+  for (unsigned char* gb : c->guards)
+    if (hipMemsetAsync(gb, kGuardByte, kGuardBytes, c->stream) != hipSuccess) {
+      set_err(c, ORI_ERR_DEVICE, "hipMemsetAsync of a guard band failed");
+      return fail(ORI_ERR_DEVICE);
+    }
+  // the pinned mirrors of sc and outer_m, one block
+  const size_t sc_bytes = static_cast<size_t>(align_up(R * (int64_t)sizeof(ScalarBlock)));
+  if (pool_host_malloc(sc_bytes + 2 * R * sizeof(double), &c->pin_block) != hipSuccess) {
+    (void)hipGetLastError();
     set_err(c, ORI_ERR_OUT_OF_MEMORY, "hipHostMalloc of the scalar mirrors failed");
     return fail(ORI_ERR_OUT_OF_MEMORY);
   }
+  c->pin_bytes = sc_bytes + 2 * R * sizeof(double);
+  c->sc_host = static_cast<ScalarBlock*>(c->pin_block);
+  c->outer_m_host = reinterpret_cast<double*>(static_cast<unsigned char*>(c->pin_block) + sc_bytes);
   std::memset(c->sc_host, 0, R * sizeof(ScalarBlock));
   std::vector<cxd> twd;
   std::vector<cxf> twf;
@@ -2000,7 +2154,7 @@ ori_status ori_group_create(const ori_grid* grids, int32_t nprob, int32_t provis
   ori_group g = new ori_group_s();
   g->multi.graphs = g->graphs;
   g->caller = static_cast<hipStream_t>(stream);
-  if (hipEventCreateWithFlags(&g->ready, hipEventDisableTiming) != hipSuccess) {
+  if (hipGetDevice(&g->device) != hipSuccess || hipEventCreateWithFlags(&g->ready, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     g->ready = nullptr;
     ori_group_destroy(g);
@@ -2008,7 +2162,7 @@ ori_status ori_group_create(const ori_grid* grids, int32_t nprob, int32_t provis
   }
   for (int32_t i = 0; i < nprob; ++i) {
     hipStream_t sm = nullptr;
-    if (hipStreamCreateWithFlags(&sm, hipStreamNonBlocking) != hipSuccess) {
+    if (pool_stream(g->device, &sm) != hipSuccess) {
       (void)hipGetLastError();
       ori_group_destroy(g);
       return set_err(nullptr, ORI_ERR_DEVICE, "problem %d: hipStreamCreate failed", i);
@@ -2118,9 +2272,12 @@ void ori_group_destroy(ori_group g) {
   if (!g) return;
   for (ori_ctx c : g->members) (void)hipStreamSynchronize(c->stream);  // nothing of the group in flight
   g->multi.release();  // the graphs, then the tables their nodes point into
-  if (g->multi.gathered) (void)hipHostFree(g->multi.gathered);
+  if (g->multi.gathered) host_pool().give(-1, kGroupMaxProblems * sizeof(ScalarBlock), g->multi.gathered);
   for (ori_ctx c : g->members) ori_destroy(c);
-  for (hipStream_t sm : g->streams) (void)hipStreamDestroy(sm);
+  for (hipStream_t sm : g->streams) {
+    (void)hipStreamSynchronize(sm);
+    pool_stream_give(g->device, sm);
+  }
   if (g->ready) (void)hipEventDestroy(g->ready);
   delete g;
 }
@@ -2267,10 +2424,21 @@ void ori_destroy(ori_ctx c) {
   (void)hipStreamSynchronize(c->stream);  // all of the context's work is on its stream
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   for (auto& g : c->graphs) g.release();
-  for (void* p : c->allocs) (void)hipFree(p);
-  if (c->sc_host) (void)hipHostFree(c->sc_host);
-  if (c->outer_m_host) (void)hipHostFree(c->outer_m_host);
+  device_pool().give(c->device, c->ws_bytes, c->ws_block);
+  host_pool().give(-1, c->pin_bytes, c->pin_block);
   delete c;
+}
+
+void ori_release_cached_memory(void) {
+  device_pool().release_all();
+  host_pool().release_all();
+  std::map<int, std::vector<hipStream_t>> streams;
+  {
+    std::lock_guard<std::mutex> lk(stream_pool().mu);
+    streams.swap(stream_pool().free);
+  }
+  for (auto& kv : streams)
+    for (hipStream_t sm : kv.second) (void)hipStreamDestroy(sm);
 }
 
 const char* ori_last_error(ori_ctx c) { return c ? c->err.c_str() : g_last_error.c_str(); }
