@@ -334,6 +334,16 @@ __global__ void __launch_bounds__(kFinThreads)
   finalize_body(m.partials, m.nblk, m.sc, blockIdx.x - m.first_block, mode, eps, 0.0, 0, nullptr);
 }
 
+// Every guard band of a workspace block in one launch: workgroup i fills
+// band i with 16-byte stores (kGuardBandBytes / 16 = 256 threads).
+static_assert(kGuardBandBytes == 256 * 16, "one 16-byte store per thread and band");
+__global__ void __launch_bounds__(256) k_fill_guards(GuardBands g) {
+  const uint32_t b = g.v & 0xFFu;
+  const uint32_t w = b | (b << 8) | (b << 16) | (b << 24);
+  uint4* band = reinterpret_cast<uint4*>(static_cast<unsigned char*>(g.base) + g.off[blockIdx.x]);
+  band[threadIdx.x] = make_uint4(w, w, w, w);
+}
+
 // The scalar blocks of several problems (one right-hand side each, the sc
 // of each MultiFin entry) copied into out[0..np), host memory the device
 // writes, so that one wait brings every problem's scalars to the host.
@@ -506,6 +516,14 @@ hipError_t launch_multi_finalize(const MultiFin* tab, int32_t np, int64_t blocks
   if (np < 1 || blocks < 1) return hipErrorInvalidValue;
   return launch_kernel(k_multi_finalize, dim3(static_cast<unsigned>(blocks)), dim3(kFinThreads), st, tab, np, mode,
                        eps);
+}
+
+hipError_t launch_fill_guards(const GuardBands& g, hipStream_t st) {
+  if (g.count < 0 || g.count > kMaxGuardBands || !g.base) return hipErrorInvalidValue;
+  for (int i = 0; i < g.count; ++i)
+    if (g.off[i] < 0 || g.off[i] % 16 != 0) return hipErrorInvalidValue;
+  if (g.count == 0) return hipSuccess;
+  return launch_kernel(k_fill_guards, dim3(static_cast<unsigned>(g.count)), dim3(256), st, g);
 }
 
 hipError_t launch_gather_scalars(const MultiFin* tab, int32_t np, ScalarBlock* out, hipStream_t st) {

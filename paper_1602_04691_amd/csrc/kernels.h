@@ -354,6 +354,18 @@ hipError_t launch_gradient(const double* c, const void* u, const void* q, double
                            hipStream_t st);
 // twd[m] = exp(-2 pi i m / L) (complex128) and twf[m] the same in complex64, m < L
 hipError_t launch_twiddles(int64_t L, void* twd, void* twf, hipStream_t st);
+
+// Guard bands of a workspace block: count bands of kGuardBandBytes at
+// base + off[i] (each 16-byte aligned) filled with the byte v.
+constexpr int kMaxGuardBands = 32;
+constexpr int kGuardBandBytes = 4096;
+struct GuardBands {
+  void* base;
+  int32_t count;
+  uint32_t v;
+  int64_t off[kMaxGuardBands];
+};
+hipError_t launch_fill_guards(const GuardBands& g, hipStream_t st);
 // lam = f - s * x
 hipError_t launch_sub_mul(const void* f, const void* s, const void* x, void* lam, int64_t P, hipStream_t st);
 

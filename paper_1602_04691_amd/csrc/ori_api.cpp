@@ -78,7 +78,7 @@ const char* const kKindNames[K_NKIND] = {"f1", "f2", "zpass", "i2", "i1", "updat
 
 thread_local std::string g_last_error = "no error";
 
-constexpr int64_t kGuardBytes = 4096;
+constexpr int64_t kGuardBytes = kGuardBandBytes;
 constexpr unsigned char kGuardByte = 0xA5;
 
 // Blocks of destroyed contexts and groups, kept for the next ones of the
@@ -426,9 +426,10 @@ Layout layout_for(int64_t n, int64_t nrhs, int provision) {
   l.npart = nrhs * std::max({red_blocks(P), update_blocks(P, PREC_F32), n * n});
   const int64_t shared = 2 * l.vec_d + l.vec_f /* cN */ + (mixed ? l.vec_f : 0) /* Sf */ + 2 * l.vec_d /* t1, t2 */;
   const int64_t batch = nrhs * (6 * l.vec_d + (mixed ? 4 * l.vec_f : 0));
-  l.total = l.arena + shared + batch + l.kh + l.khf + align_up(L * 16) + align_up(L * 8) +
-            align_up(l.npart * 4 * 8) + align_up(nrhs * (int64_t)sizeof(ScalarBlock)) + align_up(2 * nrhs * 8) +
-            (mixed ? 24 : 18) * kGuardBytes;  // one guard band per allocation
+  // the context's device block (ori_create: every workspace followed by its
+  // guard band; the twiddle tables are shared per length)
+  l.total = l.arena + shared + batch + l.kh + l.khf + align_up(l.npart * 4 * 8) +
+            align_up(nrhs * (int64_t)sizeof(ScalarBlock)) + align_up(2 * nrhs * 8) + (mixed ? 22 : 16) * kGuardBytes;
   return l;
 }
 
@@ -683,6 +684,36 @@ void fill_twiddles(int64_t L, std::vector<cxd>& d, std::vector<cxf>& f) {
     d[m] = cxd{static_cast<double>(cs), static_cast<double>(-sn)};
     f[m] = cxf{static_cast<float>(cs), static_cast<float>(-sn)};
   }
+}
+
+// The twiddle tables of padded length L on a device (fill_twiddles), made
+// on first use and shared, read only, by every context of that length on
+// that device for the rest of the process.
+ori_status shared_twiddles(int device, int64_t L, cxd** twd, cxf** twf) {
+  static std::mutex mu;
+  static auto* tabs = new std::map<std::pair<int, int64_t>, std::pair<cxd*, cxf*>>();
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = tabs->find({device, L});
+  if (it == tabs->end()) {
+    std::vector<cxd> d;
+    std::vector<cxf> f;
+    fill_twiddles(L, d, f);
+    void* pd = nullptr;
+    void* pf = nullptr;
+    if (hipMalloc(&pd, L * sizeof(cxd)) != hipSuccess || hipMalloc(&pf, L * sizeof(cxf)) != hipSuccess ||
+        hipMemcpy(pd, d.data(), L * sizeof(cxd), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pf, f.data(), L * sizeof(cxf), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      if (pd) (void)hipFree(pd);
+      if (pf) (void)hipFree(pf);
+      g_last_error = "twiddle tables: allocation or copy failed";
+      return ORI_ERR_DEVICE;
+    }
+    it = tabs->emplace(std::make_pair(device, L), std::make_pair(static_cast<cxd*>(pd), static_cast<cxf*>(pf))).first;
+  }
+  *twd = it->second.first;
+  *twf = it->second.second;
+  return ORI_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1742,8 +1773,6 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
       take(lay.khf, c->khf);
     }
     take(lay.kh, c->kh);
-    take(align_up(L * 16), c->twd);
-    take(align_up(L * 8), c->twf);
     take(align_up(lay.npart * 4 * 8), c->partials);
     take(align_up(R * (int64_t)sizeof(ScalarBlock)), c->sc);
     take(align_up(2 * R * 8), c->outer_m);
@@ -1752,6 +1781,11 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
   carve([&](int64_t bytes, auto&) {
     if (bytes > 0) total = align_up(total + bytes + kGuardBytes);
   });
+  if (total != lay.total) {  // layout_for and the list above describe the same block
+    set_err(c, ORI_ERR_DEVICE, "internal: workspace of %lld bytes, layout says %lld", (long long)total,
+            (long long)lay.total);
+    return fail(ORI_ERR_DEVICE);
+  }
   {
     const hipError_t e = pool_malloc(c->device, static_cast<size_t>(total), &c->ws_block);
     if (e != hipSuccess) {
@@ -1773,12 +1807,19 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
     c->guards.push_back(base + at + bytes);
     at = align_up(at + bytes + kGuardBytes);
   });
-  // the guard bands, on the context's stream (ori_check_guards waits for it)
-  for (unsigned char* gb : c->guards)
-    if (hipMemsetAsync(gb, kGuardByte, kGuardBytes, c->stream) != hipSuccess) {
-      set_err(c, ORI_ERR_DEVICE, "hipMemsetAsync of a guard band failed");
+  // the guard bands, one launch on the context's stream (ori_check_guards
+  // waits for it)
+  {
+    GuardBands gb{};
+    gb.base = c->ws_block;
+    gb.count = static_cast<int32_t>(c->guards.size());
+    gb.v = kGuardByte;
+    for (size_t i = 0; i < c->guards.size() && i < kMaxGuardBands; ++i) gb.off[i] = c->guards[i] - base;
+    if (c->guards.size() > kMaxGuardBands || launch_fill_guards(gb, c->stream) != hipSuccess) {
+      set_err(c, ORI_ERR_DEVICE, "setting the guard bands failed");
       return fail(ORI_ERR_DEVICE);
     }
+  }
   // the pinned mirrors of sc and outer_m, one block
   const size_t sc_bytes = static_cast<size_t>(align_up(R * (int64_t)sizeof(ScalarBlock)));
   if (pool_host_malloc(sc_bytes + 2 * R * sizeof(double), &c->pin_block) != hipSuccess) {
@@ -1790,13 +1831,15 @@ ori_status ori_create(const ori_grid* g, int32_t nrhs, int32_t provision, int64_
   c->sc_host = static_cast<ScalarBlock*>(c->pin_block);
   c->outer_m_host = reinterpret_cast<double*>(static_cast<unsigned char*>(c->pin_block) + sc_bytes);
   std::memset(c->sc_host, 0, R * sizeof(ScalarBlock));
-  std::vector<cxd> twd;
-  std::vector<cxf> twf;
-  fill_twiddles(L, twd, twf);
-  if (hipMemcpy(c->twd, twd.data(), L * sizeof(cxd), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->twf, twf.data(), L * sizeof(cxf), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->sc, c->sc_host, R * sizeof(ScalarBlock), hipMemcpyHostToDevice) != hipSuccess) {
-    set_err(c, ORI_ERR_DEVICE, "initial copies failed");
+  {
+    const ori_status ts = shared_twiddles(c->device, L, &c->twd, &c->twf);
+    if (ts != ORI_OK) {
+      set_err(c, ts, "%s", g_last_error.c_str());
+      return fail(ts);
+    }
+  }
+  if (hipMemsetAsync(c->sc, 0, R * sizeof(ScalarBlock), c->stream) != hipSuccess) {
+    set_err(c, ORI_ERR_DEVICE, "clearing the scalar blocks failed");
     return fail(ORI_ERR_DEVICE);
   }
   *out = c;

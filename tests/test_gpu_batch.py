@@ -278,3 +278,31 @@ def test_group_of_sixteen_lengths_one_launch_per_kernel():
             assert torch.equal(us[j], u1), n
             assert infos[j]["iterations"] == i1["iterations"]
             assert infos[j]["rel_res_true"] <= 2e-10
+
+
+def test_cached_blocks_give_the_same_results():
+    # a context made from the blocks a destroyed one left (same n) solves
+    # bitwise as that one did, and so does one made from fresh allocations
+    # after ori_release_cached_memory; the same for a group made twice
+    n, k = 12, 3.0
+    say("[cache] n=12 context x3, group of (6, 12) x2")
+    case = workloads.make_case(n, k, seed=31)
+    outs = []
+    for release in (False, False, True):
+        if release:
+            ori.ori_release_cached_memory()
+        u, info = ori.solve(n, k, gpu(case["h"]), gpu(case["N"]), gpu(case["u0"]), tol=1e-11)
+        outs.append((u, info["iterations"]))
+    assert all(torch.equal(outs[0][0], u) and outs[0][1] == it for u, it in outs[1:])
+    ns = (6, 12)
+    cases = [workloads.make_case(m, k, seed=40 + m) for m in ns]
+    res = []
+    for _ in range(2):
+        with ori.ori_group_create(ns) as g:
+            ori.ori_group_load_all(g, [k, k], [gpu(c["h"]) for c in cases], [gpu(c["N"]) for c in cases],
+                                   [gpu(c["u0"]) for c in cases])
+            us = [torch.empty(m ** 3, dtype=torch.complex128, device="cuda") for m in ns]
+            ori.ori_group_solve(g, us, tol=1e-10)
+        res.append(us)
+    ori.ori_release_cached_memory()
+    assert all(torch.equal(a, b) for a, b in zip(*res))
