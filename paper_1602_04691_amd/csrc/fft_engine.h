@@ -233,6 +233,31 @@ struct Dft<INV, 16, T> {
     Dft<INV, 8, T>::run_half(o);
     combine(v, e, o);
   }
+  // y_j = sum_m v_m w^m W^(jm) (W = exp(-+2 pi i/16)): splitting m by its
+  // top bit gives y_(2j') from A_m = v_m + w^8 v_(m+8), a twiddled 8-point
+  // DFT with base w, and y_(2j'+1) from B_m = v_m - w^8 v_(m+8), one with
+  // base w exp(-2 pi i/16) (Dft<8>::run_tw for both).  Twiddles w, w^2, w^4,
+  // w^8 with the forward sign (the inverse conjugates them): 8 + 24
+  // butterflies of 6 operations and 4 products by constants, against 15
+  // complex products (11 of them to derive the powers) and the plain
+  // butterfly.
+  __device__ __forceinline__ static void run_tw(cx<T>* v, cx<T> w1, cx<T> w2, cx<T> w4, cx<T> w8) {
+    using D8 = Dft<INV, 8, T>;
+    const cx<T> t8 = INV ? conj(w8) : w8;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) bfly_tw(v[m], v[m + 8], t8);
+    D8::run_tw(v, w1, w2, w4, D8::times_w8(w1));
+    // the powers 1, 2, 4 of w exp(-2 pi i/16), and its product with exp(-2 pi i/8)
+    D8::run_tw(v + 8, mul_w16<false, 1>(w1), D8::times_w8(w2), mul_w4<false>(w4), mul_w16<false, 3>(w1));
+    cx<T> y[16];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      y[2 * j] = v[j];
+      y[2 * j + 1] = v[8 + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = y[j];
+  }
 };
 
 template <bool INV, typename T>
@@ -469,6 +494,27 @@ struct Engine {
         }
         if constexpr (TWM != 1) w1w = Dft<INV, 8, T>::times_w8(w1);
         Dft<INV, 8, T>::run_tw(g.v[i], w1, w2, w4, w1w);
+        continue;
+      }
+      if constexpr (NSs > 1 && R == 16) {
+        const int k = b % NSs;
+        cx<T> w1, w2, w4, w8;
+        if constexpr (TWM == 1 || TWM == 2) {
+          // the powers 1, 2, 4, 8: positions 0, 1, 2, 3 of the powers of two
+          // (TWM 2) or 0, 1, 3, 7 of every power (TWM 1)
+          constexpr int o = stage_offset(s);
+          constexpr int q4 = TWM == 2 ? 2 : 3, q8 = TWM == 2 ? 3 : 7;
+          w1 = tw[o + k];
+          w2 = tw[o + NSs + k];
+          w4 = tw[o + q4 * NSs + k];
+          w8 = tw[o + q8 * NSs + k];
+        } else {
+          w1 = tw[k * TS];
+          w2 = tw[2 * k * TS];
+          w4 = tw[4 * k * TS];
+          w8 = tw[8 * k * TS];
+        }
+        Dft<INV, 16, T>::run_tw(g.v[i], w1, w2, w4, w8);
         continue;
       }
       if constexpr (NSs > 1) {
