@@ -11,6 +11,7 @@
 #include <hip/hip_runtime_api.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "ori.h"
@@ -132,9 +133,13 @@ int main(void) {
     ori_solve_info ginfo[2];
     st = ori_group_solve(grp, &o, ug, ginfo);
     CHECK(st == ORI_OK, "ori_group_solve: %s", ori_last_error(NULL));
+    /* one launch per kernel for both problems, except under ORI_CHECK_GUARDS=1
+       (guard checks after every launch: each problem's own launches) */
+    const char* guards_env = getenv("ORI_CHECK_GUARDS");
+    const int guards_on = guards_env && atoi(guards_env) != 0;
     int64_t multi_iters = 0;
-    CHECK(ori_group_multi_iterations(grp, &multi_iters) == ORI_OK && multi_iters > 0,
-          "no multi-problem iterations (%lld)", (long long)multi_iters);
+    CHECK(ori_group_multi_iterations(grp, &multi_iters) == ORI_OK && (multi_iters > 0) == !guards_on,
+          "multi-problem iterations: %lld", (long long)multi_iters);
     for (int j = 0; j < 2; ++j) {
       const size_t P3 = (size_t)(ns[j] * ns[j] * ns[j]);
       ori_ctx c1 = NULL;

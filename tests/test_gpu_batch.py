@@ -1,5 +1,6 @@
 """Batches of right-hand sides sharing one operator, through the C ABI."""
 
+import os
 import sys
 
 import numpy as np
@@ -13,6 +14,12 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 import paper_1602_04691_amd as ori  # noqa: E402
+
+
+# With ORI_CHECK_GUARDS=1 (the guard bands checked after every launch) the
+# library runs every problem's own launches instead of one launch per kernel
+# for a group's problems (ori_solve_opts.multi)
+MULTI_LAUNCHES = os.environ.get("ORI_CHECK_GUARDS", "0") in ("", "0")
 
 
 def say(*a):
@@ -244,7 +251,7 @@ def test_group_one_launch_per_kernel_bitwise(prec):
             ran = ori.ori_group_multi_iterations(g) - before
             say(f"   multi={multi} graph={graph}: {ran} multi-problem iterations, "
                 f"iterations {[i['iterations'] for i in infos]}")
-            assert (ran > 0) == multi
+            assert (ran > 0) == (multi and MULTI_LAUNCHES)
             runs[(multi, graph)] = (us, infos)
         ref_us, ref_infos = runs[(False, True)]
         for key, (us, infos) in runs.items():
@@ -272,7 +279,7 @@ def test_group_of_sixteen_lengths_one_launch_per_kernel():
         _, infos = ori.ori_group_solve(g, us, tol=1e-10)
         ran = ori.ori_group_multi_iterations(g)
         say(f"   {ran} multi-problem iterations, iterations {[i['iterations'] for i in infos]}")
-        assert ran > 0
+        assert (ran > 0) == MULTI_LAUNCHES
         for j, (n, c) in enumerate(zip(ns, cases)):
             u1, i1 = ori.solve(n, ks[j], gpu(c["h"]), gpu(c["N"]), gpu(c["u0"]), tol=1e-10)
             assert torch.equal(us[j], u1), n
