@@ -629,11 +629,15 @@ def ori_group_solve(group, us, raise_on_error=True, **opts):
 
 
 def solve_many(problems, **opts):
-    """Independent problems of any sizes solved together as one group (a
-    stream per problem; each later iteration block of all running problems
-    is one graph replay, the problems side by side on the GPU).  problems:
-    dicts with n, k, h, N, u0 (CUDA tensors) and optionally side.  Returns a list of (u, info) in
-    order; each result equals that problem's ori_solve bit for bit."""
+    """Independent problems of any sizes solved together as one group made
+    for this call: the COCG iterations of all running problems in one launch
+    per kernel where their padded lengths allow (ori_solve_opts.multi), each
+    block of iterations one graph replay.  The group's device blocks and
+    streams come from, and go back to, the library's process-wide cache, so
+    calls in a loop allocate nothing after the first.  problems: dicts with
+    n, k, h, N, u0 (CUDA tensors) and optionally side.  Returns a list of
+    (u, info) in order; each result equals that problem's ori_solve bit for
+    bit."""
     import torch
     grids = [{"n": int(p["n"]), "side": float(p.get("side", 1.0))} for p in problems]
     dev = problems[0]["h"].device
