@@ -405,18 +405,22 @@ def test_large_matvec_sampled_rows(name, nrows, bench_layout):
     assert rel(gotm, s) <= 2e-6
 
 
-@pytest.mark.parametrize("name,n_odd", [("n128_k5", None), (None, 100)])
+@pytest.mark.parametrize("name,n_odd", [("n128_k5", None), (None, 100), ("n256_k5", None)])
 def test_matvec_whole_vector_vs_cpu_convolution(name, n_odd):
     # every element of the GPU product against the same method on the host
     # (the (2n)^3 cyclic convolution of Section 3 with scipy.fft, itself
-    # pinned against the dense sums on the CPU): n = 128, and n = 100
-    # (padded to L = 256 on the GPU, to 200 here)
+    # pinned against the dense sums on the CPU): n = 128, n = 100 (padded to
+    # L = 256 on the GPU, to 200 here), and the n = 256 workload in the
+    # layout the benchmark times
     case = workloads.named_case(name) if name else workloads.make_case(n_odd, 5.0, seed=100)
     n, k = case["n"], case["k"]
     say(f"[whole vector] n={n}")
     P = n ** 3
     x = case["u0"] * (1.0 + 0.25 * np.cos(np.arange(P) * 0.001))
     with context(n, k, case["h"], case["N"], case["u0"]) as ctx:
+        if n == 256:
+            for prec, lay in BENCH_LAYOUT:
+                ori.ori_set_layout(ctx, prec, **lay)
         xg = gpu(x)
         yg = torch.empty_like(xg)
         ori.ori_matvec(ctx, xg, yg, ori.ORI_OP_SYSTEM, ori.ORI_FP64)
