@@ -302,7 +302,9 @@ def next_workload(a):
         desc = {"workload": "ori_red_uneven_n32_48_64_96_k5", "n": [32, 48, 64, 96], "k": k,
                 "precision": "mixed", "tol": a.tol, "seeds": [20, 21, 22, 23], "check_every": a.check_every,
                 "solver": "ori_group: the COCG iterations of all running problems in one launch per kernel, "
-                          "each block of check_every iterations one graph replay"}
+                          "each block of check_every iterations one graph replay",
+                "group": "made once and loaded with the problems in every step (like an FFT plan); "
+                         "solves_per_s_with_group_created_each_step makes and destroys it inside every step"}
     elif a.workload == "gradient":
         n, k = 128, 5.0
         case = workloads.make_case(n, k, seed=3)
