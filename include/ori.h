@@ -96,7 +96,10 @@ typedef struct {
                             an inner solve stops earlier when half of the residual
                             reduction still needed for tol is reached            */
   int32_t max_outer;     /* mixed: refinement cycles (0: 10)                         */
-  int32_t true_residual; /* 1: also compute ||u0 - A u|| / ||u0|| (one extra matvec) */
+  int32_t true_residual; /* 1: also compute ||u0 - A u|| / ||u0||: one extra
+                            matvec, except in mixed precision when u = w / S
+                            (no S_p small): there the last FP64 refinement
+                            residual r = S (u0 - A u) gives it as ||r / S||  */
   int32_t graph;         /* 1: run each block of check_every COCG iterations as one
                             replay of a HIP graph, built node by node from the
                             same kernels and arguments (no stream capture) and

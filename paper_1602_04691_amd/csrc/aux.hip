@@ -157,6 +157,23 @@ __global__ void __launch_bounds__(256) k_div(const cxd* __restrict__ w, const cx
   }
 }
 
+// u = w / S as k_div, and the partials {-, -, ||r / S||^2, -} per
+// right-hand side (red_grid): with r = b - (I + S G0 S) w and b = S u0,
+// r / S = u0 - u - G0 D u, the residual of eq. 2.19 for u = w / S
+__global__ void __launch_bounds__(kRedThreads)
+    k_div_res(const cxd* __restrict__ w, const cxd* __restrict__ r, const cxd* __restrict__ s, cxd* __restrict__ u,
+              int64_t P, double* __restrict__ partials) {
+  const int64_t off = static_cast<int64_t>(blockIdx.y) * P;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  ORI_RHS_LOOP(i) {
+    const cxd d = s[i];
+    const double inv = 1.0 / norm2(d);
+    u[off + i] = scale(w[off + i] * conj(d), inv);
+    acc[2] += norm2(scale(r[off + i] * conj(d), inv));
+  }
+  block_sum4(acc, partials + 4 * (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x));
+}
+
 // a1, right-hand sides: b = S u0 (one batch row per blockIdx.y)
 __global__ void __launch_bounds__(kRedThreads)
     k_rhs(const cxd* __restrict__ u0, const cxd* __restrict__ S, int64_t P, cxd* __restrict__ b,
@@ -481,6 +498,12 @@ hipError_t launch_div(const void* w, const void* s, void* u, int64_t P, int64_t 
   e = launch_kernel(k_div, dim3(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs)), dim3(256), st,
                      static_cast<const cxd*>(w), static_cast<const cxd*>(s), static_cast<cxd*>(u), P);
   return e;
+}
+
+hipError_t launch_div_res(const void* w, const void* r, const void* s, void* u, int64_t P, int64_t nrhs,
+                          double* partials, hipStream_t st) {
+  return launch_kernel(k_div_res, red_grid(P, nrhs), dim3(kRedThreads), st, static_cast<const cxd*>(w),
+                       static_cast<const cxd*>(r), static_cast<const cxd*>(s), static_cast<cxd*>(u), P, partials);
 }
 
 hipError_t launch_rhs(const void* u0, const void* S, int64_t P, int64_t nrhs, void* b, void* u0c, double* partials,

@@ -314,6 +314,10 @@ hipError_t launch_coefficients(const void* h, const double* N, double vol, int64
 hipError_t launch_finalize_coeff(const double* partials, int64_t nblk, ScalarBlock* sc, hipStream_t st);
 // u = w / S (w, u batch vectors; S shared, nonzero)
 hipError_t launch_div(const void* w, const void* s, void* u, int64_t P, int64_t nrhs, hipStream_t st);
+// u = w / S as launch_div, and partials {-, -, ||r / S||^2, -} per
+// right-hand side on red_blocks(P) workgroups each (FIN_NORM)
+hipError_t launch_div_res(const void* w, const void* r, const void* s, void* u, int64_t P, int64_t nrhs,
+                          double* partials, hipStream_t st);
 // a1 (right-hand sides): b = S u0, u0 copied; partials {||b||^2, ||u0||^2, bad, 0} per rhs
 hipError_t launch_rhs(const void* u0, const void* S, int64_t P, int64_t nrhs, void* b, void* u0c,
                       double* partials, hipStream_t st);

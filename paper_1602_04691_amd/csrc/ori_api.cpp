@@ -1450,15 +1450,26 @@ ori_status forward_solve_group(const Members& ms, const ori_solve_opts& o, const
   ORI_TRY(solve_sym_group(jobs, o, cache, mc));
   // every member's recovery and true residual launched, then one wait per
   // stream
+  // In mixed precision the refinement loop ends with r = b - (I + S G0 S) x
+  // in FP64 for the final x = w (computed after the last correction, or r = b
+  // for x = 0); with u = w / S that is r = S (u0 - u - G0 D u), so the
+  // residual of eq. 2.19 is r / S and needs no product.
+  std::vector<bool> from_r(ms.size(), false);
   for (size_t m = 0; m < ms.size(); ++m) {
     ori_ctx c = ms[m];
     Outcome* oc = &(*ocs)[m];
+    for (auto& i : oc->info) i.rel_res_true = -1.0;
+    from_r[m] = o.true_residual && o.precision == ORI_MIXED && c->recover_by_division;
+    if (from_r[m]) {
+      ORI_TRY(launch(c, K_ELEMWISE, PREC_F64, [&] {
+        return launch_div_res(c->x, c->r, c->S, u[m], c->P, c->nrhs, c->partials, c->stream);
+      }));
+      ORI_TRY(finalize(c, rblocks(c), FIN_NORM));
+      continue;
+    }
     int rec = 0;
     ORI_TRY(recover(c, c->x, u[m], &rec));
-    for (auto& i : oc->info) {
-      i.matvecs += rec;
-      i.rel_res_true = -1.0;
-    }
+    for (auto& i : oc->info) i.matvecs += rec;
     if (o.true_residual) ORI_TRY(true_residual_orig(c, u[m]));
   }
   if (!o.true_residual) return ORI_OK;
@@ -1467,7 +1478,7 @@ ori_status forward_solve_group(const Members& ms, const ori_solve_opts& o, const
     ori_ctx c = ms[m];
     const std::vector<double> rel = true_residual_orig_read(c);
     for (int64_t i = 0; i < c->nrhs; ++i) {
-      (*ocs)[m].info[i].matvecs++;
+      if (!from_r[m]) (*ocs)[m].info[i].matvecs++;
       (*ocs)[m].info[i].rel_res_true = rel[i];
     }
   }

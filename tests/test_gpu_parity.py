@@ -178,6 +178,14 @@ def test_solve_mixed_vs_lu(n, k):
         assert err <= 1e-6
         assert info["refinements"] >= 1 and info["matvecs_c64"] >= 1
         assert info["rel_res_recursive"] < 1e-8
+        # the reported true residual (from the last FP64 refinement residual,
+        # r / S, no product) is eq. 2.19's ||u0 - A u|| / ||u0|| of the
+        # returned u, as the dense oracle evaluates it
+        u = cpu(ug)
+        r_oracle = float(np.linalg.norm(case["u0"] - O.system_matrix(pts, k, D) @ u) / np.linalg.norm(case["u0"]))
+        say(f"   rel_res_true={info['rel_res_true']:.6e} oracle={r_oracle:.6e} matvecs={info['matvecs']}")
+        assert abs(info["rel_res_true"] - r_oracle) <= 1e-3 * r_oracle + 1e-15
+        assert info["matvecs"] == info["matvecs_c64"] + info["refinements"]
 
 
 def test_config0_solve_vs_lu_and_oracle_cocg():
