@@ -133,9 +133,11 @@ typedef struct {
  * no x0, inner_tol 1e-5, max_outer 10, true_residual 1, graph 1. */
 void ori_default_opts(ori_solve_opts* opts);
 
-/* Device bytes that ori_create would allocate for this grid, batch size and
- * provision mask (host-only arithmetic; no device call).  Returns
- * ORI_ERR_INVALID_ARG / ORI_ERR_UNSUPPORTED for a bad grid or batch. */
+/* Device bytes of the one workspace block that ori_create takes for this
+ * grid, batch size and provision mask (every workspace and its guard band;
+ * the twiddle tables of a padded length are shared by all contexts of it).
+ * Host-only arithmetic, no device call.  Returns ORI_ERR_INVALID_ARG /
+ * ORI_ERR_UNSUPPORTED for a bad grid or batch. */
 ori_status ori_workspace_bytes(const ori_grid* g, int32_t nrhs, int32_t provision, int64_t* bytes);
 
 /* Allocate a context and its workspaces for grid g and a batch of nrhs
