@@ -111,7 +111,7 @@ typedef struct {
   int32_t multi;         /* ori_group_solve: 1 runs the COCG iterations of the
                             problems still running in one launch per kernel when
                             every one of them has a padded length in 8..256
-                            other than 16 and the default layout, and neither
+                            and the default layout, and neither
                             per-kernel profiling nor the guard checks of
                             ORI_CHECK_GUARDS=1 are on (otherwise, and with 0,
                             each problem launches its own kernels).  The

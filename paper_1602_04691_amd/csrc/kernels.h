@@ -188,11 +188,11 @@ struct MultiProblem {
   } a;
 };
 enum MultiPass : int32_t { MP_F1 = 0, MP_F2 = 1, MP_Z = 2, MP_I2 = 3, MP_I1 = 4, MP_NPASS = 5 };
-// The padded lengths that have multi-problem bodies: 8 to 256 except 16,
-// whose single radix-16 stage holds 16 values per thread (a complex128 Z
-// body of 188 VGPRs would set the register budget of every problem's Z
-// workgroups in the launch).
-constexpr bool multi_length(int L) { return L >= 8 && L <= 256 && L != 16 && radix_plan(L).n > 0; }
+// The padded lengths that have multi-problem bodies: 8 to 256 (L = 16 is
+// planned as 4 x 4: a single radix-16 stage would hold 16 values per thread,
+// and its complex128 Z body of 188 VGPRs would set the register budget of
+// every problem's Z workgroups in the launch).
+constexpr bool multi_length(int L) { return L >= 8 && L <= 256 && radix_plan(L).n > 0; }
 // Their tile shape: wide strided tiles, no Z prefetch, the default Z plan,
 // and Z tiles narrow for complex64 and wide for complex128 (the library's
 // default layout up to L = 256).  A problem whose layout differs runs its

@@ -29,6 +29,12 @@ constexpr int L = 12;
 #include "multi_len.inc"
 }  // namespace ml12
 
+namespace ml16 {
+constexpr int L = 16;
+#include "pass_bodies.inc"
+#include "multi_len.inc"
+}  // namespace ml16
+
 namespace ml20 {
 constexpr int L = 20;
 #include "pass_bodies.inc"
@@ -96,7 +102,7 @@ constexpr int L = 256;
 }  // namespace ml256
 
 // every length with multi-problem bodies (multi_length in kernels.h)
-#define ORI_MULTI_LENGTHS(X) X(8) X(10) X(12) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(192) X(256)
+#define ORI_MULTI_LENGTHS(X) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(192) X(256)
 
 namespace {
 

@@ -21,8 +21,8 @@ struct RadixPlan {
 // input is skipped at compile time.  Radix 8 is the sweet spot on gfx950 in
 // complex128: 8 values (32 VGPRs) per butterfly leave room for the spectrum
 // and twiddles of the fused Z pass at 4 waves per SIMD, where radix 16 needs
-// over 200 VGPRs; radix 16 survives only where a single stage is the whole
-// transform (L = 16).
+// over 200 VGPRs.  L = 16 is 4 x 4 (four threads per pencil), so that its
+// pass bodies fit the register budget of the multi-problem launches.
 constexpr RadixPlan radix_plan(int L) {
   switch (L) {
     case 2: return {1, {2, 0, 0, 0}};
@@ -31,7 +31,7 @@ constexpr RadixPlan radix_plan(int L) {
     case 8: return {1, {8, 0, 0, 0}};
     case 10: return {2, {2, 5, 0, 0}};
     case 12: return {2, {4, 3, 0, 0}};
-    case 16: return {1, {16, 0, 0, 0}};
+    case 16: return {2, {4, 4, 0, 0}};
     case 20: return {2, {4, 5, 0, 0}};
     case 24: return {2, {8, 3, 0, 0}};
     case 32: return {2, {8, 4, 0, 0}};

@@ -264,11 +264,11 @@ def test_group_one_launch_per_kernel_bitwise(prec):
             assert i1["iterations"] == ref_infos[j]["iterations"]
 
 
-def test_group_of_sixteen_lengths_one_launch_per_kernel():
-    # sixteen problems over eleven padded lengths (8 to 128), some with n =
-    # L / 2 and some not, in one launch per kernel: each result bitwise its
-    # own ori_solve, and the iterations ran in common launches
-    ns = (4, 5, 6, 9, 10, 12, 13, 17, 20, 24, 25, 33, 40, 48, 49, 64)
+def test_group_of_many_lengths_one_launch_per_kernel():
+    # eighteen problems over thirteen padded lengths (8 to 128, 16 included),
+    # some with n = L / 2 and some not, in one launch per kernel: each result
+    # bitwise its own ori_solve, and the iterations ran in common launches
+    ns = (4, 5, 6, 7, 8, 9, 10, 12, 13, 17, 20, 24, 25, 33, 40, 48, 49, 64)
     say(f"[multi16] n in {ns}")
     cases = [workloads.make_case(n, 1.0 + 0.25 * (j % 5), seed=200 + j) for j, n in enumerate(ns)]
     ks = [1.0 + 0.25 * (j % 5) for j in range(len(ns))]
