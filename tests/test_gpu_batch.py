@@ -231,12 +231,12 @@ def test_group_load_all_reports_bad_input():
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_group_one_launch_per_kernel_bitwise(prec):
-    # problems of five padded lengths (n = 5, 9, 20, 33, 48: L = 10, 20, 40,
-    # 80, 96; n = 9 and 33 not L / 2) solved with the iterations of all
-    # running problems in one launch per kernel, with graph replay and
+    # problems of six padded lengths (n = 5, 8, 9, 20, 33, 48: L = 10, 16,
+    # 20, 40, 80, 96; n = 9 and 33 not L / 2) solved with the iterations of
+    # all running problems in one launch per kernel, with graph replay and
     # eagerly: bitwise the group's own per-problem launches and each
     # problem's ori_solve, and the multi-problem iterations did run
-    ns = (5, 9, 20, 33, 48)
+    ns = (5, 8, 9, 20, 33, 48)
     say(f"[multi] n in {ns}, precision {prec}")
     cases = [workloads.make_case(n, 2.0 + 0.5 * j, seed=90 + j) for j, n in enumerate(ns)]
     with ori.ori_group_create(ns) as g:
