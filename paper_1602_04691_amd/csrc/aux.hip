@@ -157,6 +157,16 @@ __global__ void __launch_bounds__(256) k_div(const cxd* __restrict__ w, const cx
   }
 }
 
+// q = (z + r) / S (one right-hand side; S nonzero), the division as in k_div
+__global__ void __launch_bounds__(256) k_add_div(const cxd* __restrict__ z, const cxd* __restrict__ r,
+                                                 const cxd* __restrict__ s, cxd* __restrict__ q, int64_t P) {
+  ORI_RHS_LOOP(i) {
+    const cxd d = s[i];
+    const double inv = 1.0 / norm2(d);
+    q[i] = scale((z[i] + r[i]) * conj(d), inv);
+  }
+}
+
 // u = w / S as k_div, and the partials {-, -, ||r / S||^2, -} per
 // right-hand side (red_grid): with r = b - (I + S G0 S) w and b = S u0,
 // r / S = u0 - u - G0 D u, the residual of eq. 2.19 for u = w / S
@@ -498,6 +508,11 @@ hipError_t launch_div(const void* w, const void* s, void* u, int64_t P, int64_t 
   e = launch_kernel(k_div, dim3(grid_for(P, 256, 8192), static_cast<unsigned>(nrhs)), dim3(256), st,
                      static_cast<const cxd*>(w), static_cast<const cxd*>(s), static_cast<cxd*>(u), P);
   return e;
+}
+
+hipError_t launch_add_div(const void* z, const void* r, const void* s, void* q, int64_t P, hipStream_t st) {
+  return launch_kernel(k_add_div, dim3(grid_for(P, 256, 8192), 1u), dim3(256), st, static_cast<const cxd*>(z),
+                       static_cast<const cxd*>(r), static_cast<const cxd*>(s), static_cast<cxd*>(q), P);
 }
 
 hipError_t launch_div_res(const void* w, const void* r, const void* s, void* u, int64_t P, int64_t nrhs,

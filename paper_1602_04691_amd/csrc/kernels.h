@@ -314,6 +314,8 @@ hipError_t launch_coefficients(const void* h, const double* N, double vol, int64
 hipError_t launch_finalize_coeff(const double* partials, int64_t nblk, ScalarBlock* sc, hipStream_t st);
 // u = w / S (w, u batch vectors; S shared, nonzero)
 hipError_t launch_div(const void* w, const void* s, void* u, int64_t P, int64_t nrhs, hipStream_t st);
+// q = (z + r) / S (one right-hand side; S nonzero)
+hipError_t launch_add_div(const void* z, const void* r, const void* s, void* q, int64_t P, hipStream_t st);
 // u = w / S as launch_div, and partials {-, -, ||r / S||^2, -} per
 // right-hand side on red_blocks(P) workgroups each (FIN_NORM)
 hipError_t launch_div_res(const void* w, const void* r, const void* s, void* u, int64_t P, int64_t nrhs,

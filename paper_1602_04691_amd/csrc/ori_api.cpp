@@ -1515,10 +1515,18 @@ ori_status adjoint_solve(ori_ctx c, const ori_solve_opts& o, const cxd* u, const
   ORI_TRY(sync_scalars(c));
   const std::vector<double> bb(1, c->sc_host[0].rr0);
   ORI_TRY(solve_sym(c, o, c->t2, bb, oc));
-  // q = G0 lam = t1 - G0 S z
-  ORI_TRY(matvec(c, PREC_F64, PREC_F64, plain_f1(c->x, c->S),
-                 epi(c->q, c->t1, 1.0, nullptr, 0.0, nullptr, -1.0, nullptr, 0), nullptr));
-  oc->info[0].matvecs++;
+  // q = G0 lam = t1 - G0 S z.  In mixed precision the refinement loop ends
+  // with r = t2 - (I + S G0 S) z in FP64, and t2 = S t1, so with no S_p
+  // small G0 S z = t1 - (z + r) / S and q = (z + r) / S (to rounding)
+  // without a product.
+  if (o.precision == ORI_MIXED && c->recover_by_division) {
+    ORI_TRY(launch(c, K_ELEMWISE, PREC_F64,
+                   [&] { return launch_add_div(c->x, c->r, c->S, c->q, P, c->stream); }));
+  } else {
+    ORI_TRY(matvec(c, PREC_F64, PREC_F64, plain_f1(c->x, c->S),
+                   epi(c->q, c->t1, 1.0, nullptr, 0.0, nullptr, -1.0, nullptr, 0), nullptr));
+    oc->info[0].matvecs++;
+  }
   if (g)
     ORI_TRY(launch(c, K_ELEMWISE, PREC_F64,
                    [&] { return launch_gradient(c->cN, u, c->q, -scale, g, P, c->stream); }));
