@@ -170,6 +170,8 @@ int main(void) {
   hipFree(u0);
   hipFree(u);
   hipFree(N);
+  /* the blocks and streams the destroyed contexts and group left behind */
+  ori_release_cached_memory();
   printf("OK %s n=2 closed form max_err=%.3e iterations=%d; group n=4,5 bitwise\n", ori_version(), err,
          info.iterations);
   return 0;
